@@ -1,0 +1,166 @@
+"""The oracle: a plain, slow, obviously correct FP64 CPU reference.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` import this package.  It shares no code with
+the GPU library and never imports it.
+
+Arithmetic lives in ``ls_oracle.c`` (FP64, one rounding per operation); this
+module marshals numpy arrays and runs the narrow-band driver of the paper's
+algorithm (Sec. 1.1, Steps 1-2): rebuild the band, then advance on it.
+
+Parity status of each function is stated in its docstring; the pins live in
+``tests/test_oracle_*.py``.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+_LIB_PATH = None
+
+
+def use_library(path=None):
+    """Load the C part from ``path`` (default: the built ``liblsoracle.so``).
+
+    Used by the mutation tests to swap in copies with a planted mistake.
+    Returns the path that was in use before.
+    """
+    global _LIB, _LIB_PATH
+    old = _LIB_PATH
+    _LIB, _LIB_PATH = None, path
+    return old
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = _LIB_PATH or _build.LIB
+        if path == _build.LIB and not os.path.exists(path):
+            _build.build()
+        lib = ctypes.CDLL(path)
+        i32, i64, dbl, vp = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+        lib.lso_tile_count.restype = i64
+        lib.lso_tile_count.argtypes = [i32] * 6
+        lib.lso_band_tiles.restype = i64
+        lib.lso_band_tiles.argtypes = [vp, i32, i32, i32, i32, i32, i32, dbl, i32, vp, i64]
+        lib.lso_upwind_steps.restype = i32
+        lib.lso_upwind_steps.argtypes = [vp, vp, i32, i32, i32, dbl, dbl, i32, i32, i32, vp, i64, i32]
+        _LIB = lib
+    return _LIB
+
+
+def _dims(a):
+    """Array shape (nz, ny, nx) -> (nx, ny, nz); x is the fastest axis."""
+    nz, ny, nx = a.shape
+    return int(nx), int(ny), int(nz)
+
+
+def tile_count(dims, tile):
+    n = _lib().lso_tile_count(*[int(v) for v in dims], *[int(v) for v in tile])
+    if n < 0:
+        raise ValueError("bad dims or tile shape")
+    return int(n)
+
+
+def dequant_f16s(h, scale):
+    """Scaled-FP16 storage to its FP32 value: fl32(h * s).
+
+    The product of an 11-bit and a 24-bit significand is exact in FP64, so
+    rounding it once to FP32 is the correctly rounded FP32 product.
+    """
+    h = np.asarray(h, dtype=np.float16)
+    s = np.float64(np.float32(scale))
+    return (h.astype(np.float64) * s).astype(np.float32)
+
+
+def band_tiles(phi, tile=(8, 8, 8), gamma=0.0, dilate=True):
+    """Ascending band tile ids (Eq. 6; dilated by one tile, Eq. 11, if asked).
+
+    ``phi`` is the stored field (float32 or float64, shape (nz, ny, nx)); it is
+    promoted exactly to FP64 together with ``gamma`` given in the same
+    precision, so the comparison result equals the one made in that precision.
+    """
+    phi = np.asarray(phi)
+    if phi.dtype not in (np.float32, np.float64):
+        raise TypeError("phi must be float32 or float64")
+    gamma = float(phi.dtype.type(gamma))
+    p64 = np.ascontiguousarray(phi, dtype=np.float64)
+    nx, ny, nz = _dims(p64)
+    cap = tile_count((nx, ny, nz), tile)
+    out = np.empty(max(cap, 1), dtype=np.int32)
+    n = _lib().lso_band_tiles(p64.ctypes.data, nx, ny, nz, *tile, gamma, int(bool(dilate)),
+                              out.ctypes.data, cap)
+    if n < 0:
+        raise RuntimeError(f"lso_band_tiles failed: {n}")
+    return out[:n].copy()
+
+
+def all_tiles(dims, tile=(8, 8, 8)):
+    """Every tile of the grid: the full-grid (no band) update set."""
+    return np.arange(tile_count(dims, tile), dtype=np.int32)
+
+
+def upwind_steps(phi, F, dx, dt, tiles, nsteps, tile=(8, 8, 8)):
+    """``nsteps`` Jacobi steps of Eq. 3-5 on the listed tiles, in FP64.
+
+    Returns a new float64 array; ``phi`` and ``F`` are promoted exactly.
+    Pinned by the plane, F = 0, expanding/shrinking sphere, reflection,
+    monotonicity and brute-force tests.
+    """
+    p = np.array(phi, dtype=np.float64, order="C", copy=True)
+    f = np.ascontiguousarray(F, dtype=np.float64)
+    if f.shape != p.shape:
+        raise ValueError("phi and F shapes differ")
+    t = np.ascontiguousarray(tiles, dtype=np.int32)
+    nx, ny, nz = _dims(p)
+    rc = _lib().lso_upwind_steps(p.ctypes.data, f.ctypes.data, nx, ny, nz, float(dx), float(dt),
+                                 *tile, t.ctypes.data if t.size else None, int(t.size), int(nsteps))
+    if rc != 0:
+        raise RuntimeError(f"lso_upwind_steps failed: {rc}")
+    return p
+
+
+def decide_precision(phi64, precision):
+    """The field on which the band decision is taken, in the kernel's precision.
+
+    Where floating point decides an integer (tile membership), both sides
+    decide in the same precision: the FP64 state is rounded to the storage
+    precision of the device path first ('f32' -> FP32, 'f64' -> as is).
+    """
+    if precision == "f64":
+        return phi64
+    if precision == "f32":
+        return phi64.astype(np.float32)
+    raise ValueError(precision)
+
+
+def run_band(phi0, F, dx, dt, gamma, nsteps, window=10, tile=(8, 8, 8), precision="f32",
+             dilate=True, record_tiles=False):
+    """The narrow-band driver (Steps 1-2 of the algorithm in Sec. 1.1), FP64.
+
+    Every ``window`` steps the band U is rebuilt from the current state
+    (decision in ``precision``), then the state is advanced on U.  Returns the
+    final FP64 field and, if asked, the tile list of every window.
+    """
+    phi = np.array(phi0, dtype=np.float64, copy=True)
+    lists = []
+    done = 0
+    while done < nsteps:
+        n = min(window, nsteps - done)
+        gam = np.float32(gamma) if precision == "f32" else np.float64(gamma)
+        tiles = band_tiles(decide_precision(phi, precision), tile, gam, dilate)
+        if record_tiles:
+            lists.append(tiles)
+        phi = upwind_steps(phi, F, dx, dt, tiles, n, tile)
+        done += n
+    return (phi, lists) if record_tiles else phi
+
+
+def run_full(phi0, F, dx, dt, nsteps, tile=(8, 8, 8)):
+    """Full-grid run (every tile updated every step), FP64."""
+    phi = np.asarray(phi0, dtype=np.float64)
+    nz, ny, nx = phi.shape
+    return upwind_steps(phi, F, dx, dt, all_tiles((nx, ny, nz), tile), nsteps, tile)
