@@ -42,6 +42,8 @@ def _lib():
             _build.build()
         lib = ctypes.CDLL(path)
         i32, i64, dbl, vp = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+        lib.lso_max_threads.restype = i32
+        lib.lso_max_threads.argtypes = []
         lib.lso_tile_count.restype = i64
         lib.lso_tile_count.argtypes = [i32] * 6
         lib.lso_band_tiles.restype = i64
@@ -50,6 +52,11 @@ def _lib():
         lib.lso_upwind_steps.argtypes = [vp, vp, i32, i32, i32, dbl, dbl, i32, i32, i32, vp, i64, i32]
         _LIB = lib
     return _LIB
+
+
+def max_threads():
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_lib().lso_max_threads())
 
 
 def _dims(a):

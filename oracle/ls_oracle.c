@@ -35,6 +35,7 @@
  *             outside the listed tiles keep their value.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -43,6 +44,9 @@
 #define LSO_ERR_ARG (-1)
 #define LSO_ERR_CAPACITY (-2)
 #define LSO_ERR_NOMEM (-3)
+
+/* Threads an OpenMP region of the oracle uses (for reporting only). */
+int lso_max_threads(void) { return omp_get_max_threads(); }
 
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

@@ -1,0 +1,78 @@
+"""Device buffers for one level-set grid, and thin wrappers over the C-ABI.
+
+``BandGrid`` owns (through torch's allocator) the band list, its device
+count, the workspace and the ping-pong scratch buffer of one grid; its
+methods only marshal arguments to the ``ls_*`` entry points.  All arithmetic
+runs in libls's HIP kernels.
+"""
+import torch
+
+from . import ls
+
+_STORAGE = {"f32": torch.float32, "f64": torch.float64, "f16s": torch.float16}
+
+
+class BandGrid:
+    def __init__(self, dims, tile=(8, 8, 8), precision="f32", device="cuda"):
+        if precision not in _STORAGE:
+            raise ValueError(f"precision must be one of {sorted(_STORAGE)}")
+        self.dims = tuple(int(v) for v in dims)
+        self.tile = tuple(int(v) for v in tile)
+        self.precision = precision
+        self.device = torch.device(device)
+        self.g = ls.grid(self.dims, self.tile)
+        self.capacity = ls.ls_grid_tiles(self.g)
+        self.ws_bytes = ls.ls_workspace_bytes(self.g)
+        self.tiles = torch.empty(self.capacity, dtype=torch.int32, device=self.device)
+        self.ntiles = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.ws = self.workspace[off:off + self.ws_bytes]
+        nx, ny, nz = self.dims
+        self.scratch = torch.empty((nz, ny, nx), dtype=_STORAGE[precision], device=self.device)
+
+    # -- band -----------------------------------------------------------------
+    def build(self, phi, gamma, dilate=True, scale=None, stream=None):
+        d = 1 if dilate else 0
+        if self.precision == "f32":
+            ls.ls_band_build_f32(phi, self.g, gamma, d, self.tiles, self.capacity, self.ntiles,
+                                 self.ws, self.ws_bytes, stream)
+        elif self.precision == "f64":
+            ls.ls_band_build_f64(phi, self.g, gamma, d, self.tiles, self.capacity, self.ntiles,
+                                 self.ws, self.ws_bytes, stream)
+        else:
+            ls.ls_band_build_f16s(phi, scale, self.g, gamma, d, self.tiles, self.capacity,
+                                  self.ntiles, self.ws, self.ws_bytes, stream)
+
+    def band_list(self):
+        """The current band list as a host tensor (synchronises)."""
+        n = int(self.ntiles.item())
+        return self.tiles[:n].cpu()
+
+    # -- steps ----------------------------------------------------------------
+    def step(self, phi, F, dx, dt, nsteps, scale=None, tiles=None, ntiles=None, stream=None):
+        t = self.tiles if tiles is None else tiles
+        n = self.ntiles if ntiles is None else ntiles
+        if self.precision == "f32":
+            ls.ls_upwind_step_f32(phi, F, self.g, dx, dt, t, n, nsteps, self.scratch, self.ws,
+                                  self.ws_bytes, stream)
+        elif self.precision == "f64":
+            ls.ls_upwind_step_f64(phi, F, self.g, dx, dt, t, n, nsteps, self.scratch, self.ws,
+                                  self.ws_bytes, stream)
+        else:
+            ls.ls_upwind_step_f16s(phi, scale, F, self.g, dx, dt, t, n, nsteps, self.scratch,
+                                   self.ws, self.ws_bytes, stream)
+
+    def run(self, phi, F, dx, dt, gamma, nsteps, window=10, scale=None, stream=None):
+        if self.precision == "f32":
+            ls.ls_band_run_f32(phi, F, self.g, dx, dt, gamma, nsteps, window, self.tiles,
+                               self.capacity, self.ntiles, self.scratch, self.ws, self.ws_bytes,
+                               stream)
+        elif self.precision == "f64":
+            ls.ls_band_run_f64(phi, F, self.g, dx, dt, gamma, nsteps, window, self.tiles,
+                               self.capacity, self.ntiles, self.scratch, self.ws, self.ws_bytes,
+                               stream)
+        else:
+            ls.ls_band_run_f16s(phi, scale, F, self.g, dx, dt, gamma, nsteps, window, self.tiles,
+                                self.capacity, self.ntiles, self.scratch, self.ws, self.ws_bytes,
+                                stream)

@@ -1,0 +1,137 @@
+// Internal helpers of libls: error state, grid geometry, workspace layout,
+// storage codecs and the ordered (ballot / mbcnt) compaction used by the band
+// build and by the step's work-item list.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdarg>
+#include <cstdio>
+
+#include "ls.h"
+
+namespace ls {
+
+// ---------------------------------------------------------------------------
+// error state
+
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define LS_HIP_CHECK(expr)                                                              \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            ::ls::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),      \
+                            __FILE__, __LINE__);                                        \
+            return LS_ERR_HIP;                                                          \
+        }                                                                               \
+    } while (0)
+
+#define LS_LAUNCH_CHECK(what)                                                           \
+    do {                                                                                \
+        hipError_t e_ = hipGetLastError();                                              \
+        if (e_ != hipSuccess) {                                                         \
+            ::ls::set_error("launch of %s failed: %s", what, hipGetErrorString(e_));    \
+            return LS_ERR_HIP;                                                          \
+        }                                                                               \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// geometry
+
+struct Geom {
+    int32_t nx, ny, nz;
+    int32_t tx, ty, tz;
+    int32_t ntx, nty, ntz;
+    int64_t ntiles;
+    int64_t npoints;
+};
+
+// Validates g and fills out; returns LS_OK or a status with the message set.
+int make_geom(const ls_grid *g, Geom *out);
+
+// Threads of every kernel block in this library.
+constexpr int kBlock = 256;
+// Tiles examined per block by the compaction kernels (16 rounds of kBlock).
+constexpr int kCompactRounds = 16;
+constexpr int kCompactChunk = kBlock * kCompactRounds;
+// int32 words of one work-item record of the band step.
+constexpr int kItemWords = 8;
+
+// Workspace layout (byte offsets), all regions 256-byte aligned.
+struct Workspace {
+    int64_t a_flags;     // uint8[ntiles]   tile holds a point with |phi| < gamma
+    int64_t u_map;       // uint8[ntiles]   tile is in the update set
+    int64_t blk_counts;  // int32[nblk + 1] per-block counts, then offsets
+    int64_t items;       // int32[8*ntiles] work-item records of the band step
+    int64_t counters;    // int32[64]       item count and spares
+    int64_t total;
+    int64_t nblk;        // compaction blocks for ntiles entries
+};
+Workspace workspace_layout(const Geom &g);
+
+// Checks the workspace argument against the layout for g.
+int check_workspace(const Geom &g, const void *ws, int64_t ws_bytes);
+
+inline int64_t cdiv64(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Device properties of the current device, cached per device.
+struct DeviceInfo {
+    int cus;
+};
+int device_info(DeviceInfo *out);
+
+// ---------------------------------------------------------------------------
+// storage codecs: stored type S <-> compute type C
+
+template <class S>
+struct Codec;
+
+template <>
+struct Codec<float> {
+    using C = float;
+    __device__ static inline float load(float v, float) { return v; }
+    __device__ static inline float store(float v, float) { return v; }
+};
+
+template <>
+struct Codec<double> {
+    using C = double;
+    __device__ static inline double load(double v, double) { return v; }
+    __device__ static inline double store(double v, double) { return v; }
+};
+
+// Scaled FP16: h = fp16(phi / s) with round to nearest even; phi = fl32(h * s).
+template <>
+struct Codec<uint16_t> {
+    using C = float;
+    __device__ static inline float load(uint16_t h, float s) {
+        _Float16 v = __builtin_bit_cast(_Float16, h);
+        return static_cast<float>(v) * s;
+    }
+    __device__ static inline uint16_t store(float v, float s) {
+        _Float16 h = static_cast<_Float16>(v / s);
+        return __builtin_bit_cast(uint16_t, h);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// wave-level helpers (wave64)
+
+__device__ inline int lane_prefix(uint64_t mask) {
+    // number of set bits of `mask` below this lane (v_mbcnt_lo / v_mbcnt_hi)
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+// ---------------------------------------------------------------------------
+// host launchers (defined in ls_band.hip)
+
+// Ordered compaction of the nonzero bytes of map[0..n) into out (ascending
+// indices) with the count in *count; blk is int32[cdiv(n, kCompactChunk) + 1].
+int compact_map(const uint8_t *map, int64_t n, int32_t *out, int32_t *count, int32_t *blk,
+                hipStream_t stream);
+
+}  // namespace ls

@@ -1,0 +1,14 @@
+// Kernel timing hooks (see ls_stats_enable in ls.h).
+#pragma once
+
+#include "ls_internal.h"
+
+namespace ls {
+
+bool stats_on();
+// Records the start event of a timed launch of `kind` on `stream`; *slot < 0
+// when the launch is not timed.
+int stats_before(int kind, hipStream_t stream, int64_t *slot);
+int stats_after(int kind, hipStream_t stream, int64_t slot);
+
+}  // namespace ls

@@ -1,0 +1,86 @@
+// Kernel timing with HIP events (measurement support).
+#include <mutex>
+#include <vector>
+
+#include "ls_stats.h"
+
+namespace ls {
+
+namespace {
+constexpr int kKinds = 2;
+constexpr int64_t kMaxPairs = 65536;
+
+struct Record {
+    std::vector<hipEvent_t> start, stop;
+    int64_t launches = 0;
+    int64_t used = 0;
+};
+
+std::mutex g_mu;
+bool g_on = false;
+Record g_rec[kKinds];
+}  // namespace
+
+bool stats_on() { return g_on; }
+
+int stats_before(int kind, hipStream_t stream, int64_t *slot) {
+    *slot = -1;
+    if (!g_on) return LS_OK;
+    std::lock_guard<std::mutex> lock(g_mu);
+    Record &r = g_rec[kind];
+    ++r.launches;
+    if (r.used >= kMaxPairs) return LS_OK;
+    if (r.used == static_cast<int64_t>(r.start.size())) {
+        hipEvent_t a, b;
+        LS_HIP_CHECK(hipEventCreate(&a));
+        LS_HIP_CHECK(hipEventCreate(&b));
+        r.start.push_back(a);
+        r.stop.push_back(b);
+    }
+    *slot = r.used++;
+    LS_HIP_CHECK(hipEventRecord(r.start[*slot], stream));
+    return LS_OK;
+}
+
+int stats_after(int kind, hipStream_t stream, int64_t slot) {
+    if (slot < 0) return LS_OK;
+    std::lock_guard<std::mutex> lock(g_mu);
+    LS_HIP_CHECK(hipEventRecord(g_rec[kind].stop[slot], stream));
+    return LS_OK;
+}
+
+}  // namespace ls
+
+extern "C" {
+
+int ls_stats_enable(int on) {
+    ls::clear_error();
+    std::lock_guard<std::mutex> lock(ls::g_mu);
+    ls::g_on = on != 0;
+    if (ls::g_on)
+        for (auto &r : ls::g_rec) r.launches = 0, r.used = 0;
+    return LS_OK;
+}
+
+int ls_stats_read(int which, int64_t *launches, int64_t *timed, double *total_ms) {
+    ls::clear_error();
+    if (which < 0 || which >= ls::kKinds || !launches || !timed || !total_ms) {
+        ls::set_error("stats read: bad kernel id or NULL output");
+        return LS_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> lock(ls::g_mu);
+    const ls::Record &r = ls::g_rec[which];
+    double sum = 0.0;
+    for (int64_t i = 0; i < r.used; ++i) {
+        LS_HIP_CHECK(hipEventSynchronize(r.stop[i]));
+        float ms = 0.f;
+        LS_HIP_CHECK(hipEventElapsedTime(&ms, r.start[i], r.stop[i]));
+        sum += ms;
+    }
+    *launches = r.launches;
+    *timed = r.used;
+    *total_ms = sum;
+    return LS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,215 @@
+"""ctypes binding of libls (include/ls.h): argument marshalling only.
+
+Each ``ls_*`` function here has the name and argument order of the C entry
+point.  Pointer arguments accept a torch tensor (its ``data_ptr()``), a plain
+integer address or None; ``stream`` accepts a torch stream, a raw
+hipStream_t integer or None (the current torch stream).  A negative status
+raises :class:`LsError` carrying the status and ``ls_last_error()``.
+
+The library must have been built (``python -m paper_1612_04040_amd.build``);
+there is no fallback implementation.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libls.so")
+
+LS_OK = 0
+LS_ERR_ARG = -1
+LS_ERR_CAPACITY = -2
+LS_ERR_HIP = -3
+LS_ERR_UNSUPPORTED = -4
+
+
+class LsError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"libls status {status}: {message}")
+        self.status = status
+        self.message = message
+
+
+class ls_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("tx", ctypes.c_int32), ("ty", ctypes.c_int32), ("tz", ctypes.c_int32)]
+
+
+def grid(dims, tile=(8, 8, 8)):
+    """ls_grid for dims = (nx, ny, nz) and tile = (tx, ty, tz)."""
+    nx, ny, nz = (int(v) for v in dims)
+    tx, ty, tz = (int(v) for v in tile)
+    return ls_grid(nx, ny, nz, tx, ty, tz)
+
+
+_LIB = None
+
+_I32, _I64, _F32, _F64, _VP = (ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_double,
+                               ctypes.c_void_p)
+_G = ctypes.POINTER(ls_grid)
+
+_SIGNATURES = {
+    "ls_last_error": (ctypes.c_char_p, []),
+    "ls_version": (ctypes.c_char_p, []),
+    "ls_grid_tiles": (_I64, [_G]),
+    "ls_workspace_bytes": (_I64, [_G]),
+    "ls_band_build_f32": (_I32, [_VP, _G, _F32, _I32, _VP, _I64, _VP, _VP, _I64, _VP]),
+    "ls_band_build_f64": (_I32, [_VP, _G, _F64, _I32, _VP, _I64, _VP, _VP, _I64, _VP]),
+    "ls_band_build_f16s": (_I32, [_VP, _F32, _G, _F32, _I32, _VP, _I64, _VP, _VP, _I64, _VP]),
+    "ls_upwind_step_f32": (_I32, [_VP, _VP, _G, _F32, _F32, _VP, _VP, _I32, _VP, _VP, _I64, _VP]),
+    "ls_upwind_step_f64": (_I32, [_VP, _VP, _G, _F64, _F64, _VP, _VP, _I32, _VP, _VP, _I64, _VP]),
+    "ls_upwind_step_f16s": (_I32, [_VP, _F32, _VP, _G, _F32, _F32, _VP, _VP, _I32, _VP, _VP, _I64,
+                                   _VP]),
+    "ls_band_run_f32": (_I32, [_VP, _VP, _G, _F32, _F32, _F32, _I32, _I32, _VP, _I64, _VP, _VP,
+                               _VP, _I64, _VP]),
+    "ls_band_run_f64": (_I32, [_VP, _VP, _G, _F64, _F64, _F64, _I32, _I32, _VP, _I64, _VP, _VP,
+                               _VP, _I64, _VP]),
+    "ls_band_run_f16s": (_I32, [_VP, _F32, _VP, _G, _F32, _F32, _F32, _I32, _I32, _VP, _I64, _VP,
+                                _VP, _VP, _I64, _VP]),
+    "ls_stats_enable": (_I32, [_I32]),
+    "ls_stats_read": (_I32, [_I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
+                             ctypes.POINTER(_F64)]),
+}
+
+LS_KERNEL_UPWIND = 0
+LS_KERNEL_BAND_FLAG = 1
+
+
+def lib():
+    """The loaded libls.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1612_04040_amd.build` (no fallback exists)")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = handle
+    return _LIB
+
+
+def exported_symbols():
+    return sorted(_SIGNATURES)
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    raise TypeError(f"cannot pass {type(x).__name__} as a device pointer")
+
+
+def _stream(s):
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _check(status):
+    if status < 0:
+        raise LsError(int(status), lib().ls_last_error().decode())
+    return status
+
+
+def _g(g):
+    return ctypes.byref(g)
+
+
+def ls_last_error():
+    return lib().ls_last_error().decode()
+
+
+def ls_version():
+    return lib().ls_version().decode()
+
+
+def ls_grid_tiles(g):
+    return _check(lib().ls_grid_tiles(_g(g)))
+
+
+def ls_workspace_bytes(g):
+    return _check(lib().ls_workspace_bytes(_g(g)))
+
+
+def ls_band_build_f32(phi, g, gamma, dilate, tiles, capacity, ntiles_dev, workspace,
+                      workspace_bytes, stream=None):
+    return _check(lib().ls_band_build_f32(_ptr(phi), _g(g), gamma, dilate, _ptr(tiles), capacity,
+                                          _ptr(ntiles_dev), _ptr(workspace), workspace_bytes,
+                                          _stream(stream)))
+
+
+def ls_band_build_f64(phi, g, gamma, dilate, tiles, capacity, ntiles_dev, workspace,
+                      workspace_bytes, stream=None):
+    return _check(lib().ls_band_build_f64(_ptr(phi), _g(g), gamma, dilate, _ptr(tiles), capacity,
+                                          _ptr(ntiles_dev), _ptr(workspace), workspace_bytes,
+                                          _stream(stream)))
+
+
+def ls_band_build_f16s(phi_h, scale, g, gamma, dilate, tiles, capacity, ntiles_dev, workspace,
+                       workspace_bytes, stream=None):
+    return _check(lib().ls_band_build_f16s(_ptr(phi_h), scale, _g(g), gamma, dilate, _ptr(tiles),
+                                           capacity, _ptr(ntiles_dev), _ptr(workspace),
+                                           workspace_bytes, _stream(stream)))
+
+
+def ls_upwind_step_f32(phi, F, g, dx, dt, tiles, ntiles_dev, nsteps, scratch, workspace,
+                       workspace_bytes, stream=None):
+    return _check(lib().ls_upwind_step_f32(_ptr(phi), _ptr(F), _g(g), dx, dt, _ptr(tiles),
+                                           _ptr(ntiles_dev), nsteps, _ptr(scratch),
+                                           _ptr(workspace), workspace_bytes, _stream(stream)))
+
+
+def ls_upwind_step_f64(phi, F, g, dx, dt, tiles, ntiles_dev, nsteps, scratch, workspace,
+                       workspace_bytes, stream=None):
+    return _check(lib().ls_upwind_step_f64(_ptr(phi), _ptr(F), _g(g), dx, dt, _ptr(tiles),
+                                           _ptr(ntiles_dev), nsteps, _ptr(scratch),
+                                           _ptr(workspace), workspace_bytes, _stream(stream)))
+
+
+def ls_upwind_step_f16s(phi_h, scale, F, g, dx, dt, tiles, ntiles_dev, nsteps, scratch,
+                        workspace, workspace_bytes, stream=None):
+    return _check(lib().ls_upwind_step_f16s(_ptr(phi_h), scale, _ptr(F), _g(g), dx, dt,
+                                            _ptr(tiles), _ptr(ntiles_dev), nsteps, _ptr(scratch),
+                                            _ptr(workspace), workspace_bytes, _stream(stream)))
+
+
+def ls_band_run_f32(phi, F, g, dx, dt, gamma, nsteps, window, tiles, capacity, ntiles_dev,
+                    scratch, workspace, workspace_bytes, stream=None):
+    return _check(lib().ls_band_run_f32(_ptr(phi), _ptr(F), _g(g), dx, dt, gamma, nsteps, window,
+                                        _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(scratch),
+                                        _ptr(workspace), workspace_bytes, _stream(stream)))
+
+
+def ls_band_run_f64(phi, F, g, dx, dt, gamma, nsteps, window, tiles, capacity, ntiles_dev,
+                    scratch, workspace, workspace_bytes, stream=None):
+    return _check(lib().ls_band_run_f64(_ptr(phi), _ptr(F), _g(g), dx, dt, gamma, nsteps, window,
+                                        _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(scratch),
+                                        _ptr(workspace), workspace_bytes, _stream(stream)))
+
+
+def ls_band_run_f16s(phi_h, scale, F, g, dx, dt, gamma, nsteps, window, tiles, capacity,
+                     ntiles_dev, scratch, workspace, workspace_bytes, stream=None):
+    return _check(lib().ls_band_run_f16s(_ptr(phi_h), scale, _ptr(F), _g(g), dx, dt, gamma,
+                                         nsteps, window, _ptr(tiles), capacity, _ptr(ntiles_dev),
+                                         _ptr(scratch), _ptr(workspace), workspace_bytes,
+                                         _stream(stream)))
+
+
+def ls_stats_enable(on):
+    return _check(lib().ls_stats_enable(1 if on else 0))
+
+
+def ls_stats_read(which):
+    """(launches, timed launches, summed duration in ms) of kernel `which`."""
+    launches, timed, ms = _I64(), _I64(), _F64()
+    _check(lib().ls_stats_read(which, ctypes.byref(launches), ctypes.byref(timed),
+                               ctypes.byref(ms)))
+    return launches.value, timed.value, ms.value

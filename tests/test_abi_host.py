@@ -1,0 +1,152 @@
+"""Host-side checks of the C-ABI (no GPU needed).
+
+The library loads and exports every entry point include/ls.h declares, and
+every argument error is reported with a negative status and a message before
+anything is launched (so these calls never touch a device).
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1612_04040_amd import ls
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ls.h")
+
+FAKE = 0x10000  # never dereferenced: every call below fails its host checks first
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ls_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_bound_symbols():
+    assert declared_symbols() == ls.exported_symbols()
+
+
+def test_library_exports_every_declared_symbol():
+    handle = ctypes.CDLL(ls.LIB_PATH)
+    for name in declared_symbols():
+        assert hasattr(handle, name), name
+
+
+def test_version_and_tiles():
+    assert "gfx950" in ls.ls_version()
+    g = ls.grid((512, 512, 512))
+    assert ls.ls_grid_tiles(g) == 64 ** 3
+    assert ls.ls_grid_tiles(ls.grid((17, 9, 8), (8, 4, 3))) == 3 * 3 * 3
+    assert ls.ls_workspace_bytes(g) >= 6 * 64 ** 3
+
+
+def _status(fn, *args):
+    with pytest.raises(ls.LsError) as e:
+        fn(*args)
+    assert e.value.message
+    return e.value.status
+
+
+def test_grid_errors():
+    assert _status(ls.ls_grid_tiles, ls.grid((0, 4, 4))) == ls.LS_ERR_ARG
+    assert _status(ls.ls_grid_tiles, ls.grid((4, 4, 4), (8, 0, 8))) == ls.LS_ERR_ARG
+    assert _status(ls.ls_workspace_bytes, ls.grid((-1, 4, 4))) == ls.LS_ERR_ARG
+    assert "positive" in ls.ls_last_error()
+    assert ls.lib().ls_grid_tiles(None) == ls.LS_ERR_ARG
+    assert _status(ls.ls_grid_tiles, ls.grid((1 << 30, 1 << 30, 4), (1, 1, 1))) == \
+        ls.LS_ERR_UNSUPPORTED
+
+
+def _band_args(g0, **over):
+    g = g0
+    cap = ls.ls_grid_tiles(g)
+    a = dict(phi=FAKE, g=g, gamma=0.1, dilate=1, tiles=FAKE, capacity=cap, ntiles_dev=FAKE,
+             workspace=FAKE * 256, workspace_bytes=ls.ls_workspace_bytes(g), stream=0)
+    a.update(over)
+    return a
+
+
+@pytest.mark.parametrize("fn", ["f32", "f64"])
+def test_band_build_errors(fn):
+    build = getattr(ls, f"ls_band_build_{fn}")
+    g = ls.grid((64, 64, 64))
+    cases = [
+        (dict(phi=None), ls.LS_ERR_ARG),
+        (dict(tiles=None), ls.LS_ERR_ARG),
+        (dict(ntiles_dev=None), ls.LS_ERR_ARG),
+        (dict(dilate=2), ls.LS_ERR_ARG),
+        (dict(gamma=float("nan")), ls.LS_ERR_ARG),
+        (dict(capacity=10), ls.LS_ERR_CAPACITY),
+        (dict(workspace=None), ls.LS_ERR_ARG),
+        (dict(workspace_bytes=100), ls.LS_ERR_CAPACITY),
+        (dict(workspace=FAKE * 256 + 8), ls.LS_ERR_ARG),
+        (dict(g=ls.grid((64, 0, 64))), ls.LS_ERR_ARG),
+    ]
+    for over, status in cases:
+        a = _band_args(g, **over)
+        assert _status(build, *a.values()) == status, over
+
+
+def test_band_build_f16s_errors():
+    g = ls.grid((32, 32, 32))
+    a = _band_args(g)
+    args = list(a.values())
+    args.insert(1, 0.0)  # scale
+    assert _status(ls.ls_band_build_f16s, *args) == ls.LS_ERR_ARG
+    args[1] = float("inf")
+    assert _status(ls.ls_band_build_f16s, *args) == ls.LS_ERR_ARG
+
+
+def _step_args(g0, **over):
+    g = g0
+    a = dict(phi=FAKE, F=FAKE, g=g, dx=0.01, dt=0.005, tiles=FAKE, ntiles_dev=FAKE, nsteps=3,
+             scratch=FAKE * 2, workspace=FAKE * 256, workspace_bytes=ls.ls_workspace_bytes(g),
+             stream=0)
+    a.update(over)
+    return a
+
+
+@pytest.mark.parametrize("fn", ["f32", "f64"])
+def test_step_errors(fn):
+    step = getattr(ls, f"ls_upwind_step_{fn}")
+    g = ls.grid((64, 64, 64))
+    cases = [
+        (dict(phi=None), ls.LS_ERR_ARG),
+        (dict(F=None), ls.LS_ERR_ARG),
+        (dict(tiles=None), ls.LS_ERR_ARG),
+        (dict(scratch=None), ls.LS_ERR_ARG),
+        (dict(scratch=FAKE), ls.LS_ERR_ARG),  # aliases phi
+        (dict(nsteps=-1), ls.LS_ERR_ARG),
+        (dict(dx=0.0), ls.LS_ERR_ARG),
+        (dict(dx=float("inf")), ls.LS_ERR_ARG),
+        (dict(dt=-1e-3), ls.LS_ERR_ARG),
+        (dict(dt=float("nan")), ls.LS_ERR_ARG),
+        (dict(workspace_bytes=1), ls.LS_ERR_CAPACITY),
+        (dict(g=ls.grid((64, 64, 64), (512, 8, 8))), ls.LS_ERR_UNSUPPORTED),
+        (dict(g=ls.grid((64, 64, 64), (4, 64, 64))), ls.LS_ERR_UNSUPPORTED),
+    ]
+    for over, status in cases:
+        a = _step_args(g, **over)
+        if "g" in over:
+            a["workspace_bytes"] = ls.ls_workspace_bytes(over["g"])
+        assert _status(step, *a.values()) == status, over
+
+
+def test_step_zero_steps_launches_nothing():
+    g = ls.grid((64, 64, 64))
+    a = _step_args(g, nsteps=0)
+    assert ls.ls_upwind_step_f32(*a.values()) == ls.LS_OK
+
+
+def test_run_errors():
+    g = ls.grid((32, 32, 32))
+    cap = ls.ls_grid_tiles(g)
+    ws = ls.ls_workspace_bytes(g)
+    base = [FAKE, FAKE, g, 0.1, 0.05, 0.2, 10, 0, FAKE, cap, FAKE, FAKE * 2, FAKE * 256, ws, 0]
+    assert _status(ls.ls_band_run_f32, *base) == ls.LS_ERR_ARG  # window 0
+    bad = list(base)
+    bad[6] = -5
+    bad[7] = 10
+    assert _status(ls.ls_band_run_f32, *bad) == ls.LS_ERR_ARG  # nsteps < 0
