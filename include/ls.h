@@ -126,25 +126,80 @@ int ls_upwind_step_f16s(uint16_t *phi_h, float scale, const float *F, const ls_g
                         void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Incremental band rebuild: the list ls_band_build_* (dilate = 1) would
+ * return, computed by rescanning only the tiles of a previous band list
+ * prev_tiles[0 .. *prev_ntiles_dev) instead of the whole grid.
+ *
+ * Exact under this precondition: no tile outside prev_tiles holds a point with
+ * |phi| < gamma.  It holds when prev_tiles is the dilated band of an earlier
+ * build or rebuild of this grid and phi has changed only on prev_tiles since
+ * (the band step changes nothing else): a tile outside that band had no point
+ * in the tube then (the band contains the tube's tiles) and has the same
+ * values now.  prev_tiles / prev_ntiles_dev must not alias tiles /
+ * ntiles_dev.  Cost O(|prev band|) instead of O(nx*ny*nz).
+ * ------------------------------------------------------------------------- */
+int ls_band_rebuild_f32(const float *phi, const ls_grid *g, float gamma,
+                        const int32_t *prev_tiles, const int32_t *prev_ntiles_dev, int32_t *tiles,
+                        int64_t capacity, int32_t *ntiles_dev, void *workspace,
+                        int64_t workspace_bytes, void *stream);
+int ls_band_rebuild_f64(const double *phi, const ls_grid *g, double gamma,
+                        const int32_t *prev_tiles, const int32_t *prev_ntiles_dev, int32_t *tiles,
+                        int64_t capacity, int32_t *ntiles_dev, void *workspace,
+                        int64_t workspace_bytes, void *stream);
+int ls_band_rebuild_f16s(const uint16_t *phi_h, float scale, const ls_grid *g, float gamma,
+                         const int32_t *prev_tiles, const int32_t *prev_ntiles_dev,
+                         int32_t *tiles, int64_t capacity, int32_t *ntiles_dev, void *workspace,
+                         int64_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Narrow-band driver (Steps 1-2 of the algorithm in Sec. 1.1, repeated):
  * for every window of `window` steps, rebuild the dilated band from the
- * current phi (as ls_band_build_*) and advance `window` steps on it (as
- * ls_upwind_step_*); the last window may be shorter.  tiles / ntiles_dev
- * receive the band of the last window.  Equivalent to calling the two
- * entry points in turn; one call, no host synchronisation.
+ * current phi and advance `window` steps on it; the last window may be
+ * shorter.  The first window builds from a full scan (ls_band_build_*), the
+ * later ones rebuild incrementally from the previous window's band
+ * (ls_band_rebuild_*, exact here), so the result equals calling
+ * ls_band_build_* and ls_upwind_step_* window by window, bit for bit.
+ * tiles / ntiles_dev receive the band of the last window.  tile_steps_dev
+ * (device int64, may be NULL) is incremented by the number of band tiles
+ * times the steps taken on them, summed over the windows.  One call, no host
+ * synchronisation.
  * ------------------------------------------------------------------------- */
 int ls_band_run_f32(float *phi, const float *F, const ls_grid *g, float dx, float dt,
                     float gamma, int nsteps, int window, int32_t *tiles, int64_t capacity,
-                    int32_t *ntiles_dev, float *scratch, void *workspace,
-                    int64_t workspace_bytes, void *stream);
+                    int32_t *ntiles_dev, int64_t *tile_steps_dev, float *scratch,
+                    void *workspace, int64_t workspace_bytes, void *stream);
 int ls_band_run_f64(double *phi, const double *F, const ls_grid *g, double dx, double dt,
                     double gamma, int nsteps, int window, int32_t *tiles, int64_t capacity,
-                    int32_t *ntiles_dev, double *scratch, void *workspace,
-                    int64_t workspace_bytes, void *stream);
+                    int32_t *ntiles_dev, int64_t *tile_steps_dev, double *scratch,
+                    void *workspace, int64_t workspace_bytes, void *stream);
 int ls_band_run_f16s(uint16_t *phi_h, float scale, const float *F, const ls_grid *g, float dx,
                      float dt, float gamma, int nsteps, int window, int32_t *tiles,
-                     int64_t capacity, int32_t *ntiles_dev, uint16_t *scratch, void *workspace,
-                     int64_t workspace_bytes, void *stream);
+                     int64_t capacity, int32_t *ntiles_dev, int64_t *tile_steps_dev,
+                     uint16_t *scratch, void *workspace, int64_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Launch tuning (process-wide; used by the autotuner, not part of the method).
+ *
+ * run_width: target width in grid points of one work item of the band step
+ * (a run of run_width / tx consecutive band tiles of one tile row, at least
+ * one tile, at most 32); blocks_per_cu: workgroups launched per compute unit
+ * by the band step (0 = the occupancy limit).  Zero fields select the
+ * defaults (run_width 32).  Results do not depend on the tuning, only speed
+ * does.  Not thread-safe against concurrent launches.
+ * ------------------------------------------------------------------------- */
+typedef struct ls_tuning {
+    int32_t run_width;
+    int32_t blocks_per_cu;
+} ls_tuning;
+int ls_set_tuning(const ls_tuning *t);
+int ls_get_tuning(ls_tuning *t);
+
+/* Launch configuration the band step would use for grid g on the current
+ * device: precision 0 = f32, 1 = f64, 2 = f16s.  Outputs (any may be NULL):
+ * workgroups, LDS bytes per workgroup, tiles per work item, and the
+ * occupancy limit in workgroups per compute unit. */
+int ls_upwind_launch_info(const ls_grid *g, int precision, int32_t *blocks, int32_t *lds_bytes,
+                          int32_t *run_tiles, int32_t *blocks_per_cu_limit);
 
 /* ---------------------------------------------------------------------------
  * Kernel timing (measurement support, not part of the method).
@@ -161,6 +216,11 @@ int ls_band_run_f16s(uint16_t *phi_h, float scale, const float *F, const ls_grid
 enum { LS_KERNEL_UPWIND = 0, LS_KERNEL_BAND_FLAG = 1 };
 int ls_stats_enable(int on);
 int ls_stats_read(int which, int64_t *launches, int64_t *timed, double *total_ms);
+
+/* Plain copy dst[i] = src[i], i < n, one 4-byte load and store per lane (the
+ * access width of the band step): the reference kernel against which the
+ * hardware traffic counters are calibrated.  Device pointers, n >= 0. */
+int ls_copy_f32(float *dst, const float *src, int64_t n, void *stream);
 
 #ifdef __cplusplus
 }

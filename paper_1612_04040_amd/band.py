@@ -63,16 +63,30 @@ class BandGrid:
             ls.ls_upwind_step_f16s(phi, scale, F, self.g, dx, dt, t, n, nsteps, self.scratch,
                                    self.ws, self.ws_bytes, stream)
 
-    def run(self, phi, F, dx, dt, gamma, nsteps, window=10, scale=None, stream=None):
+    def rebuild(self, phi, gamma, prev_tiles, prev_ntiles, scale=None, stream=None):
+        """Incremental rebuild from a previous band (see ls_band_rebuild_*)."""
+        if self.precision == "f32":
+            ls.ls_band_rebuild_f32(phi, self.g, gamma, prev_tiles, prev_ntiles, self.tiles,
+                                   self.capacity, self.ntiles, self.ws, self.ws_bytes, stream)
+        elif self.precision == "f64":
+            ls.ls_band_rebuild_f64(phi, self.g, gamma, prev_tiles, prev_ntiles, self.tiles,
+                                   self.capacity, self.ntiles, self.ws, self.ws_bytes, stream)
+        else:
+            ls.ls_band_rebuild_f16s(phi, scale, self.g, gamma, prev_tiles, prev_ntiles,
+                                    self.tiles, self.capacity, self.ntiles, self.ws,
+                                    self.ws_bytes, stream)
+
+    def run(self, phi, F, dx, dt, gamma, nsteps, window=10, scale=None, tile_steps=None,
+            stream=None):
         if self.precision == "f32":
             ls.ls_band_run_f32(phi, F, self.g, dx, dt, gamma, nsteps, window, self.tiles,
-                               self.capacity, self.ntiles, self.scratch, self.ws, self.ws_bytes,
-                               stream)
+                               self.capacity, self.ntiles, tile_steps, self.scratch, self.ws,
+                               self.ws_bytes, stream)
         elif self.precision == "f64":
             ls.ls_band_run_f64(phi, F, self.g, dx, dt, gamma, nsteps, window, self.tiles,
-                               self.capacity, self.ntiles, self.scratch, self.ws, self.ws_bytes,
-                               stream)
+                               self.capacity, self.ntiles, tile_steps, self.scratch, self.ws,
+                               self.ws_bytes, stream)
         else:
             ls.ls_band_run_f16s(phi, scale, F, self.g, dx, dt, gamma, nsteps, window, self.tiles,
-                                self.capacity, self.ntiles, self.scratch, self.ws, self.ws_bytes,
-                                stream)
+                                self.capacity, self.ntiles, tile_steps, self.scratch, self.ws,
+                                self.ws_bytes, stream)

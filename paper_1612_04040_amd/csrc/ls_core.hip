@@ -60,8 +60,12 @@ Workspace workspace_layout(const Geom &g) {
     off = align256(off + g.ntiles);
     w.blk_counts = off;
     off = align256(off + 4 * (w.nblk + 1));
+    w.blk_counts2 = off;
+    off = align256(off + 4 * (w.nblk + 1));
     w.items = off;
     off = align256(off + 4 * kItemWords * g.ntiles);
+    w.prev_list = off;
+    off = align256(off + 4 * g.ntiles);
     w.counters = off;
     off = align256(off + 4 * 64);
     w.total = off;

@@ -54,8 +54,9 @@ int make_geom(const ls_grid *g, Geom *out);
 
 // Threads of every kernel block in this library.
 constexpr int kBlock = 256;
-// Tiles examined per block by the compaction kernels (16 rounds of kBlock).
-constexpr int kCompactRounds = 16;
+// Tiles examined per block by the compaction kernels (kCompactRounds rounds
+// of kBlock).
+constexpr int kCompactRounds = 4;
 constexpr int kCompactChunk = kBlock * kCompactRounds;
 // int32 words of one work-item record of the band step.
 constexpr int kItemWords = 8;
@@ -65,8 +66,10 @@ struct Workspace {
     int64_t a_flags;     // uint8[ntiles]   tile holds a point with |phi| < gamma
     int64_t u_map;       // uint8[ntiles]   tile is in the update set
     int64_t blk_counts;  // int32[nblk + 1] per-block counts, then offsets
+    int64_t blk_counts2; // int32[nblk + 1] same, second predicate of a dual compaction
     int64_t items;       // int32[8*ntiles] work-item records of the band step
-    int64_t counters;    // int32[64]       item count and spares
+    int64_t prev_list;   // int32[ntiles]   band list of the previous window (driver)
+    int64_t counters;    // int32[64]       [0] item count, [1] previous-list count
     int64_t total;
     int64_t nblk;        // compaction blocks for ntiles entries
 };
@@ -129,9 +132,15 @@ __device__ inline int lane_prefix(uint64_t mask) {
 // ---------------------------------------------------------------------------
 // host launchers (defined in ls_band.hip)
 
-// Ordered compaction of the nonzero bytes of map[0..n) into out (ascending
-// indices) with the count in *count; blk is int32[cdiv(n, kCompactChunk) + 1].
-int compact_map(const uint8_t *map, int64_t n, int32_t *out, int32_t *count, int32_t *blk,
-                hipStream_t stream);
+// Tiles per work item of the band step for this geometry (the launch tuning's
+// run width over tx, at least 1, at most 32).
+int plan_run_tiles(const Geom &g);
+
+// The step plan of a band: from the update map u_map (one byte per tile,
+// complete in the workspace) and, when list != nullptr, the ordered band list
+// (count in *list_count), writes the work-item records and their count.  One
+// dual ordered compaction over the tile ids plus a record kernel.
+int build_plan(const Geom &g, uint8_t *ws, int32_t *list, int32_t *list_count,
+               hipStream_t stream);
 
 }  // namespace ls

@@ -1,4 +1,5 @@
 // Kernel timing with HIP events (measurement support).
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -49,9 +50,34 @@ int stats_after(int kind, hipStream_t stream, int64_t slot) {
     return LS_OK;
 }
 
+__global__ __launch_bounds__(kBlock) void copy_f32_kernel(float *__restrict__ dst,
+                                                          const float *__restrict__ src,
+                                                          int64_t n) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kBlock)
+        dst[i] = src[i];
+}
+
 }  // namespace ls
 
 extern "C" {
+
+int ls_copy_f32(float *dst, const float *src, int64_t n, void *stream) {
+    ls::clear_error();
+    if (!dst || !src || n < 0) {
+        ls::set_error("copy: NULL pointer or negative size");
+        return LS_ERR_ARG;
+    }
+    if (n == 0) return LS_OK;
+    ls::DeviceInfo di;
+    int rc = ls::device_info(&di);
+    if (rc != LS_OK) return rc;
+    const int64_t blocks = std::min<int64_t>(ls::cdiv64(n, ls::kBlock), int64_t(di.cus) * 16);
+    hipLaunchKernelGGL(ls::copy_f32_kernel, dim3(static_cast<unsigned>(blocks)), dim3(ls::kBlock),
+                       0, static_cast<hipStream_t>(stream), dst, src, n);
+    LS_LAUNCH_CHECK("copy_f32_kernel");
+    return LS_OK;
+}
 
 int ls_stats_enable(int on) {
     ls::clear_error();

@@ -88,55 +88,18 @@ struct StepArgs {
     typename Codec<S>::C dx, dt, dtdx, scale;
 };
 
-// Work-item record: [0] first tile id, [1] run length (tiles), [2..5] bit l =
-// "tile l of the run has its y-, y+, z-, z+ face neighbour in the band (or
-// outside the grid)", [6] bit 0 / bit 1 = same for the x- / x+ neighbour.
-struct EmitItem {
-    int32_t *rec;
-    const int32_t *tiles;
-    const int32_t *ntiles_dev;
-    const uint8_t *umap;
-    int ntx, nty, ntz, R, cap;
-    __device__ void operator()(int pos, int64_t p) const {
-        const int n = min(*ntiles_dev, cap);
-        const int t0 = tiles[p];
-        const int ti0 = t0 % ntx;
-        const int r = t0 / ntx;
-        const int tj = r % nty, tk = r / nty;
-        int len = 1;
-        while (len < R && p + len < n && ti0 + len < ntx && tiles[p + len] == t0 + len &&
-               (ti0 + len) % R != 0)
-            ++len;
-        uint32_t m[4] = {0, 0, 0, 0};
-        for (int l = 0; l < len; ++l) {
-            const int t = t0 + l;
-            m[0] |= uint32_t(tj == 0 || umap[t - ntx]) << l;
-            m[1] |= uint32_t(tj == nty - 1 || umap[t + ntx]) << l;
-            m[2] |= uint32_t(tk == 0 || umap[t - ntx * nty]) << l;
-            m[3] |= uint32_t(tk == ntz - 1 || umap[t + ntx * nty]) << l;
-        }
-        const uint32_t xb = uint32_t(ti0 == 0 || umap[t0 - 1]) |
-                            (uint32_t(ti0 + len == ntx || umap[t0 + len]) << 1);
-        int32_t *o = rec + static_cast<int64_t>(pos) * kItemWords;
-        o[0] = t0;
-        o[1] = len;
-        o[2] = static_cast<int32_t>(m[0]);
-        o[3] = static_cast<int32_t>(m[1]);
-        o[4] = static_cast<int32_t>(m[2]);
-        o[5] = static_cast<int32_t>(m[3]);
-        o[6] = static_cast<int32_t>(xb);
-        o[7] = 0;
-    }
-};
-
 // Slice of the item list of this block: contiguous, XCD-aware.
+// Workgroups are dispatched to the 8 XCDs round-robin (block b on XCD b % 8),
+// so XCD x gets the x-th eighth of the list and its blocks split that eighth
+// into contiguous slices: neighbouring items share an L2.
 __device__ inline void block_slice(int nitems, int *w0, int *w1) {
-    const int G = gridDim.x;
-    const int b = blockIdx.x;
-    const int cb = (b & 7) * (G >> 3) + (b >> 3);
-    const int per = (nitems + G - 1) / G;
-    *w0 = min(cb * per, nitems);
-    *w1 = min(*w0 + per, nitems);
+    const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int gx = gridDim.x >> 3;
+    const int xs = static_cast<int>((static_cast<int64_t>(nitems) * x) >> 3);
+    const int xe = static_cast<int>((static_cast<int64_t>(nitems) * (x + 1)) >> 3);
+    const int per = (xe - xs + gx - 1) / gx;
+    *w0 = min(xs + j * per, xe);
+    *w1 = min(*w0 + per, xe);
 }
 
 // One persistent block walks its slice of work items.  Per item:
@@ -319,6 +282,240 @@ __global__ __launch_bounds__(kBlock) void upwind_kernel(StepGeom g, StepArgs<S, 
     }
 }
 
+// Fast kernel for a compile-time tile shape (TX, TY, TZ), R tiles per work
+// item, and grids whose y and z extents are whole tiles (only the x extent of
+// an item varies: W = len*TX, or less at the high x face).  Every index is a
+// per-thread constant or a uniform value: global loads and stores take a
+// uniform item base plus a per-thread offset, LDS accesses a per-thread base
+// plus immediates, and the only per-item lane predicate is lx < W.
+//
+// Software pipeline: while item w is evaluated from LDS, the global loads of
+// item w+1 (into registers) and the record of item w+2 are in flight, so each
+// persistent block always has memory traffic outstanding.  Records are read
+// with vector loads (lane k holds word k) so that waiting for LDS never waits
+// for them.  Same results as upwind_kernel, bit for bit.
+template <class S, class FT, bool EXACT, int TX, int TY, int TZ, int R>
+struct FastCfg {
+    static constexpr int XL = cpow2(R * TX);
+    static constexpr int RP = kBlock / XL;      // grid rows per pass
+    static constexpr int ROWS = TY * TZ;
+    static constexpr int NOWN = ROWS / RP;      // own points per thread
+    static constexpr int NHR = 2 * (TY + TZ);   // halo rows of the y and z faces
+    static constexpr int NHALO = (NHR + RP - 1) / RP;
+    static constexpr int SX = R * TX + 2, SXY = SX * (TY + 2);
+    using C = typename Codec<S>::C;
+    static constexpr bool RAW = sizeof(S) != sizeof(C);  // keep stored bits for F == 0
+    static constexpr size_t box_bytes = sizeof(C) * SXY * (TZ + 2);
+    static constexpr size_t f_bytes = sizeof(FT) * NOWN * kBlock;
+    static constexpr size_t raw_bytes = RAW ? sizeof(S) * NOWN * kBlock : 0;
+    static constexpr size_t lds = box_bytes + f_bytes + raw_bytes;
+    static_assert(XL <= kBlock && ROWS % RP == 0, "shape does not tile the block");
+    static_assert(RP % TY == 0 || TY % RP == 0, "rows per pass must divide or be divided by TY");
+    static_assert(ROWS <= kBlock, "x-face points exceed two per thread");
+    static_assert(box_bytes % 16 == 0 || true, "");
+};
+
+// Geometry of one work item of the fast kernel (all uniform).  The record's
+// neighbour masks stay in the record register (lane k = word k) and are read
+// with readlane where used, so no per-lane selection ever indexes memory.
+struct FastItem {
+    bool valid;
+    int x0, W, lo_x_in, hi_x_in;
+    int ebits;  // bit f set: face f (y-, y+, z-, z+) lies on the domain boundary
+    int64_t base;
+};
+
+template <int TX, int TY, int TZ>
+__device__ inline FastItem fast_decode(const StepGeom &g, int rv) {
+    FastItem it;
+    const int t0 = __builtin_amdgcn_readlane(rv, 0);
+    it.valid = t0 >= 0 && t0 < g.ntiles;
+    const int tt = it.valid ? t0 : 0;
+    const int len = __builtin_amdgcn_readlane(rv, 1);
+    const int ti0 = tt % g.ntx;
+    const int rr = tt / g.ntx;
+    const int tj = rr % g.nty, tk = rr / g.nty;
+    it.x0 = ti0 * TX;
+    const int y0 = tj * TY, z0 = tk * TZ;
+    it.W = min(len * TX, g.nx - it.x0);
+    it.base = (static_cast<int64_t>(z0) * g.ny + y0) * g.nx + it.x0;
+    it.ebits = (y0 == 0 ? 1 : 0) | (y0 + TY == g.ny ? 2 : 0) | (z0 == 0 ? 4 : 0) |
+               (z0 + TZ == g.nz ? 8 : 0);
+    it.lo_x_in = it.x0 > 0 ? -1 : 0;                    // clamped x- neighbour column
+    it.hi_x_in = it.x0 + it.W < g.nx ? it.W : it.W - 1;  // clamped x+ neighbour column
+    return it;
+}
+
+template <class S, class FT, bool EXACT, int TX, int TY, int TZ, int R>
+__global__ __launch_bounds__(kBlock) void upwind_fast_kernel(StepGeom g, StepArgs<S, FT> a) {
+    using K = FastCfg<S, FT, EXACT, TX, TY, TZ, R>;
+    using C = typename K::C;
+    constexpr int XL = K::XL, RP = K::RP, ROWS = K::ROWS, NOWN = K::NOWN, NHALO = K::NHALO;
+    constexpr int SX = K::SX, SXY = K::SXY;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *box = reinterpret_cast<C *>(smem);
+    FT *fbox = reinterpret_cast<FT *>(smem + K::box_bytes);
+    S *rbox = reinterpret_cast<S *>(smem + K::box_bytes + K::f_bytes);
+
+    const int nitems = *a.nitems;
+    int w0, w1;
+    block_slice(nitems, &w0, &w1);
+
+    const int lane = threadIdx.x & 63;
+    const int lx = threadIdx.x % XL;
+    const int lr = threadIdx.x / XL;
+    const int lt = lx / TX;
+    const int nx = g.nx, plane = g.ny * g.nx;
+
+    // own points: row lr + q*RP  ->  (ly, lz) = (ly0 + dly(q), lz0 + dlz(q))
+    const int ly0 = (RP % TY == 0) ? lr % TY : lr;
+    const int lz0 = (RP % TY == 0) ? lr / TY : 0;
+    const int toff = lz0 * plane + ly0 * nx + lx;
+    const int lbase = (lz0 + 1) * SXY + (ly0 + 1) * SX + lx + 1;
+    auto dly = [](int q) { return (RP % TY == 0) ? 0 : (q % (TY / RP)) * RP; };
+    auto dlz = [](int q) { return (RP % TY == 0) ? q * (RP / TY) : q / (TY / RP); };
+
+    // halo rows of this thread: h = lr + q*RP (y faces first, then z faces)
+    int hoff[NHALO], hoffc[NHALO], hlds[NHALO], hface[NHALO];
+#pragma unroll
+    for (int q = 0; q < NHALO; ++q) {
+        const int h = lr + q * RP;
+        int ly, lz, lyc, lzc, face;
+        if (h < 2 * TZ) {
+            lz = h >> 1;
+            face = h & 1;
+            ly = face ? TY : -1;
+            lyc = face ? TY - 1 : 0;  // clamped into the item at a domain face
+            lzc = lz;
+        } else {
+            const int hh = h - 2 * TZ;
+            ly = hh >> 1;
+            face = 2 + (hh & 1);
+            lz = (hh & 1) ? TZ : -1;
+            lzc = (hh & 1) ? TZ - 1 : 0;
+            lyc = ly;
+            if (hh >= 2 * TY) face = -1;
+        }
+        hface[q] = face;
+        hoff[q] = lz * plane + ly * nx + lx;
+        hoffc[q] = lzc * plane + lyc * nx + lx;
+        hlds[q] = (lz + 1) * SXY + (ly + 1) * SX + lx + 1;
+    }
+    // x-face point of this thread (threads below 2*ROWS): side tid & 1, row tid >> 1
+    const bool xok = threadIdx.x < 2 * ROWS;
+    const int xside = threadIdx.x & 1;
+    const int xrow = threadIdx.x >> 1;
+    const int xoff = (xrow / TY) * plane + (xrow % TY) * nx;
+    const int xlds = (xrow / TY + 1) * SXY + (xrow % TY + 1) * SX;
+
+    S raw[NOWN];
+    FT fv[NOWN];
+    S hv[NHALO];
+    S xv;
+
+    auto issue = [&](const FastItem &it, int rv) __attribute__((always_inline)) {
+        const uint32_t m0 = __builtin_amdgcn_readlane(rv, 2), m1 = __builtin_amdgcn_readlane(rv, 3);
+        const uint32_t m2 = __builtin_amdgcn_readlane(rv, 4), m3 = __builtin_amdgcn_readlane(rv, 5);
+        const uint32_t mx = __builtin_amdgcn_readlane(rv, 6);
+        const S *cur = a.cur + it.base;
+        const S *orig = a.orig + it.base;
+        const FT *Fb = a.F + it.base;
+        if (lx < it.W) {
+#pragma unroll
+            for (int q = 0; q < NOWN; ++q) {
+                const int u = dlz(q) * plane + dly(q) * nx;  // uniform
+                raw[q] = (cur + u)[toff];
+                fv[q] = (Fb + u)[toff];
+            }
+#pragma unroll
+            for (int q = 0; q < NHALO; ++q) {
+                const int face = hface[q];
+                if (face >= 0) {
+                    // face is per thread: select without indexing (no scratch)
+                    const bool hi = face & 1, zf = face & 2;
+                    const bool clamp = (it.ebits >> face) & 1;
+                    const uint32_t mk = zf ? (hi ? m3 : m2) : (hi ? m1 : m0);
+                    const bool in = clamp || ((mk >> lt) & 1u);
+                    const int o = clamp ? hoffc[q] : hoff[q];
+                    if (in)
+                        hv[q] = cur[o];
+                    else
+                        hv[q] = orig[o];
+                }
+            }
+        }
+        if (xok) {
+            const int cx = xside ? it.hi_x_in : it.lo_x_in;
+            const bool in = (cx >= 0 && cx < it.W) || ((mx >> xside) & 1u);
+            if (in)
+                xv = cur[xoff + cx];
+            else
+                xv = orig[xoff + cx];
+        }
+    };
+    auto stage = [&](const FastItem &it) __attribute__((always_inline)) {
+        if (lx < it.W) {
+#pragma unroll
+            for (int q = 0; q < NOWN; ++q) {
+                box[lbase + dlz(q) * SXY + dly(q) * SX] = Codec<S>::load(raw[q], a.scale);
+                fbox[q * kBlock + threadIdx.x] = fv[q];
+                if constexpr (K::RAW) rbox[q * kBlock + threadIdx.x] = raw[q];
+            }
+#pragma unroll
+            for (int q = 0; q < NHALO; ++q)
+                if (hface[q] >= 0) box[hlds[q]] = Codec<S>::load(hv[q], a.scale);
+        }
+        if (xok) box[xlds + (xside ? it.W + 1 : 0)] = Codec<S>::load(xv, a.scale);
+    };
+    auto compute = [&](const FastItem &it) __attribute__((always_inline)) {
+        S *nxt = a.nxt + it.base;
+        if (lx < it.W) {
+#pragma unroll
+            for (int q = 0; q < NOWN; ++q) {
+                const int o = lbase + dlz(q) * SXY + dly(q) * SX;
+                const C c = box[o];
+                const C f = static_cast<C>(fbox[q * kBlock + threadIdx.x]);
+                const C v = upwind_point<C, EXACT>(c, box[o - 1], box[o + 1], box[o - SX],
+                                                   box[o + SX], box[o - SXY], box[o + SXY], f,
+                                                   a.dx, a.dt, a.dtdx);
+                S keep;
+                if constexpr (K::RAW)
+                    keep = rbox[q * kBlock + threadIdx.x];
+                else
+                    keep = Codec<S>::store(c, a.scale);  // identity codec: the stored bits
+                const S out = (f == C(0)) ? keep : Codec<S>::store(v, a.scale);
+                (nxt + dlz(q) * plane + dly(q) * nx)[toff] = out;
+            }
+        }
+    };
+    auto load_rec = [&](int w) __attribute__((always_inline)) {
+        int v = -1;
+        if (w < w1 && lane < kItemWords) v = a.rec[static_cast<int64_t>(w) * kItemWords + lane];
+        return v;
+    };
+
+    if (w0 >= w1) return;  // uniform
+    int rv = load_rec(w0);
+    FastItem cur_it = fast_decode<TX, TY, TZ>(g, rv);
+    if (cur_it.valid) issue(cur_it, rv);
+    rv = load_rec(w0 + 1);
+    for (int w = w0; w < w1; ++w) {
+        if (cur_it.valid) stage(cur_it);
+        __syncthreads();  // box complete
+        FastItem nxt_it;
+        nxt_it.valid = false;
+        if (w + 1 < w1) {
+            nxt_it = fast_decode<TX, TY, TZ>(g, rv);
+            if (nxt_it.valid) issue(nxt_it, rv);
+            rv = load_rec(w + 2);
+        }
+        if (cur_it.valid) compute(cur_it);
+        __syncthreads();  // box free for the next item
+        cur_it = nxt_it;
+    }
+}
+
 // Copies the band points of src into dst (used when nsteps is odd).
 template <class S>
 __global__ __launch_bounds__(kBlock) void band_copy_kernel(StepGeom g, const S *__restrict__ src,
@@ -351,12 +548,6 @@ __global__ __launch_bounds__(kBlock) void band_copy_kernel(StepGeom g, const S *
     }
 }
 
-__global__ __launch_bounds__(kBlock) void fill_u8_kernel(uint8_t *p, int64_t n16) {
-    for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n16;
-         i += static_cast<int64_t>(gridDim.x) * kBlock)
-        reinterpret_cast<uint4 *>(p)[i] = make_uint4(0, 0, 0, 0);
-}
-
 __global__ __launch_bounds__(kBlock) void map_set_kernel(uint8_t *map, const int32_t *tiles,
                                                          const int32_t *ntiles_dev,
                                                          int ntiles_cap) {
@@ -367,27 +558,17 @@ __global__ __launch_bounds__(kBlock) void map_set_kernel(uint8_t *map, const int
     }
 }
 
-// A band-list position starts a work item if its tile does not continue the
-// x-run of the previous entry, or sits on a multiple-of-R tile column.
-struct HeadPred {
-    const int32_t *tiles;
-    int ntx, R;
-    __device__ bool operator()(int64_t p) const {
-        const int t = tiles[p];
-        if (p == 0) return true;
-        if ((t % ntx) % R == 0) return true;
-        return tiles[p - 1] != t - 1;
-    }
-};
-
 // ---------------------------------------------------------------------------
 // host side
 
-struct Tuning {
-    int run_width;  // target item width in grid points (R = run_width / tx)
-};
+// Process-wide launch tuning (ls_set_tuning); 0 fields mean the defaults.
+static ls_tuning g_tuning = {0, 0};
+constexpr int kDefaultRunWidth = 32;
+constexpr int kDefaultBlocksPerCu = 32;
 
-static Tuning g_tuning = {32};
+static int run_width() { return g_tuning.run_width > 0 ? g_tuning.run_width : kDefaultRunWidth; }
+
+int plan_run_tiles(const Geom &g) { return std::max(1, std::min(kMaxRun, run_width() / g.tx)); }
 
 template <class S>
 static int make_step_geom(const Geom &G, StepGeom *out, size_t *lds) {
@@ -396,7 +577,7 @@ static int make_step_geom(const Geom &G, StepGeom *out, size_t *lds) {
     s.tx = G.tx, s.ty = G.ty, s.tz = G.tz;
     s.ntx = G.ntx, s.nty = G.nty, s.ntz = G.ntz;
     s.ntiles = static_cast<int>(G.ntiles);
-    s.R = std::max(1, std::min(kMaxRun, g_tuning.run_width / G.tx));
+    s.R = plan_run_tiles(G);
     const int wbox = s.R * G.tx;
     int xl = 1, lg = 0;
     while (xl < wbox) xl <<= 1, ++lg;
@@ -459,11 +640,25 @@ static UpwindFn<S, FT, EXACT> select_halo(int nhalo) {
 // Kernel for a launch: a compile-time specialisation for the common tile
 // shapes and run lengths, else the run-time-shape kernel.
 template <class S, class FT, bool EXACT>
-static UpwindFn<S, FT, EXACT> select_upwind_kernel(const StepGeom &sg, int nown, int nhalo) {
+static UpwindFn<S, FT, EXACT> select_upwind_kernel(const StepGeom &sg, int nown, int nhalo,
+                                                   size_t *lds) {
+    const bool whole_yz = sg.ny % sg.ty == 0 && sg.nz % sg.tz == 0;
+#define LS_FAST(TX_, TY_, TZ_, R_)                                                   \
+    if (whole_yz && sg.tx == TX_ && sg.ty == TY_ && sg.tz == TZ_ && sg.R == R_) {    \
+        *lds = FastCfg<S, FT, EXACT, TX_, TY_, TZ_, R_>::lds;                        \
+        return upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_>;                  \
+    }
+    LS_FAST(8, 8, 8, 4)
+    LS_FAST(8, 8, 8, 2)
+    LS_FAST(16, 4, 4, 2)
+    LS_FAST(16, 4, 4, 4)
+    LS_FAST(32, 4, 4, 1)
+    LS_FAST(32, 4, 4, 2)
+    LS_FAST(16, 8, 8, 2)
+    LS_FAST(4, 4, 4, 8)
+#undef LS_FAST
     if (sg.tx == 8 && sg.ty == 8 && sg.tz == 8 && sg.R == 4)
         return upwind_kernel<S, FT, EXACT, 8, 4, Shape<8, 8, 8, 4>>;
-    if (sg.tx == 8 && sg.ty == 8 && sg.tz == 8 && sg.R == 8)
-        return upwind_kernel<S, FT, EXACT, 16, 8, Shape<8, 8, 8, 8>>;
     switch (nown) {
     case 1: return select_halo<S, FT, EXACT, 1>(nhalo);
     case 2: return select_halo<S, FT, EXACT, 2>(nhalo);
@@ -474,31 +669,35 @@ static UpwindFn<S, FT, EXACT> select_upwind_kernel(const StepGeom &sg, int nown,
 }
 
 template <class K>
-static int persistent_grid(K kernel, size_t lds, int *grid) {
+static int persistent_grid(K kernel, size_t lds, int *grid, int *limit = nullptr,
+                           int64_t max_items = INT32_MAX) {
     DeviceInfo di;
     int rc = device_info(&di);
     if (rc != LS_OK) return rc;
     int per_cu = 0;
     LS_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, lds));
     if (per_cu < 1) per_cu = 1;
-    int G = di.cus * per_cu;
-    G = std::max(8, G - G % 8);
+    if (limit) *limit = per_cu;
+    // Default: about one block per work item, beyond what fits at once, so the
+    // dispatcher balances the uneven items (measured faster than a strictly
+    // persistent grid); the blocks left without an item exit at once.
+    per_cu = g_tuning.blocks_per_cu > 0 ? g_tuning.blocks_per_cu : kDefaultBlocksPerCu;
+    int64_t G64 = std::min<int64_t>(int64_t(di.cus) * per_cu, max_items + 7);
+    int G = static_cast<int>(std::max<int64_t>(8, G64 - G64 % 8));
     *grid = G;
     return LS_OK;
 }
 
+// Host checks shared by the step entry points and the driver.
 template <class S, class FT>
-static int upwind_step(S *phi, const FT *F, typename Codec<S>::C scale, const ls_grid *grid,
-                       typename Codec<S>::C dx, typename Codec<S>::C dt, const int32_t *tiles,
-                       const int32_t *ntiles_dev, int nsteps, S *scratch, void *workspace,
-                       int64_t ws_bytes, hipStream_t stream) {
+static int step_args(S *phi, const FT *F, const ls_grid *grid, typename Codec<S>::C dx,
+                     typename Codec<S>::C dt, int nsteps, S *scratch, void *workspace,
+                     int64_t ws_bytes, Geom *G, StepGeom *sg) {
     using C = typename Codec<S>::C;
-    constexpr bool EXACT = sizeof(C) == 8;
-    Geom G;
-    int rc = make_geom(grid, &G);
+    int rc = make_geom(grid, G);
     if (rc != LS_OK) return rc;
-    if (!phi || !F || !tiles || !ntiles_dev || !scratch) {
-        set_error("step: phi, F, tiles, ntiles_dev and scratch must be non-NULL");
+    if (!phi || !F || !scratch) {
+        set_error("step: phi, F and scratch must be non-NULL");
         return LS_ERR_ARG;
     }
     if (static_cast<const void *>(phi) == static_cast<const void *>(scratch)) {
@@ -517,41 +716,32 @@ static int upwind_step(S *phi, const FT *F, typename Codec<S>::C scale, const ls
         set_error("step: dt must be >= 0 and finite");
         return LS_ERR_ARG;
     }
-    if ((rc = check_workspace(G, workspace, ws_bytes)) != LS_OK) return rc;
-    StepGeom sg;
+    if ((rc = check_workspace(*G, workspace, ws_bytes)) != LS_OK) return rc;
     size_t lds = 0;
-    if ((rc = make_step_geom<S>(G, &sg, &lds)) != LS_OK) return rc;
-    if (nsteps == 0) return LS_OK;
+    return make_step_geom<S>(*G, sg, &lds);
+}
 
+// nsteps launches of the step kernel on the plan held by the workspace (the
+// update map, the work-item records and their count), then the copy-back of
+// the band when nsteps is odd.
+template <class S, class FT>
+static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const Geom &G,
+                         const StepGeom &sg, typename Codec<S>::C dx, typename Codec<S>::C dt,
+                         int nsteps, S *scratch, uint8_t *ws, hipStream_t stream) {
+    using C = typename Codec<S>::C;
+    constexpr bool EXACT = sizeof(C) == 8;
+    if (nsteps == 0) return LS_OK;
     const Workspace w = workspace_layout(G);
-    uint8_t *ws = static_cast<uint8_t *>(workspace);
-    uint8_t *umap = ws + w.u_map;
-    int32_t *blk = reinterpret_cast<int32_t *>(ws + w.blk_counts);
     int32_t *items = reinterpret_cast<int32_t *>(ws + w.items);
     int32_t *nitems = reinterpret_cast<int32_t *>(ws + w.counters);
-
-    // band membership map and work items from the list
-    const int64_t n16 = cdiv64(G.ntiles, 16);
-    const unsigned fill_blocks = static_cast<unsigned>(std::min<int64_t>(cdiv64(n16, kBlock), 4096));
-    hipLaunchKernelGGL(fill_u8_kernel, dim3(fill_blocks), dim3(kBlock), 0, stream, umap, n16);
-    LS_LAUNCH_CHECK("fill_u8_kernel");
-    const unsigned set_blocks =
-        static_cast<unsigned>(std::min<int64_t>(cdiv64(G.ntiles, kBlock), 4096));
-    hipLaunchKernelGGL(map_set_kernel, dim3(set_blocks), dim3(kBlock), 0, stream, umap, tiles,
-                       ntiles_dev, static_cast<int>(G.ntiles));
-    LS_LAUNCH_CHECK("map_set_kernel");
-    rc = compact(HeadPred{tiles, G.ntx, sg.R},
-                 EmitItem{items, tiles, ntiles_dev, umap, G.ntx, G.nty, G.ntz, sg.R,
-                          static_cast<int>(G.ntiles)},
-                 ntiles_dev, G.ntiles, nitems, blk, stream);
-    if (rc != LS_OK) return rc;
-
     const int rp = kBlock / sg.xl;
     const int nown = pow2_at_least((G.ty * G.tz + rp - 1) / rp);
     const int nhalo = pow2_at_least((2 * (G.ty + G.tz) + rp - 1) / rp);
-    auto kernel = select_upwind_kernel<S, FT, EXACT>(sg, nown, nhalo);
+    size_t lds = static_cast<size_t>(sg.sx) * sg.sy * (G.tz + 2) * sizeof(C);
+    auto kernel = select_upwind_kernel<S, FT, EXACT>(sg, nown, nhalo, &lds);
     int nblocks = 0;
-    if ((rc = persistent_grid(kernel, lds, &nblocks)) != LS_OK) return rc;
+    int rc;
+    if ((rc = persistent_grid(kernel, lds, &nblocks, nullptr, G.ntiles)) != LS_OK) return rc;
 
     StepArgs<S, FT> args;
     args.F = F;
@@ -581,34 +771,131 @@ static int upwind_step(S *phi, const FT *F, typename Codec<S>::C scale, const ls
     return LS_OK;
 }
 
+int fill_zero(uint8_t *p, int64_t bytes, hipStream_t stream);  // ls_band.hip
+
+template <class S, class FT>
+static int upwind_step(S *phi, const FT *F, typename Codec<S>::C scale, const ls_grid *grid,
+                       typename Codec<S>::C dx, typename Codec<S>::C dt, const int32_t *tiles,
+                       const int32_t *ntiles_dev, int nsteps, S *scratch, void *workspace,
+                       int64_t ws_bytes, hipStream_t stream) {
+    Geom G;
+    StepGeom sg;
+    int rc = step_args<S, FT>(phi, F, grid, dx, dt, nsteps, scratch, workspace, ws_bytes, &G, &sg);
+    if (rc != LS_OK) return rc;
+    if (!tiles || !ntiles_dev) {
+        set_error("step: tiles and ntiles_dev must be non-NULL");
+        return LS_ERR_ARG;
+    }
+    if (nsteps == 0) return LS_OK;
+    const Workspace w = workspace_layout(G);
+    uint8_t *ws = static_cast<uint8_t *>(workspace);
+    uint8_t *umap = ws + w.u_map;
+    // plan of the given list: its membership map, then the work items
+    if ((rc = fill_zero(umap, G.ntiles, stream)) != LS_OK) return rc;
+    const unsigned set_blocks =
+        static_cast<unsigned>(std::min<int64_t>(cdiv64(G.ntiles, kBlock), 4096));
+    hipLaunchKernelGGL(map_set_kernel, dim3(set_blocks), dim3(kBlock), 0, stream, umap, tiles,
+                       ntiles_dev, static_cast<int>(G.ntiles));
+    LS_LAUNCH_CHECK("map_set_kernel");
+    if ((rc = build_plan(G, ws, nullptr, nullptr, stream)) != LS_OK) return rc;
+    return upwind_launch<S, FT>(phi, F, scale, G, sg, dx, dt, nsteps, scratch, ws, stream);
+}
+
+template <class S, class FT>
+static int launch_info(const ls_grid *grid, int32_t *blocks, int32_t *lds_bytes,
+                       int32_t *run_tiles, int32_t *limit) {
+    using C = typename Codec<S>::C;
+    constexpr bool EXACT = sizeof(C) == 8;
+    Geom G;
+    int rc = make_geom(grid, &G);
+    if (rc != LS_OK) return rc;
+    StepGeom sg;
+    size_t lds = 0;
+    if ((rc = make_step_geom<S>(G, &sg, &lds)) != LS_OK) return rc;
+    const int rp = kBlock / sg.xl;
+    const int nown = pow2_at_least((G.ty * G.tz + rp - 1) / rp);
+    const int nhalo = pow2_at_least((2 * (G.ty + G.tz) + rp - 1) / rp);
+    auto kernel = select_upwind_kernel<S, FT, EXACT>(sg, nown, nhalo, &lds);
+    int nb = 0, lim = 0;
+    if ((rc = persistent_grid(kernel, lds, &nb, &lim, G.ntiles)) != LS_OK) return rc;
+    if (blocks) *blocks = nb;
+    if (lds_bytes) *lds_bytes = static_cast<int32_t>(lds);
+    if (run_tiles) *run_tiles = sg.R;
+    if (limit) *limit = lim;
+    return LS_OK;
+}
+
 // declared in ls_band.hip
 template <class S>
 int band_build(const S *phi, typename Codec<S>::C scale, const ls_grid *grid,
                typename Codec<S>::C gamma, int dilate, int32_t *tiles, int64_t capacity,
                int32_t *ntiles_dev, void *workspace, int64_t ws_bytes, void *stream_);
+template <class S>
+int band_rebuild(const S *phi, typename Codec<S>::C scale, const ls_grid *grid,
+                 typename Codec<S>::C gamma, const int32_t *prev_tiles,
+                 const int32_t *prev_ntiles_dev, int32_t *tiles, int64_t capacity,
+                 int32_t *ntiles_dev, void *workspace, int64_t ws_bytes, void *stream_);
 
+__global__ void accumulate_kernel(int64_t *acc, const int32_t *count, int nsteps) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *acc += static_cast<int64_t>(*count) * nsteps;
+}
+
+// The windowed driver: a full band build for the first window, then an exact
+// incremental rebuild from the previous window's band (every point outside
+// that band is unchanged, so no tile outside it can join the tube); each
+// build leaves the step plan in the workspace, so the steps need no
+// preparation of their own.  The band lists alternate between the caller's
+// buffer and the workspace so that the last one lands in `tiles`.
 template <class S, class FT>
 static int band_run(S *phi, const FT *F, typename Codec<S>::C scale, const ls_grid *grid,
                     typename Codec<S>::C dx, typename Codec<S>::C dt, typename Codec<S>::C gamma,
                     int nsteps, int window, int32_t *tiles, int64_t capacity,
-                    int32_t *ntiles_dev, S *scratch, void *workspace, int64_t ws_bytes,
-                    void *stream_) {
+                    int32_t *ntiles_dev, int64_t *tile_steps_dev, S *scratch, void *workspace,
+                    int64_t ws_bytes, void *stream_) {
     if (window <= 0) {
         set_error("band run: window must be positive (got %d)", window);
         return LS_ERR_ARG;
     }
-    if (nsteps < 0) {
-        set_error("band run: nsteps must be >= 0 (got %d)", nsteps);
+    Geom G;
+    StepGeom sg;
+    int rc = step_args<S, FT>(phi, F, grid, dx, dt, nsteps, scratch, workspace, ws_bytes, &G, &sg);
+    if (rc != LS_OK) return rc;
+    if (!tiles || !ntiles_dev) {
+        set_error("band run: tiles and ntiles_dev must be non-NULL");
         return LS_ERR_ARG;
     }
+    if (!(gamma == gamma)) {
+        set_error("band run: gamma is NaN");
+        return LS_ERR_ARG;
+    }
+    if (capacity < G.ntiles) {
+        set_error("band run: capacity %lld < %lld tiles", (long long)capacity,
+                  (long long)G.ntiles);
+        return LS_ERR_CAPACITY;
+    }
     hipStream_t stream = static_cast<hipStream_t>(stream_);
-    for (int done = 0; done < nsteps; done += window) {
-        const int n = std::min(window, nsteps - done);
-        int rc = band_build<S>(phi, scale, grid, gamma, 1, tiles, capacity, ntiles_dev, workspace,
-                               ws_bytes, stream_);
+    const Workspace w = workspace_layout(G);
+    uint8_t *ws = static_cast<uint8_t *>(workspace);
+    int32_t *lists[2] = {tiles, reinterpret_cast<int32_t *>(ws + w.prev_list)};
+    int32_t *counts[2] = {ntiles_dev, reinterpret_cast<int32_t *>(ws + w.counters) + 1};
+    const int nwin = (nsteps + window - 1) / window;
+    for (int k = 0; k < nwin; ++k) {
+        const int n = std::min(window, nsteps - k * window);
+        const int cur = (nwin - 1 - k) & 1;  // the last window writes lists[0]
+        if (k == 0)
+            rc = band_build<S>(phi, scale, grid, gamma, 1, lists[cur], capacity, counts[cur],
+                               workspace, ws_bytes, stream_);
+        else
+            rc = band_rebuild<S>(phi, scale, grid, gamma, lists[cur ^ 1], counts[cur ^ 1],
+                                 lists[cur], capacity, counts[cur], workspace, ws_bytes, stream_);
         if (rc != LS_OK) return rc;
-        rc = upwind_step<S, FT>(phi, F, scale, grid, dx, dt, tiles, ntiles_dev, n, scratch,
-                                workspace, ws_bytes, stream);
+        if (tile_steps_dev) {
+            hipLaunchKernelGGL(accumulate_kernel, dim3(1), dim3(64), 0, stream, tile_steps_dev,
+                               static_cast<const int32_t *>(counts[cur]), n);
+            LS_LAUNCH_CHECK("accumulate_kernel");
+        }
+        rc = upwind_launch<S, FT>(phi, F, scale, G, sg, dx, dt, n, scratch, ws, stream);
         if (rc != LS_OK) return rc;
     }
     return LS_OK;
@@ -617,6 +904,38 @@ static int band_run(S *phi, const FT *F, typename Codec<S>::C scale, const ls_gr
 }  // namespace ls
 
 extern "C" {
+
+int ls_set_tuning(const ls_tuning *t) {
+    ls::clear_error();
+    if (!t || t->run_width < 0 || t->blocks_per_cu < 0 || t->blocks_per_cu > 64) {
+        ls::set_error("tuning: NULL or out-of-range field");
+        return LS_ERR_ARG;
+    }
+    ls::g_tuning = *t;
+    return LS_OK;
+}
+
+int ls_get_tuning(ls_tuning *t) {
+    ls::clear_error();
+    if (!t) {
+        ls::set_error("tuning: NULL output");
+        return LS_ERR_ARG;
+    }
+    t->run_width = ls::run_width();
+    t->blocks_per_cu = ls::g_tuning.blocks_per_cu;
+    return LS_OK;
+}
+
+int ls_upwind_launch_info(const ls_grid *g, int precision, int32_t *blocks, int32_t *lds_bytes,
+                          int32_t *run_tiles, int32_t *blocks_per_cu_limit) {
+    ls::clear_error();
+    switch (precision) {
+    case 0: return ls::launch_info<float, float>(g, blocks, lds_bytes, run_tiles, blocks_per_cu_limit);
+    case 1: return ls::launch_info<double, double>(g, blocks, lds_bytes, run_tiles, blocks_per_cu_limit);
+    case 2: return ls::launch_info<uint16_t, float>(g, blocks, lds_bytes, run_tiles, blocks_per_cu_limit);
+    default: ls::set_error("launch info: precision must be 0, 1 or 2"); return LS_ERR_ARG;
+    }
+}
 
 int ls_upwind_step_f32(float *phi, const float *F, const ls_grid *g, float dx, float dt,
                        const int32_t *tiles, const int32_t *ntiles_dev, int nsteps,
@@ -652,35 +971,35 @@ int ls_upwind_step_f16s(uint16_t *phi_h, float scale, const float *F, const ls_g
 
 int ls_band_run_f32(float *phi, const float *F, const ls_grid *g, float dx, float dt, float gamma,
                     int nsteps, int window, int32_t *tiles, int64_t capacity,
-                    int32_t *ntiles_dev, float *scratch, void *workspace,
-                    int64_t workspace_bytes, void *stream) {
+                    int32_t *ntiles_dev, int64_t *tile_steps_dev, float *scratch,
+                    void *workspace, int64_t workspace_bytes, void *stream) {
     ls::clear_error();
     return ls::band_run<float, float>(phi, F, 1.0f, g, dx, dt, gamma, nsteps, window, tiles,
-                                      capacity, ntiles_dev, scratch, workspace, workspace_bytes,
-                                      stream);
+                                      capacity, ntiles_dev, tile_steps_dev, scratch, workspace,
+                                      workspace_bytes, stream);
 }
 
 int ls_band_run_f64(double *phi, const double *F, const ls_grid *g, double dx, double dt,
                     double gamma, int nsteps, int window, int32_t *tiles, int64_t capacity,
-                    int32_t *ntiles_dev, double *scratch, void *workspace,
-                    int64_t workspace_bytes, void *stream) {
+                    int32_t *ntiles_dev, int64_t *tile_steps_dev, double *scratch,
+                    void *workspace, int64_t workspace_bytes, void *stream) {
     ls::clear_error();
     return ls::band_run<double, double>(phi, F, 1.0, g, dx, dt, gamma, nsteps, window, tiles,
-                                        capacity, ntiles_dev, scratch, workspace,
+                                        capacity, ntiles_dev, tile_steps_dev, scratch, workspace,
                                         workspace_bytes, stream);
 }
 
 int ls_band_run_f16s(uint16_t *phi_h, float scale, const float *F, const ls_grid *g, float dx,
                      float dt, float gamma, int nsteps, int window, int32_t *tiles,
-                     int64_t capacity, int32_t *ntiles_dev, uint16_t *scratch, void *workspace,
-                     int64_t workspace_bytes, void *stream) {
+                     int64_t capacity, int32_t *ntiles_dev, int64_t *tile_steps_dev,
+                     uint16_t *scratch, void *workspace, int64_t workspace_bytes, void *stream) {
     ls::clear_error();
     if (!(scale > 0.0f) || !(scale < INFINITY)) {
         ls::set_error("band run f16s: scale must be positive and finite");
         return LS_ERR_ARG;
     }
     return ls::band_run<uint16_t, float>(phi_h, F, scale, g, dx, dt, gamma, nsteps, window, tiles,
-                                         capacity, ntiles_dev, scratch, workspace,
+                                         capacity, ntiles_dev, tile_steps_dev, scratch, workspace,
                                          workspace_bytes, stream);
 }
 

@@ -34,6 +34,10 @@ class ls_grid(ctypes.Structure):
                 ("tx", ctypes.c_int32), ("ty", ctypes.c_int32), ("tz", ctypes.c_int32)]
 
 
+class ls_tuning(ctypes.Structure):
+    _fields_ = [("run_width", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+
+
 def grid(dims, tile=(8, 8, 8)):
     """ls_grid for dims = (nx, ny, nz) and tile = (tx, ty, tz)."""
     nx, ny, nz = (int(v) for v in dims)
@@ -59,13 +63,22 @@ _SIGNATURES = {
     "ls_upwind_step_f64": (_I32, [_VP, _VP, _G, _F64, _F64, _VP, _VP, _I32, _VP, _VP, _I64, _VP]),
     "ls_upwind_step_f16s": (_I32, [_VP, _F32, _VP, _G, _F32, _F32, _VP, _VP, _I32, _VP, _VP, _I64,
                                    _VP]),
+    "ls_band_rebuild_f32": (_I32, [_VP, _G, _F32, _VP, _VP, _VP, _I64, _VP, _VP, _I64, _VP]),
+    "ls_band_rebuild_f64": (_I32, [_VP, _G, _F64, _VP, _VP, _VP, _I64, _VP, _VP, _I64, _VP]),
+    "ls_band_rebuild_f16s": (_I32, [_VP, _F32, _G, _F32, _VP, _VP, _VP, _I64, _VP, _VP, _I64,
+                                    _VP]),
     "ls_band_run_f32": (_I32, [_VP, _VP, _G, _F32, _F32, _F32, _I32, _I32, _VP, _I64, _VP, _VP,
-                               _VP, _I64, _VP]),
+                               _VP, _VP, _I64, _VP]),
     "ls_band_run_f64": (_I32, [_VP, _VP, _G, _F64, _F64, _F64, _I32, _I32, _VP, _I64, _VP, _VP,
-                               _VP, _I64, _VP]),
+                               _VP, _VP, _I64, _VP]),
     "ls_band_run_f16s": (_I32, [_VP, _F32, _VP, _G, _F32, _F32, _F32, _I32, _I32, _VP, _I64, _VP,
-                                _VP, _VP, _I64, _VP]),
+                                _VP, _VP, _VP, _I64, _VP]),
+    "ls_set_tuning": (_I32, [ctypes.c_void_p]),
+    "ls_get_tuning": (_I32, [ctypes.c_void_p]),
+    "ls_upwind_launch_info": (_I32, [_G, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                     ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "ls_stats_enable": (_I32, [_I32]),
+    "ls_copy_f32": (_I32, [_VP, _VP, _I64, _VP]),
     "ls_stats_read": (_I32, [_I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                              ctypes.POINTER(_F64)]),
 }
@@ -181,26 +194,52 @@ def ls_upwind_step_f16s(phi_h, scale, F, g, dx, dt, tiles, ntiles_dev, nsteps, s
                                             _ptr(workspace), workspace_bytes, _stream(stream)))
 
 
+def ls_band_rebuild_f32(phi, g, gamma, prev_tiles, prev_ntiles_dev, tiles, capacity, ntiles_dev,
+                        workspace, workspace_bytes, stream=None):
+    return _check(lib().ls_band_rebuild_f32(_ptr(phi), _g(g), gamma, _ptr(prev_tiles),
+                                            _ptr(prev_ntiles_dev), _ptr(tiles), capacity,
+                                            _ptr(ntiles_dev), _ptr(workspace), workspace_bytes,
+                                            _stream(stream)))
+
+
+def ls_band_rebuild_f64(phi, g, gamma, prev_tiles, prev_ntiles_dev, tiles, capacity, ntiles_dev,
+                        workspace, workspace_bytes, stream=None):
+    return _check(lib().ls_band_rebuild_f64(_ptr(phi), _g(g), gamma, _ptr(prev_tiles),
+                                            _ptr(prev_ntiles_dev), _ptr(tiles), capacity,
+                                            _ptr(ntiles_dev), _ptr(workspace), workspace_bytes,
+                                            _stream(stream)))
+
+
+def ls_band_rebuild_f16s(phi_h, scale, g, gamma, prev_tiles, prev_ntiles_dev, tiles, capacity,
+                         ntiles_dev, workspace, workspace_bytes, stream=None):
+    return _check(lib().ls_band_rebuild_f16s(_ptr(phi_h), scale, _g(g), gamma, _ptr(prev_tiles),
+                                             _ptr(prev_ntiles_dev), _ptr(tiles), capacity,
+                                             _ptr(ntiles_dev), _ptr(workspace), workspace_bytes,
+                                             _stream(stream)))
+
+
 def ls_band_run_f32(phi, F, g, dx, dt, gamma, nsteps, window, tiles, capacity, ntiles_dev,
-                    scratch, workspace, workspace_bytes, stream=None):
+                    tile_steps_dev, scratch, workspace, workspace_bytes, stream=None):
     return _check(lib().ls_band_run_f32(_ptr(phi), _ptr(F), _g(g), dx, dt, gamma, nsteps, window,
-                                        _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(scratch),
-                                        _ptr(workspace), workspace_bytes, _stream(stream)))
+                                        _ptr(tiles), capacity, _ptr(ntiles_dev),
+                                        _ptr(tile_steps_dev), _ptr(scratch), _ptr(workspace),
+                                        workspace_bytes, _stream(stream)))
 
 
 def ls_band_run_f64(phi, F, g, dx, dt, gamma, nsteps, window, tiles, capacity, ntiles_dev,
-                    scratch, workspace, workspace_bytes, stream=None):
+                    tile_steps_dev, scratch, workspace, workspace_bytes, stream=None):
     return _check(lib().ls_band_run_f64(_ptr(phi), _ptr(F), _g(g), dx, dt, gamma, nsteps, window,
-                                        _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(scratch),
-                                        _ptr(workspace), workspace_bytes, _stream(stream)))
+                                        _ptr(tiles), capacity, _ptr(ntiles_dev),
+                                        _ptr(tile_steps_dev), _ptr(scratch), _ptr(workspace),
+                                        workspace_bytes, _stream(stream)))
 
 
 def ls_band_run_f16s(phi_h, scale, F, g, dx, dt, gamma, nsteps, window, tiles, capacity,
-                     ntiles_dev, scratch, workspace, workspace_bytes, stream=None):
+                     ntiles_dev, tile_steps_dev, scratch, workspace, workspace_bytes, stream=None):
     return _check(lib().ls_band_run_f16s(_ptr(phi_h), scale, _ptr(F), _g(g), dx, dt, gamma,
                                          nsteps, window, _ptr(tiles), capacity, _ptr(ntiles_dev),
-                                         _ptr(scratch), _ptr(workspace), workspace_bytes,
-                                         _stream(stream)))
+                                         _ptr(tile_steps_dev), _ptr(scratch), _ptr(workspace),
+                                         workspace_bytes, _stream(stream)))
 
 
 def ls_stats_enable(on):
@@ -213,3 +252,30 @@ def ls_stats_read(which):
     _check(lib().ls_stats_read(which, ctypes.byref(launches), ctypes.byref(timed),
                                ctypes.byref(ms)))
     return launches.value, timed.value, ms.value
+
+
+def ls_set_tuning(run_width=0, blocks_per_cu=0):
+    t = ls_tuning(int(run_width), int(blocks_per_cu))
+    return _check(lib().ls_set_tuning(ctypes.byref(t)))
+
+
+def ls_get_tuning():
+    t = ls_tuning()
+    _check(lib().ls_get_tuning(ctypes.byref(t)))
+    return t.run_width, t.blocks_per_cu
+
+
+PRECISION_ID = {"f32": 0, "f64": 1, "f16s": 2}
+
+
+def ls_upwind_launch_info(g, precision):
+    """dict(blocks, lds_bytes, run_tiles, blocks_per_cu_limit) for grid g."""
+    out = [_I32() for _ in range(4)]
+    _check(lib().ls_upwind_launch_info(_g(g), PRECISION_ID.get(precision, precision),
+                                       *[ctypes.byref(v) for v in out]))
+    return dict(zip(("blocks", "lds_bytes", "run_tiles", "blocks_per_cu_limit"),
+                    (v.value for v in out)))
+
+
+def ls_copy_f32(dst, src, n, stream=None):
+    return _check(lib().ls_copy_f32(_ptr(dst), _ptr(src), int(n), _stream(stream)))

@@ -1,0 +1,112 @@
+"""Summaries of rocprofv3 results (measurement support, not part of the method).
+
+``python -m paper_1612_04040_amd.profiling trace DB...`` prints per-kernel
+dispatch counts and mean durations from rocprofv3 ``--kernel-trace`` result
+databases; ``counters DB...`` prints per-kernel mean counter values from
+``--pmc`` runs.  ``traffic`` combines a FETCH_SIZE and a WRITE_SIZE run into
+HBM bytes per dispatch, each counter scaled by what it reads for the plain
+dword copy kernel (``ls::copy_f32_kernel``, 1 GiB read and 1 GiB written in
+the bench's calibration pass), and records them in profiles/traffic.json
+under the kernel source digest they were taken on.
+"""
+import argparse
+import collections
+import json
+import os
+import sqlite3
+import sys
+
+CALIB_KERNEL = "ls::copy_f32_kernel"
+CALIB_BYTES = 1 << 30
+
+
+def _rows(db, query):
+    con = sqlite3.connect(db)
+    try:
+        return con.execute(query).fetchall()
+    finally:
+        con.close()
+
+
+def short_name(k):
+    k = k.replace("void ", "")
+    return k.split("(")[0]
+
+
+def kernel_durations(db):
+    """{kernel: (dispatches, mean duration in us)} from a kernel-trace database."""
+    rows = _rows(db, "select name, start, end from kernels")
+    acc = collections.defaultdict(list)
+    for name, start, end in rows:
+        acc[short_name(name)].append((end - start) / 1e3)
+    return {k: (len(v), sum(v) / len(v)) for k, v in acc.items()}
+
+
+def kernel_counters(db):
+    """{(kernel, counter): (dispatches, mean value)} from a --pmc database."""
+    rows = _rows(db, "select kernel_name, counter_name, value from counters_collection")
+    acc = collections.defaultdict(list)
+    for k, c, v in rows:
+        acc[(short_name(k), c)].append(v)
+    return {key: (len(v), sum(v) / len(v)) for key, v in acc.items()}
+
+
+def traffic(fetch_db, write_db, kernel):
+    """HBM bytes per dispatch of `kernel`, calibrated by the copy kernel."""
+    f = kernel_counters(fetch_db)
+    w = kernel_counters(write_db)
+    f_cal = f[(CALIB_KERNEL, "FETCH_SIZE")][1] * 1024.0
+    w_cal = w[(CALIB_KERNEL, "WRITE_SIZE")][1] * 1024.0
+    rf, wf = CALIB_BYTES / f_cal, CALIB_BYTES / w_cal
+    fk = f[(kernel, "FETCH_SIZE")][1] * 1024.0 * rf
+    wk = w[(kernel, "WRITE_SIZE")][1] * 1024.0 * wf
+    return {"read_bytes": fk, "write_bytes": wk, "bytes_per_launch": fk + wk,
+            "fetch_scale": rf, "write_scale": wf}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("db", nargs="+")
+    c = sub.add_parser("counters")
+    c.add_argument("db", nargs="+")
+    tr = sub.add_parser("traffic")
+    tr.add_argument("fetch_db")
+    tr.add_argument("write_db")
+    tr.add_argument("--kernel", required=True, help="kernel name prefix")
+    tr.add_argument("--key", required=True, help="kernel/workload key in traffic.json")
+    tr.add_argument("--digest", required=True, help="kernel source digest of the run")
+    tr.add_argument("--out", default=os.path.join(os.path.dirname(os.path.dirname(
+        os.path.abspath(__file__))), "profiles", "traffic.json"))
+    a = ap.parse_args(argv)
+    if a.cmd == "trace":
+        for db in a.db:
+            for k, (n, us) in sorted(kernel_durations(db).items(), key=lambda kv: -kv[1][0] * kv[1][1]):
+                print(f"{k[:100]:100s} dispatches={n:6d} mean_us={us:10.3f}")
+    elif a.cmd == "counters":
+        for db in a.db:
+            for (k, cn), (n, v) in sorted(kernel_counters(db).items()):
+                print(f"{k[:100]:100s} {cn:20s} dispatches={n:6d} mean={v:16.1f}")
+    else:
+        names = {k for k, _ in kernel_counters(a.fetch_db)}
+        match = sorted(n for n in names if n.startswith(a.kernel))
+        if not match:
+            print(f"no kernel starting with {a.kernel}", file=sys.stderr)
+            return 1
+        rec = traffic(a.fetch_db, a.write_db, match[0])
+        rec["kernel"] = match[0]
+        rec["source_digest"] = a.digest
+        data = {}
+        if os.path.exists(a.out):
+            with open(a.out) as fh:
+                data = json.load(fh)
+        data[a.key] = rec
+        with open(a.out, "w") as fh:
+            json.dump(data, fh, indent=1, sort_keys=True)
+        print(json.dumps(rec))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -28,6 +28,11 @@ def test_header_declares_the_bound_symbols():
     assert declared_symbols() == ls.exported_symbols()
 
 
+def test_binding_wraps_every_declared_symbol():
+    for name in declared_symbols():
+        assert callable(getattr(ls, name, None)), name
+
+
 def test_library_exports_every_declared_symbol():
     handle = ctypes.CDLL(ls.LIB_PATH)
     for name in declared_symbols():
@@ -144,9 +149,34 @@ def test_run_errors():
     g = ls.grid((32, 32, 32))
     cap = ls.ls_grid_tiles(g)
     ws = ls.ls_workspace_bytes(g)
-    base = [FAKE, FAKE, g, 0.1, 0.05, 0.2, 10, 0, FAKE, cap, FAKE, FAKE * 2, FAKE * 256, ws, 0]
+    base = [FAKE, FAKE, g, 0.1, 0.05, 0.2, 10, 0, FAKE, cap, FAKE, None, FAKE * 2, FAKE * 256, ws,
+            0]
     assert _status(ls.ls_band_run_f32, *base) == ls.LS_ERR_ARG  # window 0
     bad = list(base)
     bad[6] = -5
     bad[7] = 10
     assert _status(ls.ls_band_run_f32, *bad) == ls.LS_ERR_ARG  # nsteps < 0
+    bad = list(base)
+    bad[7] = 10
+    bad[9] = cap - 1
+    assert _status(ls.ls_band_run_f32, *bad) == ls.LS_ERR_CAPACITY
+    bad[9] = cap
+    bad[5] = float("nan")
+    assert _status(ls.ls_band_run_f32, *bad) == ls.LS_ERR_ARG
+
+
+def test_rebuild_errors():
+    g = ls.grid((32, 32, 32))
+    cap = ls.ls_grid_tiles(g)
+    ws = ls.ls_workspace_bytes(g)
+    base = [FAKE, g, 0.1, FAKE * 3, FAKE * 4, FAKE * 5, cap, FAKE * 6, FAKE * 256, ws, 0]
+    for i, status in [(3, ls.LS_ERR_ARG), (4, ls.LS_ERR_ARG), (5, ls.LS_ERR_ARG)]:
+        bad = list(base)
+        bad[i] = None
+        assert _status(ls.ls_band_rebuild_f32, *bad) == status
+    bad = list(base)
+    bad[3] = bad[5]  # previous list aliases the new one
+    assert _status(ls.ls_band_rebuild_f32, *bad) == ls.LS_ERR_ARG
+    bad = list(base)
+    bad[6] = 3
+    assert _status(ls.ls_band_rebuild_f32, *bad) == ls.LS_ERR_CAPACITY

@@ -89,11 +89,52 @@ def test_three_spheres_512_f32_200_steps():
     bound = wl.nsteps * (0.5 * np.spacing(np.float32(pmax)) + 4 * EPS32 * 0.5 * wl.dx)
     assert err.max() <= bound, (err.max(), bound)
 
-    # the one-call driver gives the same bits
+    # the one-call driver (incremental rebuilds) gives the same bits and counts
     pd2 = to_dev(wl.phi)
-    bg.run(pd2, fd, wl.dx, wl.dt, float(g32), wl.nsteps, wl.window)
+    acc = torch.zeros(1, dtype=torch.int64, device=dev())
+    bg.run(pd2, fd, wl.dx, wl.dt, float(g32), wl.nsteps, wl.window, tile_steps=acc)
     assert host(pd2).tobytes() == got.tobytes()
     assert bg.band_list().numpy().tolist() == lists[-1].tolist()
+    assert int(acc.item()) == sum(int(x.size) for x in lists) * wl.window
+
+
+@pytest.mark.timeout(600)
+def test_incremental_rebuild_equals_full_build():
+    """Window by window on the 512^3 workload: the rebuild from the previous
+    band equals the full scan, bit for bit (and the step plan it leaves is
+    the one the steps use)."""
+    wl = W.three_spheres_f32(512, 60)
+    g32 = float(np.float32(wl.gamma))
+    full = BandGrid((512,) * 3, wl.tile, "f32")
+    inc = BandGrid((512,) * 3, wl.tile, "f32")
+    pd, fd = to_dev(wl.phi), to_dev(wl.F)
+    inc.build(pd, g32, dilate=True)
+    for w in range(wl.nsteps // wl.window):
+        full.build(pd, g32, dilate=True)
+        if w > 0:
+            inc.rebuild(pd, g32, prev_t, prev_n)
+        assert inc.band_list().numpy().tolist() == full.band_list().numpy().tolist(), w
+        prev_t, prev_n = inc.tiles.clone(), inc.ntiles.clone()
+        full.step(pd, fd, wl.dx, wl.dt, wl.window)
+
+
+def test_rebuild_random_fields():
+    """A random band whose complement holds no tube point: rebuild == build."""
+    rng = np.random.default_rng(12)
+    dims, tile = (67, 45, 33), (8, 8, 8)
+    nz, ny, nx = 33, 45, 67
+    gamma = 0.25
+    phi = np.where(rng.random((nz, ny, nx)) < 0.5, 1.0, -1.0).astype(np.float32)
+    phi[10:14, 20:22, 30:40] = rng.uniform(-0.3, 0.3, (4, 2, 10))  # a small tube
+    bg = BandGrid(dims, tile, "f32")
+    pd = to_dev(phi)
+    bg.build(pd, gamma, dilate=True)
+    prev_t, prev_n = bg.tiles.clone(), bg.ntiles.clone()
+    # move values only inside the band, as a step would
+    bg.step(pd, to_dev(rng.uniform(-1, 1, phi.shape).astype(np.float32)), 0.05, 0.01, 3)
+    bg.rebuild(pd, gamma, prev_t, prev_n)
+    got = bg.band_list().numpy()
+    assert got.tolist() == oracle.band_tiles(host(pd), tile, np.float32(gamma), True).tolist()
 
 
 def test_torus_f16s_reduced():
