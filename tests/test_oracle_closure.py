@@ -1,0 +1,116 @@
+"""Pins of the FP64 closure reference.
+
+* the convolution equals scipy.ndimage.correlate (zero padding) channel by
+  channel, a library routine that shares no code with it;
+* every parameter gradient matches central finite differences (h = 1e-6);
+* the restriction reproduces linear fields exactly at the coarse centres and
+  averages the 2x2x2 fine points around them;
+* with the last layer zero the corrected step is the plain step, bit for bit;
+* Adam's first step moves every parameter by lr * sign(gradient).
+"""
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle
+from oracle import closure as CL
+from paper_1612_04040_amd import workloads as W
+
+
+def test_conv3_equals_scipy_correlate():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((3, 5, 6, 7))
+    w = rng.standard_normal((4, 3, 3, 3, 3))
+    b = rng.standard_normal(4)
+    got = CL.conv3(x, w, b)
+    for o in range(4):
+        want = sum(ndimage.correlate(x[c], w[o, c], mode="constant", cval=0.0)
+                   for c in range(3)) + b[o]
+        assert np.allclose(got[o], want, atol=1e-12)
+
+
+def _small_problem(seed=1, shape=(6, 5, 7)):
+    rng = np.random.default_rng(seed)
+    feat = rng.standard_normal((3,) + shape)
+    params = CL.init_params(rng, scale=0.3)
+    params["w2"] = rng.standard_normal(params["w2"].shape) * 0.2  # non-zero last layer
+    for k in ("b0", "b1", "b2"):
+        params[k] = rng.standard_normal(params[k].shape) * 0.1
+    rstar = rng.standard_normal(shape) * 0.1
+    mask = rng.random(shape) < 0.7
+    return params, feat, rstar, mask
+
+
+@pytest.mark.parametrize("name", ["w0", "b0", "w1", "b1", "w2", "b2"])
+def test_gradients_match_finite_differences(name):
+    params, feat, rstar, mask = _small_problem()
+    _, g = CL.loss_and_grad(params, feat, rstar, mask)
+    rng = np.random.default_rng(3)
+    flat = params[name].reshape(-1)
+    idx = rng.choice(flat.size, size=min(12, flat.size), replace=False)
+    h = 1e-6
+    for i in idx:
+        old = flat[i]
+        flat[i] = old + h
+        lp, _ = CL.loss_and_grad(params, feat, rstar, mask)
+        flat[i] = old - h
+        lm, _ = CL.loss_and_grad(params, feat, rstar, mask)
+        flat[i] = old
+        fd = (lp - lm) / (2 * h)
+        an = g[name].reshape(-1)[i]
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (name, i, fd, an)
+
+
+def test_restriction_closed_forms():
+    n = 32
+    dx = 1.0 / n
+    fine = W.plane((n, n, n), dx, (0.3, -0.5, 0.8), 0.1)
+    coarse = CL.restrict4(fine)
+    want = W.plane((n // 4,) * 3, 4 * dx, (0.3, -0.5, 0.8), 0.1)
+    assert np.max(np.abs(coarse - want)) < 1e-14
+    rng = np.random.default_rng(2)
+    f = rng.standard_normal((8, 8, 8))
+    c = CL.restrict4(f)
+    assert c.shape == (2, 2, 2)
+    assert np.isclose(c[1, 0, 1], f[5:7, 1:3, 5:7].mean())
+
+
+def test_zero_network_is_the_plain_step():
+    n = 32
+    wl = W.three_spheres_f32(n, 1)
+    phi = wl.phi.astype(np.float64)
+    band = oracle.band_tiles(wl.phi, (8, 8, 8), np.float32(wl.gamma), True)
+    active = oracle.band_tiles(wl.phi, (8, 8, 8), np.float32(wl.gamma), False)
+    params = CL.init_params(np.random.default_rng(0))
+    out, fb = CL.closure_step(params, phi, wl.F, wl.dx, wl.dt, wl.gamma, 0.5, band, active)
+    plain = oracle.upwind_steps(phi, wl.F, wl.dx, wl.dt, band, 1)
+    assert fb == 0
+    assert out.tobytes() == plain.tobytes()
+
+
+def test_fallback_on_large_correction():
+    n = 32
+    wl = W.three_spheres_f32(n, 1)
+    phi = wl.phi.astype(np.float64)
+    band = oracle.band_tiles(wl.phi, (8, 8, 8), np.float32(wl.gamma), True)
+    active = oracle.band_tiles(wl.phi, (8, 8, 8), np.float32(wl.gamma), False)
+    params = CL.init_params(np.random.default_rng(0))
+    params["b2"][:] = 0.75  # |r| > 1/2 everywhere: every active tile falls back
+    out, fb = CL.closure_step(params, phi, wl.F, wl.dx, wl.dt, wl.gamma, 0.5, band, active)
+    plain = oracle.upwind_steps(phi, wl.F, wl.dx, wl.dt, band, 1)
+    assert fb == len(active)
+    assert out.tobytes() == plain.tobytes()
+    params["b2"][:] = 0.25  # accepted everywhere: plain + dx/4 on the active tiles
+    out, fb = CL.closure_step(params, phi, wl.F, wl.dx, wl.dt, wl.gamma, 0.5, band, active)
+    assert fb == 0
+    diff = out - plain
+    assert np.isclose(diff.max(), 0.25 * wl.dx) and np.count_nonzero(diff) == len(active) * 512
+
+
+def test_adam_first_step_is_signed_lr():
+    rng = np.random.default_rng(4)
+    params = {"w": rng.standard_normal(10)}
+    grads = {"w": rng.standard_normal(10)}
+    before = params["w"].copy()
+    CL.adam_step(params, grads, {}, lr=1e-3)
+    assert np.allclose(params["w"] - before, -1e-3 * np.sign(grads["w"]), rtol=1e-4)
