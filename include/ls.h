@@ -178,6 +178,65 @@ int ls_band_run_f16s(uint16_t *phi_h, float scale, const float *F, const ls_grid
                      uint16_t *scratch, void *workspace, int64_t workspace_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Batches: many grids of uneven size, advanced in lockstep by the same
+ * launches (the narrow-band driver above, applied to every grid at once).
+ *
+ * Each grid lives in the caller's phi / F / scratch buffers (FP32) at element
+ * `offset`, x fastest as above; the grids must not overlap.  The tile shape of
+ * a grid is its own (typically picked per size by an autotuner); it must be
+ * one of the shapes the batched step kernel is compiled for: 8x8x8, 16x4x4,
+ * 32x4x4, 16x8x8 or 4x4x4 with the default run width, and the other shapes
+ * ls_upwind_launch_info reports as having a compiled fast kernel.
+ *
+ * The grids' tile grids are concatenated, in an order ls_batch_layout gives,
+ * into one global tile space; band lists of a batch hold global tile ids
+ * (ascending), grid i owning [tile_base[i], tile_base[i] + its tile count).
+ * ------------------------------------------------------------------------- */
+typedef struct ls_instance {
+    ls_grid grid;     /* dims and band tile shape */
+    int64_t offset;   /* first element of this grid in phi, F and scratch */
+    float dx, dt;     /* spacing and time step */
+    float gamma;      /* band half-width */
+    int32_t reserved; /* 0 */
+} ls_instance;
+
+/* Workspace bytes of a batch (device memory, caller-owned). */
+int64_t ls_batch_workspace_bytes(const ls_instance *inst, int n);
+/* Global tile base of every grid (host array of n) and the total tile count. */
+int ls_batch_layout(const ls_instance *inst, int n, int64_t *tile_base, int64_t *total_tiles);
+/* Uploads the grid descriptors into the workspace (synchronises `stream`);
+ * call once before ls_batch_run_f32 with the same instance array. */
+int ls_batch_setup(const ls_instance *inst, int n, void *workspace, int64_t workspace_bytes,
+                   void *stream);
+/* The narrow-band driver for every grid of the batch: per window one band
+ * build of all grids (a full scan for the first window, the exact incremental
+ * rescan of the previous bands afterwards) and `window` steps of all grids;
+ * equal, grid by grid, to ls_band_run_f32 on each grid alone with its tile
+ * shape, bit for bit.  tile_steps_dev as in ls_band_run_f32 (summed over the
+ * grids).  Asynchronous, no host synchronisation: capturable in a HIP graph. */
+int ls_batch_run_f32(const ls_instance *inst, int n, float *phi, const float *F, float *scratch,
+                     int nsteps, int window, int64_t *tile_steps_dev, void *workspace,
+                     int64_t workspace_bytes, void *stream);
+/* Device pointers (inside the workspace) to the batch's last band list and
+ * its length. */
+int ls_batch_band(const ls_instance *inst, int n, void *workspace, int64_t workspace_bytes,
+                  const int32_t **tiles_dev, const int32_t **ntiles_dev);
+
+/* ---------------------------------------------------------------------------
+ * HIP graphs: capture the library calls issued on `stream` between
+ * ls_graph_begin and ls_graph_end into an executable graph, replayed with
+ * ls_graph_launch.  `stream` must not be the NULL stream.  A replay repeats
+ * exactly the captured launches with the captured arguments (pointers and
+ * scalars); the band lists, counts and work items they use live on the
+ * device, so a captured window sequence needs no host involvement.  Do not
+ * enable kernel timing while capturing.  *graph is an opaque handle.
+ * ------------------------------------------------------------------------- */
+int ls_graph_begin(void *stream);
+int ls_graph_end(void *stream, void **graph);
+int ls_graph_launch(void *graph, void *stream);
+int ls_graph_destroy(void *graph);
+
+/* ---------------------------------------------------------------------------
  * Launch tuning (process-wide; used by the autotuner, not part of the method).
  *
  * run_width: target width in grid points of one work item of the band step
@@ -221,6 +280,87 @@ int ls_stats_read(int which, int64_t *launches, int64_t *timed, double *total_ms
  * access width of the band step): the reference kernel against which the
  * hardware traffic counters are calibrated.  Device pointers, n >= 0. */
 int ls_copy_f32(float *dst, const float *src, int64_t n, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned closure of the coarse first-order step (an addition to the method:
+ * the paper has no network; the step it corrects is Eq. 3-5 on the band of
+ * Eq. 6 and Eq. 11).
+ *
+ * A 3-layer 3x3x3 convolutional network, channels 3 -> 16 -> 16 -> 1 with
+ * SiLU after the first two layers and zero padding outside the grid, maps
+ * per-point features of the coarse field
+ *     c0 = clip(phi / gamma, -2, 2),  c1 = F / fmax,  c2 = (plain - phi) / dx
+ * (plain = phi after one plain step, Eq. 3) to a correction r, and the
+ * corrected step is
+ *     phi^{n+1} = plain + dx * r    on the active tiles A (Eq. 6 in tile form),
+ *     phi^{n+1} = plain             elsewhere in the band U,
+ * except that an active tile any of whose r is non-finite or above 1/2 in
+ * magnitude takes the plain step (a fallback, counted).  Activations outside
+ * U count as zero; since A lies one tile inside U and the network sees three
+ * points around a point, r on A equals the network's value with no band.
+ * Weights and activations are BF16 on the matrix cores with FP32
+ * accumulation; the parameters are an FP32 master vector.
+ *
+ * Parameters: a flat FP32 vector of ls_closure_param_count() = 8673 values,
+ * in the order w0 (16,3,3,3,3), b0 (16), w1 (16,16,3,3,3), b1 (16),
+ * w2 (1,16,3,3,3), b2 (1); each weight is indexed (out, in, dz, dy, dx) and
+ * the layer is the cross-correlation
+ *     out[o](z,y,x) = b[o] + sum_{c,dz,dy,dx} w[o,c,dz,dy,dx] in[c](z+dz-1, y+dy-1, x+dx-1).
+ *
+ * Grid: FP32, 8x8x8 tiles, every dimension a multiple of 8.  Every closure
+ * call takes, besides the band workspace of ls_workspace_bytes, a closure
+ * workspace of ls_closure_workspace_bytes(g) bytes (device, caller-owned,
+ * 256-byte aligned; no initialisation needed), and the caller's band list
+ * buffer (tiles, capacity >= ls_grid_tiles, ntiles_dev) into which U is
+ * built from the call's phi (band half-width gamma, 26-neighbour dilation).
+ * fmax > 0 is the feature scale of F (the caller's max |F|).
+ * ------------------------------------------------------------------------- */
+int64_t ls_closure_param_count(void);
+int64_t ls_closure_workspace_bytes(const ls_grid *g);
+
+/* Coarse field of a fine one, 4x in every axis: coarse point (I,J,K) is the
+ * mean of the 2x2x2 fine points 4I+1..4I+2 (likewise J, K), which surround
+ * the coarse cell centre on a cell-centred grid.  fine_grid gives the fine
+ * dims (multiples of 4); coarse holds (nx/4)(ny/4)(nz/4) floats. */
+int ls_restrict4_f32(const float *fine, const ls_grid *fine_grid, float *coarse, void *stream);
+
+/* One network evaluation at phi: builds A and U from phi, the plain step into
+ * `plain` (dense, may be NULL) and r into `r` (dense; zero outside A; may be
+ * NULL).  phi is not modified.  scratch: one grid of FP32. */
+int ls_closure_forward_f32(const float *phi, const float *F, const ls_grid *g, float dx, float dt,
+                           float gamma, float fmax, const float *params, float *r, float *plain,
+                           int32_t *tiles, int64_t capacity, int32_t *ntiles_dev, float *scratch,
+                           void *ws, int64_t ws_bytes, void *cws, int64_t cws_bytes,
+                           void *stream);
+
+/* Training loss and gradient at phi toward target (the fine solution one
+ * coarse step later, restricted): loss = mean over the points of A of
+ * (r - r*)^2 with r* = (target - plain) / dx, written to *loss_dev (may be
+ * NULL); grad (8673 floats, overwritten) is d loss / d params, computed by
+ * the backward kernels (data gradients through the transposed convolutions,
+ * weight gradients as per-tile partial sums reduced in tile order). */
+int ls_closure_backward_f32(const float *phi, const float *target, const float *F,
+                            const ls_grid *g, float dx, float dt, float gamma, float fmax,
+                            const float *params, float *grad, float *loss_dev, int32_t *tiles,
+                            int64_t capacity, int32_t *ntiles_dev, float *scratch, void *ws,
+                            int64_t ws_bytes, void *cws, int64_t cws_bytes, void *stream);
+
+/* One Adam update (Kingma and Ba) of n FP32 parameters with step count t >= 1:
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps). */
+int ls_adam_step(float *params, const float *grad, float *m, float *v, int64_t n, float lr,
+                 float beta1, float beta2, float eps, int t, void *stream);
+
+/* The corrected narrow-band driver: per window of `window` steps, A and U are
+ * built from the current phi, then every step is the plain step on U plus the
+ * correction on A (with the per-tile fallback).  *fallbacks_dev (int32,
+ * caller-zeroed) accumulates the fallback count.  On return phi holds the
+ * result; the band list of the last window is in tiles / ntiles_dev. */
+int ls_closure_run_f32(float *phi, const float *F, const ls_grid *g, float dx, float dt,
+                       float gamma, float fmax, const float *params, int nsteps, int window,
+                       int32_t *tiles, int64_t capacity, int32_t *ntiles_dev,
+                       int32_t *fallbacks_dev, float *scratch, void *ws, int64_t ws_bytes,
+                       void *cws, int64_t cws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -245,8 +245,9 @@ __global__ __launch_bounds__(kBlock) void band_dilate_kernel(const uint8_t *__re
     u[t] = hit ? 1 : 0;
 }
 
-// Tile flags of the listed tiles only (the incremental rebuild): one block per
-// listed tile at a time, a block-wide OR of |phi| < gamma over its points.
+// Tile flags of the listed tiles only (the incremental rebuild): one wave per
+// listed tile at a time; every lane tests its share of the tile's points and
+// the wave ORs the results with a ballot.
 template <class S>
 __global__ __launch_bounds__(kBlock) void band_flag_list_kernel(
     const S *__restrict__ phi, int nx, int ny, int nz, int tx, int ty, int tz, int ntx, int nty,
@@ -254,22 +255,26 @@ __global__ __launch_bounds__(kBlock) void band_flag_list_kernel(
     const int32_t *__restrict__ list, const int32_t *__restrict__ list_count,
     uint8_t *__restrict__ a_flags) {
     const int n = min(*list_count, ntiles_cap);
-    for (int p = blockIdx.x; p < n; p += gridDim.x) {
+    const int lane = threadIdx.x & 63;
+    const int waves = gridDim.x * (kBlock / 64);
+    for (int p = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); p < n; p += waves) {
         const int t = list[p];
-        if (t < 0 || t >= ntiles_cap) continue;  // uniform
+        if (t < 0 || t >= ntiles_cap) continue;  // uniform per wave
         const int ti = t % ntx, r = t / ntx;
         const int tj = r % nty, tk = r / nty;
         const int x0 = ti * tx, y0 = tj * ty, z0 = tk * tz;
         const int W = min(tx, nx - x0), H = min(ty, ny - y0), D = min(tz, nz - z0);
+        const int npts = W * H * D;
         bool hit = false;
-        for (int q = threadIdx.x; q < W * H * D; q += kBlock) {
+#pragma unroll 8
+        for (int q = lane; q < npts; q += 64) {
             const int lx = q % W, rr = q / W;
             const int ly = rr % H, lz = rr / H;
             const int64_t gi = (static_cast<int64_t>(z0 + lz) * ny + (y0 + ly)) * nx + x0 + lx;
             hit |= fabs(Codec<S>::load(phi[gi], scale)) < gamma;
         }
-        hit = __syncthreads_or(hit);
-        if (threadIdx.x == 0) a_flags[t] = hit ? 1 : 0;
+        const bool any = __ballot(hit) != 0;
+        if (lane == 0) a_flags[t] = any ? 1 : 0;
     }
 }
 
@@ -371,11 +376,16 @@ int fill_zero(uint8_t *p, int64_t bytes, hipStream_t stream) {
     return LS_OK;
 }
 
+// With flags_valid the workspace's tile flags already equal the A of the
+// build that produced prev_tiles (the driver's case: every build writes A, and
+// A lies inside the band it dilates to), so they need no clearing: rescanning
+// the previous band overwrites every flag that can change.
 template <class S>
 int band_rebuild(const S *phi, typename Codec<S>::C scale, const ls_grid *grid,
                  typename Codec<S>::C gamma, const int32_t *prev_tiles,
                  const int32_t *prev_ntiles_dev, int32_t *tiles, int64_t capacity,
-                 int32_t *ntiles_dev, void *workspace, int64_t ws_bytes, void *stream_) {
+                 int32_t *ntiles_dev, void *workspace, int64_t ws_bytes, void *stream_,
+                 bool flags_valid) {
     Geom g;
     int rc = band_args(phi, grid, gamma, 1, tiles, capacity, ntiles_dev, workspace, ws_bytes, &g);
     if (rc != LS_OK) return rc;
@@ -391,11 +401,11 @@ int band_rebuild(const S *phi, typename Codec<S>::C scale, const ls_grid *grid,
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     const Workspace w = workspace_layout(g);
     uint8_t *ws = static_cast<uint8_t *>(workspace);
-    if ((rc = fill_zero(ws + w.a_flags, g.ntiles, stream)) != LS_OK) return rc;
+    if (!flags_valid && (rc = fill_zero(ws + w.a_flags, g.ntiles, stream)) != LS_OK) return rc;
     DeviceInfo di;
     if ((rc = device_info(&di)) != LS_OK) return rc;
     const unsigned blocks =
-        static_cast<unsigned>(std::min<int64_t>(g.ntiles, int64_t(di.cus) * 16));
+        static_cast<unsigned>(std::min<int64_t>(cdiv64(g.ntiles, kBlock / 64), int64_t(di.cus) * 16));
     int64_t slot;
     if ((rc = stats_before(LS_KERNEL_BAND_FLAG, stream, &slot)) != LS_OK) return rc;
     hipLaunchKernelGGL(band_flag_list_kernel<S>, dim3(blocks), dim3(kBlock), 0, stream, phi, g.nx,
@@ -414,13 +424,13 @@ template int band_build<uint16_t>(const uint16_t *, float, const ls_grid *, floa
                                   int32_t *, int64_t, int32_t *, void *, int64_t, void *);
 template int band_rebuild<float>(const float *, float, const ls_grid *, float, const int32_t *,
                                  const int32_t *, int32_t *, int64_t, int32_t *, void *, int64_t,
-                                 void *);
+                                 void *, bool);
 template int band_rebuild<double>(const double *, double, const ls_grid *, double,
                                   const int32_t *, const int32_t *, int32_t *, int64_t, int32_t *,
-                                  void *, int64_t, void *);
+                                  void *, int64_t, void *, bool);
 template int band_rebuild<uint16_t>(const uint16_t *, float, const ls_grid *, float,
                                     const int32_t *, const int32_t *, int32_t *, int64_t,
-                                    int32_t *, void *, int64_t, void *);
+                                    int32_t *, void *, int64_t, void *, bool);
 
 }  // namespace ls
 
@@ -448,7 +458,8 @@ int ls_band_rebuild_f32(const float *phi, const ls_grid *g, float gamma,
                         int64_t workspace_bytes, void *stream) {
     ls::clear_error();
     return ls::band_rebuild<float>(phi, 1.0f, g, gamma, prev_tiles, prev_ntiles_dev, tiles,
-                                   capacity, ntiles_dev, workspace, workspace_bytes, stream);
+                                   capacity, ntiles_dev, workspace, workspace_bytes, stream,
+                                   false);
 }
 
 int ls_band_rebuild_f64(const double *phi, const ls_grid *g, double gamma,
@@ -457,7 +468,8 @@ int ls_band_rebuild_f64(const double *phi, const ls_grid *g, double gamma,
                         int64_t workspace_bytes, void *stream) {
     ls::clear_error();
     return ls::band_rebuild<double>(phi, 1.0, g, gamma, prev_tiles, prev_ntiles_dev, tiles,
-                                    capacity, ntiles_dev, workspace, workspace_bytes, stream);
+                                    capacity, ntiles_dev, workspace, workspace_bytes, stream,
+                                    false);
 }
 
 int ls_band_rebuild_f16s(const uint16_t *phi_h, float scale, const ls_grid *g, float gamma,
@@ -470,7 +482,8 @@ int ls_band_rebuild_f16s(const uint16_t *phi_h, float scale, const ls_grid *g, f
         return LS_ERR_ARG;
     }
     return ls::band_rebuild<uint16_t>(phi_h, scale, g, gamma, prev_tiles, prev_ntiles_dev, tiles,
-                                      capacity, ntiles_dev, workspace, workspace_bytes, stream);
+                                      capacity, ntiles_dev, workspace, workspace_bytes, stream,
+                                      false);
 }
 
 int ls_band_build_f16s(const uint16_t *phi_h, float scale, const ls_grid *g, float gamma,

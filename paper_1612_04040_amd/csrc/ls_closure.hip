@@ -1,0 +1,883 @@
+// Learned closure of the coarse first-order step: a 3-layer 3^3-conv network
+// (3 -> 16 -> 16 -> 1 channels, SiLU) whose output r corrects the plain coarse
+// update on the active tiles, phi + delta_plain + dx * r, trained toward fine
+// runs of the same scheme restricted 4x.  BF16 weights and activations, FP32
+// accumulation on the matrix cores (v_mfma_f32_16x16x32_bf16).
+//
+// Every convolution is an implicit GEMM over the 8^3 tiles of a tile list:
+// one block per tile stages the tile and its one-point halo (10^3 points,
+// channel-last) in LDS; the 16 output channels are the MFMA rows, 16 output
+// points its columns, and the reduction runs over (tap, input channel) in
+// chunks of 32.  Activations outside the band count as zero; since the active
+// tiles lie one tile deep inside the band and the network sees 3 points
+// around a point, r on the active tiles is the same as with no band at all.
+#include <algorithm>
+#include <cmath>
+
+#include "ls_compact.h"
+#include "ls_stencil.h"
+
+namespace ls {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kT = 8;          // closure tile edge (8^3 tiles)
+constexpr int kP = kT + 2;     // patch edge with the one-point halo
+constexpr int kTaps = 27;
+// flat parameter layout (FP32 master copy), numpy order (out, in, dz, dy, dx)
+constexpr int kW0 = 0, kB0 = kW0 + 16 * 3 * 27, kW1 = kB0 + 16, kB1 = kW1 + 16 * 16 * 27,
+              kW2 = kB1 + 16, kB2 = kW2 + 1 * 16 * 27, kNParams = kB2 + 1;
+static_assert(kNParams == 8673, "parameter count");
+
+__device__ inline __bf16 to_bf16(float v) { return static_cast<__bf16>(v); }
+__device__ inline float from_bf16(__bf16 v) { return static_cast<float>(v); }
+__device__ inline float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+__device__ inline float silu_grad_f(float z) {
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// ---------------------------------------------------------------------------
+// weight packing: the MFMA A operand of every reduction chunk, per lane.
+//   CIN = 16: chunk c, k = 8*(lane/16) + j: tap 2c + k/16, input channel k%16
+//   CIN = 4:  chunk c, k = 8*(lane/16) + j: tap 8c + k/4,  input channel k%4
+// row (output channel) = lane % 16.  Taps >= 27, channels beyond the real
+// ones and rows beyond the real outputs are zero.  `flip` packs the
+// transposed, tap-reversed weights of the backward (data-gradient) conv.
+
+template <int CIN>
+constexpr int nchunk() { return CIN == 16 ? 14 : 4; }
+
+struct PackSpec {
+    int woff;       // offset of the layer's weights in the flat parameters
+    int cin, cout;  // real channel counts of the layer (forward)
+    int pcin;       // packed input width: 4 or 16
+    bool flip;      // backward: swap in/out and reverse the taps
+};
+
+__global__ void pack_weights_kernel(const float *__restrict__ params, __bf16 *__restrict__ out,
+                                    PackSpec s) {
+    const int nch = s.pcin == 16 ? 14 : 4;
+    const int total = nch * 64 * 8;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const int c = i / 512, lane = (i / 8) % 64, j = i % 8;
+        const int k = 8 * (lane / 16) + j;
+        const int row = lane % 16;
+        int tap, ci;
+        if (s.pcin == 16) {
+            tap = 2 * c + k / 16;
+            ci = k % 16;
+        } else {
+            tap = 8 * c + k / 4;
+            ci = k % 4;
+        }
+        float v = 0.f;
+        if (tap < kTaps) {
+            // forward: w[out=row][in=ci][tap]; backward: w[out=ci][in=row][26-tap]
+            const int o = s.flip ? ci : row, in = s.flip ? row : ci;
+            const int t = s.flip ? kTaps - 1 - tap : tap;
+            if (o < s.cout && in < s.cin) v = params[s.woff + (o * s.cin + in) * kTaps + t];
+        }
+        out[i] = to_bf16(v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the convolution kernel
+
+struct ConvGeo {
+    int nx, ny, nz;
+    int ntx, nty, ntz;
+};
+
+// Input of a CIN = 4 convolution, built on the fly per patch point:
+//  FEAT: (clip(phi/gamma, +-2), F / Fmax, (plain - phi)/dx, 0) of the band;
+//  GRAD: (g, 0, 0, 0) with g the loss gradient w.r.t. r (FP32, dense).
+struct In4 {
+    const float *phi, *F, *plain, *g;
+    float inv_gamma, inv_fmax, inv_dx;
+};
+
+enum { OUT_HIDDEN = 0, OUT_LAST = 1, OUT_GRAD = 2 };
+
+// One block per listed tile.  CIN: 16 (input bf16 x16 channel-last) or 4
+// (In4 source).  MODE: OUT_HIDDEN writes z (pre-activation) and a = SiLU(z),
+// bf16 x16; OUT_LAST writes r = row 0 (+ bias) as FP32 and, when `apply`,
+// corrects the plain step on the tile (phi_next += dx*r) unless some r of
+// the tile is non-finite or above 1/2 (then counts a fallback); OUT_GRAD
+// writes acc * SiLU'(z) as bf16 x16 (z read from zin).
+template <int CIN, int MODE>
+__global__ __launch_bounds__(kBlock) void closure_conv_kernel(
+    ConvGeo g, const int32_t *__restrict__ tiles, const int32_t *__restrict__ ntiles_dev,
+    int ntiles_cap, const uint8_t *__restrict__ umap, const __bf16 *__restrict__ in16, In4 in4,
+    const __bf16 *__restrict__ wpack, const float *__restrict__ bias, __bf16 *__restrict__ zout,
+    __bf16 *__restrict__ aout, const __bf16 *__restrict__ zin, float *__restrict__ rout,
+    float *__restrict__ phi_next, float dx, int32_t *__restrict__ fallbacks) {
+    constexpr int NCH = nchunk<CIN>();
+    __shared__ __align__(16) __bf16 patch[kP * kP * kP * CIN];
+    __shared__ int bad_s;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = min(*ntiles_dev, ntiles_cap);
+
+    // weights of this lane: one 8-wide A operand per chunk
+    bf16x8 wa[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+        wa[c] = *reinterpret_cast<const bf16x8 *>(wpack + (c * 64 + lane) * 8);
+
+    for (int p = blockIdx.x; p < n; p += gridDim.x) {
+        const int t = tiles[p];
+        if (t < 0 || t >= g.ntx * g.nty * g.ntz) continue;  // uniform
+        const int ti = t % g.ntx, rr = t / g.ntx;
+        const int tj = rr % g.nty, tk = rr / g.nty;
+        const int x0 = ti * kT, y0 = tj * kT, z0 = tk * kT;
+
+        // stage the 10^3 patch (zero outside the grid and outside the band)
+        for (int q = threadIdx.x; q < kP * kP * kP; q += kBlock) {
+            const int px = q % kP, py = (q / kP) % kP, pz = q / (kP * kP);
+            const int gx = x0 + px - 1, gy = y0 + py - 1, gz = z0 + pz - 1;
+            bool ok = gx >= 0 && gy >= 0 && gz >= 0 && gx < g.nx && gy < g.ny && gz < g.nz;
+            if (ok) {
+                const int nt = ((gz / kT) * g.nty + gy / kT) * g.ntx + gx / kT;
+                ok = umap[nt] != 0;
+            }
+            const int64_t gi = (static_cast<int64_t>(gz) * g.ny + gy) * g.nx + gx;
+            if constexpr (CIN == 16) {
+                uint4 lo = make_uint4(0, 0, 0, 0), hi = lo;
+                if (ok) {
+                    const uint4 *src = reinterpret_cast<const uint4 *>(in16 + gi * 16);
+                    lo = src[0];
+                    hi = src[1];
+                }
+                uint4 *dst = reinterpret_cast<uint4 *>(patch + q * 16);
+                dst[0] = lo;
+                dst[1] = hi;
+            } else {
+                float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+                if (ok) {
+                    if (in4.g) {
+                        v0 = in4.g[gi];
+                    } else {
+                        const float ph = in4.phi[gi];
+                        v0 = fminf(fmaxf(ph * in4.inv_gamma, -2.f), 2.f);
+                        v1 = in4.F[gi] * in4.inv_fmax;
+                        v2 = (in4.plain[gi] - ph) * in4.inv_dx;
+                    }
+                }
+                patch[q * 4 + 0] = to_bf16(v0);
+                patch[q * 4 + 1] = to_bf16(v1);
+                patch[q * 4 + 2] = to_bf16(v2);
+                patch[q * 4 + 3] = to_bf16(0.f);
+            }
+        }
+        if (MODE == OUT_LAST && threadIdx.x == 0) bad_s = 0;
+        __syncthreads();
+
+        // 32 groups of 16 output points (x fastest), 8 per wave
+        const int j = lane & 15, kq = lane >> 4;
+        float rvals[8];
+#pragma unroll
+        for (int gi8 = 0; gi8 < 8; ++gi8) {
+            const int grp = wave + 4 * gi8;
+            const int pt = grp * 16 + j;
+            const int lx = pt & 7, ly = (pt >> 3) & 7, lz = pt >> 6;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                bf16x8 b;
+                if constexpr (CIN == 16) {
+                    const int tap = 2 * c + (kq >> 1);
+                    if (tap < kTaps) {
+                        const int dz = tap / 9, dy = (tap / 3) % 3, dxx = tap % 3;
+                        const int q = ((lz + dz) * kP + (ly + dy)) * kP + (lx + dxx);
+                        b = *reinterpret_cast<const bf16x8 *>(patch + q * 16 + 8 * (kq & 1));
+                    } else {
+                        b = bf16x8{};
+                    }
+                } else {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int tap = 8 * c + 2 * kq + h;
+                        if (tap < kTaps) {
+                            const int dz = tap / 9, dy = (tap / 3) % 3, dxx = tap % 3;
+                            const int q = ((lz + dz) * kP + (ly + dy)) * kP + (lx + dxx);
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) b[4 * h + e] = patch[q * 4 + e];
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) b[4 * h + e] = to_bf16(0.f);
+                        }
+                    }
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[c], b, acc, 0, 0, 0);
+            }
+            // acc[i] = output channel 4*kq + i of point pt
+            const int64_t gpt =
+                (static_cast<int64_t>(z0 + lz) * g.ny + (y0 + ly)) * g.nx + (x0 + lx);
+            if constexpr (MODE == OUT_HIDDEN) {
+                __bf16 zb[4], ab[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float z = acc[i] + bias[4 * kq + i];
+                    zb[i] = to_bf16(z);
+                    ab[i] = to_bf16(silu_f(z));
+                }
+                if (zout) *reinterpret_cast<uint2 *>(zout + gpt * 16 + 4 * kq) = *reinterpret_cast<uint2 *>(zb);
+                *reinterpret_cast<uint2 *>(aout + gpt * 16 + 4 * kq) = *reinterpret_cast<uint2 *>(ab);
+            } else if constexpr (MODE == OUT_GRAD) {
+                const uint2 zr = *reinterpret_cast<const uint2 *>(zin + gpt * 16 + 4 * kq);
+                const __bf16 *zv = reinterpret_cast<const __bf16 *>(&zr);
+                __bf16 ob[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) ob[i] = to_bf16(acc[i] * silu_grad_f(from_bf16(zv[i])));
+                *reinterpret_cast<uint2 *>(aout + gpt * 16 + 4 * kq) = *reinterpret_cast<uint2 *>(ob);
+            } else {
+                rvals[gi8] = acc[0] + bias[0];
+                if (kq == 0) {
+                    rout[gpt] = rvals[gi8];
+                    if (!(fabsf(rvals[gi8]) <= 0.5f)) atomicOr(&bad_s, 1);  // NaN fails too
+                }
+            }
+        }
+        if constexpr (MODE == OUT_LAST) {
+            __syncthreads();
+            const bool bad = bad_s != 0;
+            if (phi_next) {
+                if (!bad) {
+#pragma unroll
+                    for (int gi8 = 0; gi8 < 8; ++gi8) {
+                        const int pt = (wave + 4 * gi8) * 16 + j;
+                        const int lx = pt & 7, ly = (pt >> 3) & 7, lz = pt >> 6;
+                        if (kq == 0) {
+                            const int64_t gpt =
+                                (static_cast<int64_t>(z0 + lz) * g.ny + (y0 + ly)) * g.nx + (x0 + lx);
+                            phi_next[gpt] += dx * rvals[gi8];
+                        }
+                    }
+                } else if (threadIdx.x == 0 && fallbacks) {
+                    atomicAdd(fallbacks, 1);
+                }
+            }
+        }
+        __syncthreads();  // patch free for the next tile
+    }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradients: per tile, for every tap, GW[o][c] += sum_p G[p][o] X[p+tap][c]
+// on the matrix cores (rows o, columns c, reduction over 32 points per
+// instruction), written as per-tile partial sums; a second kernel adds the
+// partials of all tiles in list order (deterministic).
+
+template <int CIN>
+__global__ __launch_bounds__(kBlock) void closure_wgrad_kernel(
+    ConvGeo g, const int32_t *__restrict__ tiles, const int32_t *__restrict__ ntiles_dev,
+    int ntiles_cap, const uint8_t *__restrict__ umap, const __bf16 *__restrict__ x16, In4 x4,
+    const __bf16 *__restrict__ gout16, const float *__restrict__ gout_r, int cout,
+    float *__restrict__ partial) {
+    // partial layout per tile: [tap][o 16][c 16] followed by bias [16]
+    constexpr int PART = kTaps * 256 + 16;
+    __shared__ __align__(16) __bf16 xs[CIN][kP * kP * kP];  // channel-major patch
+    __shared__ __align__(16) __bf16 gs[16][kT * kT * kT];    // channel-major tile gradient
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = min(*ntiles_dev, ntiles_cap);
+    for (int p = blockIdx.x; p < n; p += gridDim.x) {
+        const int t = tiles[p];
+        float *out = partial + static_cast<int64_t>(p) * PART;
+        if (t < 0 || t >= g.ntx * g.nty * g.ntz) {
+            for (int i = threadIdx.x; i < PART; i += kBlock) out[i] = 0.f;
+            continue;
+        }
+        const int ti = t % g.ntx, rr = t / g.ntx;
+        const int tj = rr % g.nty, tk = rr / g.nty;
+        const int x0 = ti * kT, y0 = tj * kT, z0 = tk * kT;
+        for (int q = threadIdx.x; q < kP * kP * kP; q += kBlock) {
+            const int px = q % kP, py = (q / kP) % kP, pz = q / (kP * kP);
+            const int gx = x0 + px - 1, gy = y0 + py - 1, gz = z0 + pz - 1;
+            bool ok = gx >= 0 && gy >= 0 && gz >= 0 && gx < g.nx && gy < g.ny && gz < g.nz;
+            if (ok) ok = umap[((gz / kT) * g.nty + gy / kT) * g.ntx + gx / kT] != 0;
+            const int64_t gi = (static_cast<int64_t>(gz) * g.ny + gy) * g.nx + gx;
+            if constexpr (CIN == 16) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c) xs[c][q] = ok ? x16[gi * 16 + c] : to_bf16(0.f);
+            } else {
+                float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+                if (ok) {
+                    const float ph = x4.phi[gi];
+                    v0 = fminf(fmaxf(ph * x4.inv_gamma, -2.f), 2.f);
+                    v1 = x4.F[gi] * x4.inv_fmax;
+                    v2 = (x4.plain[gi] - ph) * x4.inv_dx;
+                }
+                xs[0][q] = to_bf16(v0);
+                xs[1][q] = to_bf16(v1);
+                xs[2][q] = to_bf16(v2);
+                xs[3][q] = to_bf16(0.f);
+            }
+        }
+        for (int q = threadIdx.x; q < 512; q += kBlock) {
+            const int lx = q & 7, ly = (q >> 3) & 7, lz = q >> 6;
+            const int64_t gi = (static_cast<int64_t>(z0 + lz) * g.ny + (y0 + ly)) * g.nx + x0 + lx;
+            if (gout_r) {
+                gs[0][q] = to_bf16(gout_r[gi]);
+                for (int o = 1; o < 16; ++o) gs[o][q] = to_bf16(0.f);
+            } else {
+#pragma unroll
+                for (int o = 0; o < 16; ++o) gs[o][q] = gout16[gi * 16 + o];
+            }
+        }
+        __syncthreads();
+        // bias gradient: sum over the tile's points
+        if (threadIdx.x < 16) {
+            float s = 0.f;
+            for (int q = 0; q < 512; ++q) s += from_bf16(gs[threadIdx.x][q]);
+            out[kTaps * 256 + threadIdx.x] = threadIdx.x < cout ? s : 0.f;
+        }
+        const int row = lane & 15, kq = lane >> 4;
+        for (int tap = wave; tap < kTaps; tap += 4) {
+            const int dz = tap / 9, dy = (tap / 3) % 3, dxx = tap % 3;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            for (int kc = 0; kc < 16; ++kc) {  // 16 chunks of 32 points
+                bf16x8 a, b;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int q = kc * 32 + 8 * kq + e;  // point of the tile
+                    const int lx = q & 7, ly = (q >> 3) & 7, lz = q >> 6;
+                    a[e] = gs[row][q];
+                    const int xq = ((lz + dz) * kP + (ly + dy)) * kP + (lx + dxx);
+                    b[e] = row < CIN ? xs[row < CIN ? row : 0][xq] : to_bf16(0.f);
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+            }
+            // acc[i] = GW[o = 4*kq + i][c = row]
+#pragma unroll
+            for (int i = 0; i < 4; ++i) out[tap * 256 + (4 * kq + i) * 16 + row] = acc[i];
+        }
+        __syncthreads();
+    }
+}
+
+// grad[flat param of layer] = sum over tiles of the partials, in tile order
+__global__ void closure_wgrad_reduce_kernel(const float *__restrict__ partial,
+                                            const int32_t *__restrict__ ntiles_dev, int cap,
+                                            int woff, int boff, int cin, int cout,
+                                            float *__restrict__ grad) {
+    constexpr int PART = kTaps * 256 + 16;
+    const int n = min(*ntiles_dev, cap);
+    const int nw = cout * cin * kTaps;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nw + cout;
+         i += gridDim.x * blockDim.x) {
+        int src;
+        if (i < nw) {
+            const int o = i / (cin * kTaps), c = (i / kTaps) % cin, tap = i % kTaps;
+            src = tap * 256 + o * 16 + c;
+        } else {
+            src = kTaps * 256 + (i - nw);
+        }
+        float s = 0.f;
+        for (int p = 0; p < n; ++p) s += partial[static_cast<int64_t>(p) * PART + src];
+        grad[i < nw ? woff + i : boff + (i - nw)] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// restriction, loss gradient, Adam
+
+__global__ void restrict4_kernel(const float *__restrict__ fine, int nxf, int nyf, int nzf,
+                                 float *__restrict__ coarse) {
+    const int nxc = nxf / 4, nyc = nyf / 4, nzc = nzf / 4;
+    const int64_t total = static_cast<int64_t>(nxc) * nyc * nzc;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int I = i % nxc, J = (i / nxc) % nyc, K = i / (static_cast<int64_t>(nxc) * nyc);
+        float s = 0.f;
+        for (int dz = 1; dz <= 2; ++dz)
+            for (int dy = 1; dy <= 2; ++dy)
+                for (int dxx = 1; dxx <= 2; ++dxx)
+                    s += fine[(static_cast<int64_t>(4 * K + dz) * nyf + (4 * J + dy)) * nxf +
+                              (4 * I + dxx)];
+        coarse[i] = s * 0.125f;
+    }
+}
+
+// g = 2 (r - r*) / count on the active tiles, r* = (target - phi - delta)/dx;
+// partial loss sums per tile (deterministic reduction afterwards).
+__global__ __launch_bounds__(kBlock) void closure_loss_kernel(
+    ConvGeo g, const int32_t *__restrict__ tiles, const int32_t *__restrict__ ntiles_dev, int cap,
+    const float *__restrict__ r, const float *__restrict__ phi, const float *__restrict__ plain,
+    const float *__restrict__ target, float inv_dx, float *__restrict__ gr,
+    float *__restrict__ tile_loss) {
+    const int n = min(*ntiles_dev, cap);
+    const float inv_cnt = 1.0f / fmaxf(1.0f, static_cast<float>(n) * 512.f);
+    __shared__ float red[kBlock];
+    for (int p = blockIdx.x; p < n; p += gridDim.x) {
+        const int t = tiles[p];
+        const int ti = t % g.ntx, rr = t / g.ntx;
+        const int x0 = ti * kT, y0 = (rr % g.nty) * kT, z0 = (rr / g.nty) * kT;
+        float s = 0.f;
+        for (int q = threadIdx.x; q < 512; q += kBlock) {
+            const int lx = q & 7, ly = (q >> 3) & 7, lz = q >> 6;
+            const int64_t gi = (static_cast<int64_t>(z0 + lz) * g.ny + (y0 + ly)) * g.nx + x0 + lx;
+            const float rs = (target[gi] - plain[gi]) * inv_dx;
+            const float d = r[gi] - rs;
+            gr[gi] = 2.f * d * inv_cnt;
+            s += d * d;
+        }
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) tile_loss[p] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ void loss_reduce_kernel(const float *__restrict__ tile_loss, const int32_t *ntiles_dev,
+                                   int cap, float *__restrict__ loss) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int n = min(*ntiles_dev, cap);
+        double s = 0.0;
+        for (int p = 0; p < n; ++p) s += tile_loss[p];
+        *loss = static_cast<float>(s / fmax(1.0, n * 512.0));
+    }
+}
+
+__global__ void adam_kernel(float *__restrict__ w, const float *__restrict__ grad,
+                            float *__restrict__ m, float *__restrict__ v, int n, float lr,
+                            float b1, float b2, float eps, float c1, float c2) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float gi = grad[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+__global__ void zero_f32_kernel(float *p, int64_t n) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = 0.f;
+}
+
+}  // namespace ls
+
+// ---------------------------------------------------------------------------
+// host side
+
+namespace ls {
+
+template <class S>
+int band_build(const S *phi, typename Codec<S>::C scale, const ls_grid *grid,
+               typename Codec<S>::C gamma, int dilate, int32_t *tiles, int64_t capacity,
+               int32_t *ntiles_dev, void *workspace, int64_t ws_bytes, void *stream_);  // ls_band.hip
+int plan_step_f32(float *phi, const float *F, const Geom &G, float dx, float dt, float *scratch,
+                  uint8_t *ws, hipStream_t stream);                                   // ls_step.hip
+
+constexpr int kPart = kTaps * 256 + 16;  // per-tile weight-gradient partial (floats)
+
+// Closure workspace: packed weights, activations (bf16 x16, dense), dense
+// FP32 fields, the active-tile list, per-tile partial sums.
+struct ClosureWs {
+    int64_t wp0, wp1, wp2, bp1, bp2;
+    int64_t a0, z0, a1, z1, ga;
+    int64_t r, gr, plain;
+    int64_t active, counters;  // counters: [0] active count, [1] fallbacks (scratch)
+    int64_t partial, tile_loss;
+    int64_t total;
+};
+
+static ClosureWs closure_ws(const Geom &g) {
+    auto al = [](int64_t v) { return (v + 255) & ~int64_t(255); };
+    const int64_t N = g.npoints, T = g.ntiles;
+    ClosureWs w;
+    int64_t o = 0;
+    w.wp0 = o; o = al(o + 2 * 4 * 64 * 8);
+    w.wp1 = o; o = al(o + 2 * 14 * 64 * 8);
+    w.wp2 = o; o = al(o + 2 * 14 * 64 * 8);
+    w.bp1 = o; o = al(o + 2 * 14 * 64 * 8);
+    w.bp2 = o; o = al(o + 2 * 4 * 64 * 8);
+    w.a0 = o; o = al(o + 2 * 16 * N);
+    w.z0 = o; o = al(o + 2 * 16 * N);
+    w.a1 = o; o = al(o + 2 * 16 * N);
+    w.z1 = o; o = al(o + 2 * 16 * N);
+    w.ga = o; o = al(o + 2 * 16 * N);
+    w.r = o; o = al(o + 4 * N);
+    w.gr = o; o = al(o + 4 * N);
+    w.plain = o; o = al(o + 4 * N);
+    w.active = o; o = al(o + 4 * T);
+    w.counters = o; o = al(o + 4 * 64);
+    w.partial = o; o = al(o + 4 * kPart * T);
+    w.tile_loss = o; o = al(o + 4 * T);
+    w.total = o;
+    return w;
+}
+
+static int closure_geom(const ls_grid *grid, Geom *g) {
+    int rc = make_geom(grid, g);
+    if (rc != LS_OK) return rc;
+    if (g->tx != kT || g->ty != kT || g->tz != kT || g->nx % kT || g->ny % kT || g->nz % kT) {
+        set_error("closure: needs 8x8x8 tiles and grid dims that are multiples of 8");
+        return LS_ERR_UNSUPPORTED;
+    }
+    if (g->npoints * 32 >= (int64_t(1) << 40)) {
+        set_error("closure: grid too large");
+        return LS_ERR_UNSUPPORTED;
+    }
+    return LS_OK;
+}
+
+static int check_cws(const Geom &g, void *cws, int64_t bytes, ClosureWs *w) {
+    *w = closure_ws(g);
+    if (!cws || reinterpret_cast<uintptr_t>(cws) % 256) {
+        set_error("closure: closure workspace NULL or not 256-byte aligned");
+        return LS_ERR_ARG;
+    }
+    if (bytes < w->total) {
+        set_error("closure: closure workspace too small: %lld bytes given, %lld needed",
+                  (long long)bytes, (long long)w->total);
+        return LS_ERR_CAPACITY;
+    }
+    return LS_OK;
+}
+
+struct ClosureCall {
+    Geom G;
+    ClosureWs w;
+    uint8_t *cw, *ws;
+    hipStream_t s;
+    unsigned blocks;
+};
+
+// Shared argument checks of the closure entry points.
+static int closure_setup(const ls_grid *grid, float dx, float dt, float gamma, float fmax,
+                         const float *params, void *ws, int64_t ws_bytes, void *cws,
+                         int64_t cws_bytes, void *stream, ClosureCall *c) {
+    int rc = closure_geom(grid, &c->G);
+    if (rc != LS_OK) return rc;
+    if ((rc = check_cws(c->G, cws, cws_bytes, &c->w)) != LS_OK) return rc;
+    if ((rc = check_workspace(c->G, ws, ws_bytes)) != LS_OK) return rc;
+    if (!params) {
+        set_error("closure: params is NULL");
+        return LS_ERR_ARG;
+    }
+    if (!(dx > 0.f) || !(dt >= 0.f) || !(gamma > 0.f) || !(fmax > 0.f) || !(dx < INFINITY) ||
+        !(dt < INFINITY) || !(fmax < INFINITY)) {
+        set_error("closure: need finite dx > 0, dt >= 0, gamma > 0 and fmax > 0");
+        return LS_ERR_ARG;
+    }
+    DeviceInfo di;
+    if ((rc = device_info(&di)) != LS_OK) return rc;
+    c->cw = static_cast<uint8_t *>(cws);
+    c->ws = static_cast<uint8_t *>(ws);
+    c->s = static_cast<hipStream_t>(stream);
+    c->blocks = static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(c->G.ntiles,
+                                                                              int64_t(di.cus) * 4)));
+    return LS_OK;
+}
+
+template <class T>
+static T *at(const ClosureCall &c, int64_t off) {
+    return reinterpret_cast<T *>(c.cw + off);
+}
+
+static int pack_all(const ClosureCall &c, const float *params) {
+    const PackSpec spec[5] = {{kW0, 3, 16, 4, false},  {kW1, 16, 16, 16, false},
+                              {kW2, 16, 1, 16, false}, {kW1, 16, 16, 16, true},
+                              {kW2, 16, 1, 4, true}};
+    const int64_t dst[5] = {c.w.wp0, c.w.wp1, c.w.wp2, c.w.bp1, c.w.bp2};
+    for (int i = 0; i < 5; ++i) {
+        hipLaunchKernelGGL(pack_weights_kernel, dim3(8), dim3(256), 0, c.s, params,
+                           at<__bf16>(c, dst[i]), spec[i]);
+        LS_LAUNCH_CHECK("pack_weights_kernel");
+    }
+    return LS_OK;
+}
+
+static int zero_f32(float *p, int64_t n, hipStream_t s) {
+    const unsigned b = static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(cdiv64(n, 256), 4096)));
+    hipLaunchKernelGGL(zero_f32_kernel, dim3(b), dim3(256), 0, s, p, n);
+    LS_LAUNCH_CHECK("zero_f32_kernel");
+    return LS_OK;
+}
+
+static ConvGeo conv_geo(const Geom &g) { return ConvGeo{g.nx, g.ny, g.nz, g.ntx, g.nty, g.ntz}; }
+
+// A (into the closure workspace) and U (into tiles, with its step plan in
+// the band workspace) of phi.
+static int closure_bands(const ClosureCall &c, const float *phi, const ls_grid *grid, float gamma,
+                         int32_t *tiles, int64_t capacity, int32_t *ntiles_dev, int64_t ws_bytes) {
+    int rc = band_build<float>(phi, 1.0f, grid, gamma, 0, at<int32_t>(c, c.w.active),
+                               c.G.ntiles, at<int32_t>(c, c.w.counters), c.ws, ws_bytes, c.s);
+    if (rc != LS_OK) return rc;
+    return band_build<float>(phi, 1.0f, grid, gamma, 1, tiles, capacity, ntiles_dev, c.ws,
+                             ws_bytes, c.s);
+}
+
+// plain = phi + one plain step on the planned band (dense copy first, so the
+// points outside the band hold phi).
+static int closure_plain(const ClosureCall &c, const float *phi, float *plain, const float *F,
+                         float dx, float dt, float *scratch) {
+    int rc = ls_copy_f32(plain, phi, c.G.npoints, c.s);
+    if (rc != LS_OK) return rc;
+    return plan_step_f32(plain, F, c.G, dx, dt, scratch, c.ws, c.s);
+}
+
+// The network on the band (L1, L2) and the active tiles (L3): r into the
+// workspace and, with `apply`, the corrected step plain += dx * r on every
+// active tile whose r passes the fallback test.
+static int closure_network(const ClosureCall &c, const float *phi, const float *F,
+                           const float *plain, float dx, float gamma, float fmax,
+                           const int32_t *band, const int32_t *nband, const float *params,
+                           bool store_z, float *apply, int32_t *fallbacks) {
+    const ConvGeo cg = conv_geo(c.G);
+    const int cap = static_cast<int>(c.G.ntiles);
+    const uint8_t *umap = c.ws + workspace_layout(c.G).u_map;
+    const int32_t *active = at<int32_t>(c, c.w.active);
+    const int32_t *nactive = at<int32_t>(c, c.w.counters);
+    In4 feat{phi, F, plain, nullptr, 1.0f / gamma, 1.0f / fmax, 1.0f / dx};
+    In4 none{nullptr, nullptr, nullptr, nullptr, 0.f, 0.f, 0.f};
+    hipLaunchKernelGGL((closure_conv_kernel<4, OUT_HIDDEN>), dim3(c.blocks), dim3(kBlock), 0, c.s,
+                       cg, band, nband, cap, umap, nullptr, feat, at<const __bf16>(c, c.w.wp0),
+                       params + kB0, store_z ? at<__bf16>(c, c.w.z0) : nullptr,
+                       at<__bf16>(c, c.w.a0), nullptr, nullptr, nullptr, 0.f, nullptr);
+    LS_LAUNCH_CHECK("closure_conv_kernel (layer 1)");
+    hipLaunchKernelGGL((closure_conv_kernel<16, OUT_HIDDEN>), dim3(c.blocks), dim3(kBlock), 0,
+                       c.s, cg, band, nband, cap, umap, at<const __bf16>(c, c.w.a0), none,
+                       at<const __bf16>(c, c.w.wp1), params + kB1,
+                       store_z ? at<__bf16>(c, c.w.z1) : nullptr, at<__bf16>(c, c.w.a1), nullptr,
+                       nullptr, nullptr, 0.f, nullptr);
+    LS_LAUNCH_CHECK("closure_conv_kernel (layer 2)");
+    hipLaunchKernelGGL((closure_conv_kernel<16, OUT_LAST>), dim3(c.blocks), dim3(kBlock), 0, c.s,
+                       cg, active, nactive, cap, umap, at<const __bf16>(c, c.w.a1), none,
+                       at<const __bf16>(c, c.w.wp2), params + kB2, nullptr, nullptr, nullptr,
+                       at<float>(c, c.w.r), apply, dx, fallbacks);
+    LS_LAUNCH_CHECK("closure_conv_kernel (layer 3)");
+    return LS_OK;
+}
+
+static int wgrad_reduce(const ClosureCall &c, const int32_t *ncount, int woff, int boff, int cin,
+                        int cout, float *grad) {
+    const int total = cout * cin * kTaps + cout;
+    hipLaunchKernelGGL(closure_wgrad_reduce_kernel, dim3(cdiv64(total, 256)), dim3(256), 0, c.s,
+                       at<const float>(c, c.w.partial), ncount, static_cast<int>(c.G.ntiles), woff,
+                       boff, cin, cout, grad);
+    LS_LAUNCH_CHECK("closure_wgrad_reduce_kernel");
+    return LS_OK;
+}
+
+}  // namespace ls
+
+extern "C" {
+
+int64_t ls_closure_param_count(void) { return ls::kNParams; }
+
+int64_t ls_closure_workspace_bytes(const ls_grid *g) {
+    ls::clear_error();
+    ls::Geom G;
+    int rc = ls::closure_geom(g, &G);
+    if (rc != LS_OK) return rc;
+    return ls::closure_ws(G).total;
+}
+
+int ls_restrict4_f32(const float *fine, const ls_grid *fine_grid, float *coarse, void *stream) {
+    ls::clear_error();
+    ls::Geom G;
+    int rc = ls::make_geom(fine_grid, &G);
+    if (rc != LS_OK) return rc;
+    if (!fine || !coarse) {
+        ls::set_error("restrict4: NULL buffer");
+        return LS_ERR_ARG;
+    }
+    if (G.nx % 4 || G.ny % 4 || G.nz % 4) {
+        ls::set_error("restrict4: fine dims must be multiples of 4");
+        return LS_ERR_ARG;
+    }
+    hipLaunchKernelGGL(ls::restrict4_kernel, dim3(2048), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), fine, G.nx, G.ny, G.nz, coarse);
+    LS_LAUNCH_CHECK("restrict4_kernel");
+    return LS_OK;
+}
+
+int ls_closure_forward_f32(const float *phi, const float *F, const ls_grid *g, float dx, float dt,
+                           float gamma, float fmax, const float *params, float *r, float *plain,
+                           int32_t *tiles, int64_t capacity, int32_t *ntiles_dev, float *scratch,
+                           void *ws, int64_t ws_bytes, void *cws, int64_t cws_bytes,
+                           void *stream) {
+    ls::clear_error();
+    ls::ClosureCall c;
+    int rc = ls::closure_setup(g, dx, dt, gamma, fmax, params, ws, ws_bytes, cws, cws_bytes,
+                               stream, &c);
+    if (rc != LS_OK) return rc;
+    if (!phi || !F || !tiles || !ntiles_dev || !scratch) {
+        ls::set_error("closure forward: NULL argument");
+        return LS_ERR_ARG;
+    }
+    if (capacity < c.G.ntiles) {
+        ls::set_error("closure forward: capacity %lld < %lld tiles", (long long)capacity,
+                      (long long)c.G.ntiles);
+        return LS_ERR_CAPACITY;
+    }
+    float *pl = ls::at<float>(c, c.w.plain);
+    float *rr = ls::at<float>(c, c.w.r);
+    if ((rc = ls::closure_bands(c, phi, g, gamma, tiles, capacity, ntiles_dev, ws_bytes)) != LS_OK)
+        return rc;
+    if ((rc = ls::closure_plain(c, phi, pl, F, dx, dt, scratch)) != LS_OK) return rc;
+    if ((rc = ls::pack_all(c, params)) != LS_OK) return rc;
+    if ((rc = ls::zero_f32(rr, c.G.npoints, c.s)) != LS_OK) return rc;
+    if ((rc = ls::closure_network(c, phi, F, pl, dx, gamma, fmax, tiles, ntiles_dev, params, false,
+                                  nullptr, nullptr)) != LS_OK)
+        return rc;
+    if (r && (rc = ls_copy_f32(r, rr, c.G.npoints, c.s)) != LS_OK) return rc;
+    if (plain && (rc = ls_copy_f32(plain, pl, c.G.npoints, c.s)) != LS_OK) return rc;
+    return LS_OK;
+}
+
+int ls_closure_backward_f32(const float *phi, const float *target, const float *F,
+                            const ls_grid *g, float dx, float dt, float gamma, float fmax,
+                            const float *params, float *grad, float *loss_dev, int32_t *tiles,
+                            int64_t capacity, int32_t *ntiles_dev, float *scratch, void *ws,
+                            int64_t ws_bytes, void *cws, int64_t cws_bytes, void *stream) {
+    ls::clear_error();
+    ls::ClosureCall c;
+    int rc = ls::closure_setup(g, dx, dt, gamma, fmax, params, ws, ws_bytes, cws, cws_bytes,
+                               stream, &c);
+    if (rc != LS_OK) return rc;
+    if (!phi || !target || !F || !grad || !tiles || !ntiles_dev || !scratch) {
+        ls::set_error("closure backward: NULL argument");
+        return LS_ERR_ARG;
+    }
+    if (capacity < c.G.ntiles) {
+        ls::set_error("closure backward: capacity %lld < %lld tiles", (long long)capacity,
+                      (long long)c.G.ntiles);
+        return LS_ERR_CAPACITY;
+    }
+    const ls::ConvGeo cg = ls::conv_geo(c.G);
+    const int cap = static_cast<int>(c.G.ntiles);
+    const uint8_t *umap = c.ws + ls::workspace_layout(c.G).u_map;
+    const int32_t *active = ls::at<int32_t>(c, c.w.active);
+    const int32_t *nactive = ls::at<int32_t>(c, c.w.counters);
+    float *pl = ls::at<float>(c, c.w.plain);
+    float *gr = ls::at<float>(c, c.w.gr);
+    float *part = ls::at<float>(c, c.w.partial);
+    if ((rc = ls::closure_bands(c, phi, g, gamma, tiles, capacity, ntiles_dev, ws_bytes)) != LS_OK)
+        return rc;
+    if ((rc = ls::closure_plain(c, phi, pl, F, dx, dt, scratch)) != LS_OK) return rc;
+    if ((rc = ls::pack_all(c, params)) != LS_OK) return rc;
+    if ((rc = ls::closure_network(c, phi, F, pl, dx, gamma, fmax, tiles, ntiles_dev, params, true,
+                                  nullptr, nullptr)) != LS_OK)
+        return rc;
+    // loss and its gradient w.r.t. r on the active tiles (zero elsewhere)
+    if ((rc = ls::zero_f32(gr, c.G.npoints, c.s)) != LS_OK) return rc;
+    hipLaunchKernelGGL(ls::closure_loss_kernel, dim3(c.blocks), dim3(ls::kBlock), 0, c.s, cg,
+                       active, nactive, cap, ls::at<const float>(c, c.w.r), phi,
+                       static_cast<const float *>(pl), target, 1.0f / dx, gr,
+                       ls::at<float>(c, c.w.tile_loss));
+    LS_LAUNCH_CHECK("closure_loss_kernel");
+    if (loss_dev) {
+        hipLaunchKernelGGL(ls::loss_reduce_kernel, dim3(1), dim3(64), 0, c.s,
+                           ls::at<const float>(c, c.w.tile_loss), nactive, cap, loss_dev);
+        LS_LAUNCH_CHECK("loss_reduce_kernel");
+    }
+    ls::In4 none{nullptr, nullptr, nullptr, nullptr, 0.f, 0.f, 0.f};
+    ls::In4 feat{phi, F, pl, nullptr, 1.0f / gamma, 1.0f / fmax, 1.0f / dx};
+    ls::In4 gin{nullptr, nullptr, nullptr, gr, 0.f, 0.f, 0.f};
+    // layer 3 weights: sum over active tiles of g(p) a1(p + tap)
+    hipLaunchKernelGGL((ls::closure_wgrad_kernel<16>), dim3(c.blocks), dim3(ls::kBlock), 0, c.s, cg,
+                       active, nactive, cap, umap, ls::at<const __bf16>(c, c.w.a1), none,
+                       nullptr, static_cast<const float *>(gr), 1, part);
+    LS_LAUNCH_CHECK("closure_wgrad_kernel (layer 3)");
+    if ((rc = ls::wgrad_reduce(c, nactive, ls::kW2, ls::kB2, 16, 1, grad)) != LS_OK) return rc;
+    // dL/dz1 = (W3^T g) * SiLU'(z1) on the band
+    hipLaunchKernelGGL((ls::closure_conv_kernel<4, ls::OUT_GRAD>), dim3(c.blocks), dim3(ls::kBlock),
+                       0, c.s, cg, static_cast<const int32_t *>(tiles),
+                       static_cast<const int32_t *>(ntiles_dev), cap, umap, nullptr, gin,
+                       ls::at<const __bf16>(c, c.w.bp2), nullptr, nullptr, ls::at<__bf16>(c, c.w.ga),
+                       ls::at<const __bf16>(c, c.w.z1), nullptr, nullptr, 0.f, nullptr);
+    LS_LAUNCH_CHECK("closure_conv_kernel (grad layer 3)");
+    // layer 2 weights
+    hipLaunchKernelGGL((ls::closure_wgrad_kernel<16>), dim3(c.blocks), dim3(ls::kBlock), 0, c.s, cg,
+                       static_cast<const int32_t *>(tiles), static_cast<const int32_t *>(ntiles_dev),
+                       cap, umap, ls::at<const __bf16>(c, c.w.a0), none,
+                       ls::at<const __bf16>(c, c.w.ga), nullptr, 16, part);
+    LS_LAUNCH_CHECK("closure_wgrad_kernel (layer 2)");
+    if ((rc = ls::wgrad_reduce(c, ntiles_dev, ls::kW1, ls::kB1, 16, 16, grad)) != LS_OK) return rc;
+    // dL/dz0 = (W2^T dL/dz1) * SiLU'(z0), into the a1 buffer (no longer needed)
+    hipLaunchKernelGGL((ls::closure_conv_kernel<16, ls::OUT_GRAD>), dim3(c.blocks),
+                       dim3(ls::kBlock), 0, c.s, cg, static_cast<const int32_t *>(tiles),
+                       static_cast<const int32_t *>(ntiles_dev), cap, umap,
+                       ls::at<const __bf16>(c, c.w.ga), none, ls::at<const __bf16>(c, c.w.bp1),
+                       nullptr, nullptr, ls::at<__bf16>(c, c.w.a1), ls::at<const __bf16>(c, c.w.z0),
+                       nullptr, nullptr, 0.f, nullptr);
+    LS_LAUNCH_CHECK("closure_conv_kernel (grad layer 2)");
+    // layer 1 weights
+    hipLaunchKernelGGL((ls::closure_wgrad_kernel<4>), dim3(c.blocks), dim3(ls::kBlock), 0, c.s, cg,
+                       static_cast<const int32_t *>(tiles), static_cast<const int32_t *>(ntiles_dev),
+                       cap, umap, nullptr, feat, ls::at<const __bf16>(c, c.w.a1), nullptr, 16, part);
+    LS_LAUNCH_CHECK("closure_wgrad_kernel (layer 1)");
+    return ls::wgrad_reduce(c, ntiles_dev, ls::kW0, ls::kB0, 3, 16, grad);
+}
+
+int ls_adam_step(float *params, const float *grad, float *m, float *v, int64_t n, float lr,
+                 float beta1, float beta2, float eps, int t, void *stream) {
+    ls::clear_error();
+    if (!params || !grad || !m || !v || n <= 0 || n > INT32_MAX || t < 1 || !(lr >= 0.f) ||
+        !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f)) {
+        ls::set_error("adam: bad argument (NULL buffer, n, t < 1, or hyper-parameter range)");
+        return LS_ERR_ARG;
+    }
+    const float c1 = static_cast<float>(1.0 - std::pow(static_cast<double>(beta1), t));
+    const float c2 = static_cast<float>(1.0 - std::pow(static_cast<double>(beta2), t));
+    hipLaunchKernelGGL(ls::adam_kernel, dim3(static_cast<unsigned>(ls::cdiv64(n, 256))), dim3(256),
+                       0, static_cast<hipStream_t>(stream), params, grad, m, v,
+                       static_cast<int>(n), lr, beta1, beta2, eps, c1, c2);
+    LS_LAUNCH_CHECK("adam_kernel");
+    return LS_OK;
+}
+
+int ls_closure_run_f32(float *phi, const float *F, const ls_grid *g, float dx, float dt,
+                       float gamma, float fmax, const float *params, int nsteps, int window,
+                       int32_t *tiles, int64_t capacity, int32_t *ntiles_dev,
+                       int32_t *fallbacks_dev, float *scratch, void *ws, int64_t ws_bytes,
+                       void *cws, int64_t cws_bytes, void *stream) {
+    ls::clear_error();
+    ls::ClosureCall c;
+    int rc = ls::closure_setup(g, dx, dt, gamma, fmax, params, ws, ws_bytes, cws, cws_bytes,
+                               stream, &c);
+    if (rc != LS_OK) return rc;
+    if (!phi || !F || !tiles || !ntiles_dev || !fallbacks_dev || !scratch) {
+        ls::set_error("closure run: NULL argument");
+        return LS_ERR_ARG;
+    }
+    if (nsteps < 0 || window <= 0) {
+        ls::set_error("closure run: need nsteps >= 0 and window > 0");
+        return LS_ERR_ARG;
+    }
+    if (capacity < c.G.ntiles) {
+        ls::set_error("closure run: capacity %lld < %lld tiles", (long long)capacity,
+                      (long long)c.G.ntiles);
+        return LS_ERR_CAPACITY;
+    }
+    if ((rc = ls::pack_all(c, params)) != LS_OK) return rc;
+    float *buf[2] = {phi, ls::at<float>(c, c.w.plain)};
+    int cur = 0;
+    for (int s = 0; s < nsteps; ++s) {
+        if (s % window == 0 &&
+            (rc = ls::closure_bands(c, buf[cur], g, gamma, tiles, capacity, ntiles_dev,
+                                    ws_bytes)) != LS_OK)
+            return rc;
+        float *x = buf[cur], *y = buf[cur ^ 1];
+        if ((rc = ls::closure_plain(c, x, y, F, dx, dt, scratch)) != LS_OK) return rc;
+        if ((rc = ls::closure_network(c, x, F, y, dx, gamma, fmax, tiles, ntiles_dev, params,
+                                      false, y, fallbacks_dev)) != LS_OK)
+            return rc;
+        cur ^= 1;
+    }
+    if (cur == 1 && (rc = ls_copy_f32(phi, buf[1], c.G.npoints, c.s)) != LS_OK) return rc;
+    return LS_OK;
+}
+
+}  // extern "C"

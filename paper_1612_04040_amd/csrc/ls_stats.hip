@@ -62,6 +62,53 @@ __global__ __launch_bounds__(kBlock) void copy_f32_kernel(float *__restrict__ ds
 
 extern "C" {
 
+int ls_graph_begin(void *stream) {
+    ls::clear_error();
+    if (!stream) {
+        ls::set_error("graph: capture needs a non-NULL stream");
+        return LS_ERR_ARG;
+    }
+    LS_HIP_CHECK(hipStreamBeginCapture(static_cast<hipStream_t>(stream),
+                                       hipStreamCaptureModeThreadLocal));
+    return LS_OK;
+}
+
+int ls_graph_end(void *stream, void **graph) {
+    ls::clear_error();
+    if (!stream || !graph) {
+        ls::set_error("graph: NULL stream or output");
+        return LS_ERR_ARG;
+    }
+    hipGraph_t g = nullptr;
+    LS_HIP_CHECK(hipStreamEndCapture(static_cast<hipStream_t>(stream), &g));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        ls::set_error("graph: instantiate failed: %s", hipGetErrorString(e));
+        return LS_ERR_HIP;
+    }
+    *graph = exec;
+    return LS_OK;
+}
+
+int ls_graph_launch(void *graph, void *stream) {
+    ls::clear_error();
+    if (!graph) {
+        ls::set_error("graph: NULL graph");
+        return LS_ERR_ARG;
+    }
+    LS_HIP_CHECK(hipGraphLaunch(static_cast<hipGraphExec_t>(graph), static_cast<hipStream_t>(stream)));
+    return LS_OK;
+}
+
+int ls_graph_destroy(void *graph) {
+    ls::clear_error();
+    if (!graph) return LS_OK;
+    LS_HIP_CHECK(hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph)));
+    return LS_OK;
+}
+
 int ls_copy_f32(float *dst, const float *src, int64_t n, void *stream) {
     ls::clear_error();
     if (!dst || !src || n < 0) {

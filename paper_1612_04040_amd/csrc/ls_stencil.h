@@ -1,0 +1,310 @@
+// The upwind stencil (Eq. 3-5) and the fast band-step kernel, shared by the
+// single-grid step and the batched step.
+#pragma once
+
+#include "ls_internal.h"
+
+namespace ls {
+
+constexpr int kMaxOwn = 16;   // grid points owned by one thread per item
+constexpr int kMaxHalo = 8;   // y/z halo points loaded by one thread per item
+constexpr int kMaxRun = 32;   // tiles per work item (4*kMaxRun + 2 <= kBlock)
+
+struct StepGeom {
+    int nx, ny, nz;
+    int tx, ty, tz;
+    int ntx, nty, ntz;
+    int ntiles;  // tiles of the grid (the list capacity)
+    int R;       // tiles per work item (x-run length cap)
+    int xl;      // threads per grid row (power of two >= R*tx)
+    int xl_log;  // log2(xl)
+    int sx, sy;  // LDS box strides: sx = R*tx + 2, sy = ty + 2
+};
+
+// One grid of a batch, as the batched kernels read it (device memory).
+struct BatchInst {
+    int64_t offset;          // first element of the grid in phi / F / scratch
+    int32_t nx, ny, nz;
+    int32_t tx, ty, tz;
+    int32_t ntx, nty, ntz;
+    int32_t tile_base;       // first global tile id of the grid
+    int32_t ntiles;
+    int32_t R;               // tiles per work item
+    int32_t slab_base;       // first global slab (tj, tk) of the grid
+    int32_t vec_ok;          // x rows may be read as 16-byte vectors
+    float dx, dt, dtdx, gamma;
+    int32_t group;           // tile-shape group of the grid
+    int32_t pad[3];
+};
+static_assert(sizeof(BatchInst) == 96, "BatchInst layout");
+
+// Fast form (f32, f16s): unscaled differences, dt/dx folded into one factor.
+// Exact form (f64): the definition term by term (D = difference / dx, the
+// squares summed x, then y, then z), no contraction.
+template <class C, bool EXACT>
+__device__ inline C upwind_point(C c, C xm, C xp, C ym, C yp, C zm, C zp, C f, C dx, C dt,
+                                 C dtdx) {
+    if constexpr (EXACT) {
+#pragma clang fp contract(off)
+        const C dmx = (c - xm) / dx, dpx = (xp - c) / dx;
+        const C dmy = (c - ym) / dx, dpy = (yp - c) / dx;
+        const C dmz = (c - zm) / dx, dpz = (zp - c) / dx;
+        const C zero = C(0);
+        auto mx = [](C a, C b) { return a > b ? a : b; };
+        auto mn = [](C a, C b) { return a < b ? a : b; };
+        if (f > zero) {
+            const C px = mx(dmx, zero) * mx(dmx, zero) + mn(dpx, zero) * mn(dpx, zero);
+            const C py = mx(dmy, zero) * mx(dmy, zero) + mn(dpy, zero) * mn(dpy, zero);
+            const C pz = mx(dmz, zero) * mx(dmz, zero) + mn(dpz, zero) * mn(dpz, zero);
+            const C g = sqrt((px + py) + pz);
+            return c - dt * f * g;
+        } else {
+            const C qx = mx(dpx, zero) * mx(dpx, zero) + mn(dmx, zero) * mn(dmx, zero);
+            const C qy = mx(dpy, zero) * mx(dpy, zero) + mn(dmy, zero) * mn(dmy, zero);
+            const C qz = mx(dpz, zero) * mx(dpz, zero) + mn(dmz, zero) * mn(dmz, zero);
+            const C g = sqrt((qx + qy) + qz);
+            return c - dt * f * g;
+        }
+    } else {
+        const bool pos = f > C(0);
+        const C ax = c - xm, bx = xp - c;
+        const C ay = c - ym, by = yp - c;
+        const C az = c - zm, bz = zp - c;
+        // upwind pair: F > 0 takes (max(D-,0), min(D+,0)); F < 0 (max(D+,0), min(D-,0))
+        const C px = fmaxf(pos ? ax : bx, 0.f), qx = fminf(pos ? bx : ax, 0.f);
+        const C py = fmaxf(pos ? ay : by, 0.f), qy = fminf(pos ? by : ay, 0.f);
+        const C pz = fmaxf(pos ? az : bz, 0.f), qz = fminf(pos ? bz : az, 0.f);
+        const C s = px * px + qx * qx + py * py + qy * qy + pz * pz + qz * qz;
+        return c - (dtdx * f) * __builtin_amdgcn_sqrtf(s);
+    }
+}
+
+template <class S, class FT>
+struct StepArgs {
+    const S *cur;
+    const S *orig;
+    S *nxt;
+    const FT *F;
+    const int32_t *rec;       // work-item records, kItemWords int32 each
+    const int32_t *nitems;    // number of records (device)
+    const int32_t *range;     // batch: [first, end) records of this launch (device), else null
+    const BatchInst *inst;    // batch: grid descriptors (record word 7 = grid), else null
+    typename Codec<S>::C dx, dt, dtdx, scale;
+};
+
+// Slice [w0, w1) of the items [first, end) for this block: contiguous and
+// XCD-aware.  Workgroups are dispatched to the 8 XCDs round-robin (block b
+// on XCD b % 8), so XCD x gets the x-th eighth of the items and its blocks
+// split that eighth into contiguous slices: neighbouring items share an L2.
+__device__ inline void block_slice(int first, int end, int *w0, int *w1) {
+    const int n = max(end - first, 0);
+    const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int gx = gridDim.x >> 3;
+    const int xs = first + static_cast<int>((static_cast<int64_t>(n) * x) >> 3);
+    const int xe = first + static_cast<int>((static_cast<int64_t>(n) * (x + 1)) >> 3);
+    const int per = (xe - xs + gx - 1) / gx;
+    *w0 = min(xs + j * per, xe);
+    *w1 = min(*w0 + per, xe);
+}
+
+constexpr int cpow2(int v) { return v <= 1 ? 1 : 2 * cpow2((v + 1) / 2); }
+constexpr int clog2(int v) { return v <= 1 ? 0 : 1 + clog2(v / 2); }
+
+template <class S, class FT, int TX, int TY, int TZ, int R>
+struct FastCfg {
+    static constexpr int XL = cpow2(R * TX);
+    static constexpr int RP = kBlock / XL;      // grid rows per pass
+    static constexpr int ROWS = TY * TZ;
+    static constexpr int NOWN = ROWS / RP;      // own points per thread
+    static constexpr int NHR = 2 * (TY + TZ);   // halo rows of the y and z faces
+    static constexpr int NHALO = (NHR + RP - 1) / RP;
+    static constexpr int SX = R * TX + 2, SXY = SX * (TY + 2);
+    using C = typename Codec<S>::C;
+    static constexpr size_t lds = sizeof(C) * SXY * (TZ + 2);
+    static_assert(XL <= kBlock && ROWS % RP == 0, "shape does not tile the block");
+    static_assert(RP % TY == 0 || TY % RP == 0, "rows per pass must divide or be divided by TY");
+    static_assert(ROWS <= kBlock, "x-face points exceed two per thread");
+};
+
+// Fast band-step kernel for a compile-time tile shape (TX, TY, TZ) and R tiles
+// per work item.  Every index is a compile-time constant, a per-thread value
+// or a uniform value: global loads and stores take a uniform item base plus a
+// per-thread offset, LDS accesses a per-thread base plus immediates.  Per
+// item, every thread
+//  (1) issues the global loads of its own points (phi and F: rows lr + q*RP of
+//      the item, x = lx), of its y/z halo rows and of at most one x-face
+//      point, all into registers before using any;
+//  (2) stores them to the LDS box; (3) after a barrier evaluates its own
+//      points from the box and stores them.
+// BATCH: the item's grid comes from the descriptor its record names (word 7);
+// PARTIAL: tiles at the high y/z faces may be partial (predicated rows).
+// A neighbour in a band tile is read from the current buffer, one in a tile
+// outside the band from phi (its value frozen for the call), one outside the
+// grid is the clamped point inside the item (zero-gradient boundary).
+template <class S, class FT, bool EXACT, int TX, int TY, int TZ, int R, bool BATCH, bool PARTIAL>
+__global__ __launch_bounds__(kBlock) void upwind_fast_kernel(StepGeom g, StepArgs<S, FT> a) {
+    using K = FastCfg<S, FT, TX, TY, TZ, R>;
+    using C = typename K::C;
+    constexpr int XL = K::XL, RP = K::RP, ROWS = K::ROWS, NOWN = K::NOWN, NHALO = K::NHALO;
+    constexpr int SX = K::SX, SXY = K::SXY;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *box = reinterpret_cast<C *>(smem);
+
+    int first = 0, end = 0;
+    if (a.range) {
+        first = a.range[0];
+        end = a.range[1];
+    } else {
+        end = *a.nitems;
+    }
+    int w0, w1;
+    block_slice(first, end, &w0, &w1);
+
+    const int lane = threadIdx.x & 63;
+    const int lx = threadIdx.x % XL;
+    const int lr = threadIdx.x / XL;
+    const int lt = lx / TX;
+    // own points: row lr + q*RP  ->  (ly, lz) = (ly0 + dly(q), lz0 + dlz(q))
+    const int ly0 = (RP % TY == 0) ? lr % TY : lr;
+    const int lz0 = (RP % TY == 0) ? lr / TY : 0;
+    const int lbase = (lz0 + 1) * SXY + (ly0 + 1) * SX + lx + 1;
+    auto dly = [](int q) { return (RP % TY == 0) ? 0 : (q % (TY / RP)) * RP; };
+    auto dlz = [](int q) { return (RP % TY == 0) ? q * (RP / TY) : q / (TY / RP); };
+    // x-face point of this thread (threads below 2*ROWS): side tid & 1, row tid >> 1
+    const bool xok = threadIdx.x < 2 * ROWS;
+    const int xside = threadIdx.x & 1;
+    const int xly = (threadIdx.x >> 1) % TY, xlz = (threadIdx.x >> 1) / TY;
+
+    for (int w = w0; w < w1; ++w) {
+        int rv = 0;
+        if (lane < kItemWords) rv = a.rec[static_cast<int64_t>(w) * kItemWords + lane];
+        const int t0 = __builtin_amdgcn_readlane(rv, 0);
+        const int len = __builtin_amdgcn_readlane(rv, 1);
+        const uint32_t m0 = __builtin_amdgcn_readlane(rv, 2), m1 = __builtin_amdgcn_readlane(rv, 3);
+        const uint32_t m2 = __builtin_amdgcn_readlane(rv, 4), m3 = __builtin_amdgcn_readlane(rv, 5);
+        const uint32_t mx = __builtin_amdgcn_readlane(rv, 6);
+
+        int nx, ny, nz, ntx, nty, ntiles;
+        int64_t goff = 0;
+        C dtdx = a.dtdx, dx = a.dx, dt = a.dt;
+        if constexpr (BATCH) {
+            const BatchInst &d = a.inst[__builtin_amdgcn_readlane(rv, 7)];
+            nx = d.nx, ny = d.ny, nz = d.nz, ntx = d.ntx, nty = d.nty, ntiles = d.ntiles;
+            goff = d.offset;
+            dtdx = static_cast<C>(d.dtdx);
+            dx = static_cast<C>(d.dx);
+            dt = static_cast<C>(d.dt);
+        } else {
+            nx = g.nx, ny = g.ny, nz = g.nz, ntx = g.ntx, nty = g.nty, ntiles = g.ntiles;
+        }
+        if (t0 < 0 || t0 >= ntiles) continue;  // invalid id: skipped (uniform)
+        const int plane = ny * nx;
+        const int ti0 = t0 % ntx;
+        const int rr = t0 / ntx;
+        const int tj = rr % nty, tk = rr / nty;
+        const int x0 = ti0 * TX, y0 = tj * TY, z0 = tk * TZ;
+        const int W = min(len * TX, nx - x0);
+        const int H = PARTIAL ? min(TY, ny - y0) : TY;
+        const int D = PARTIAL ? min(TZ, nz - z0) : TZ;
+        const int64_t base = goff + (static_cast<int64_t>(z0) * ny + y0) * nx + x0;
+        const S *cur = a.cur + base;
+        const S *orig = a.orig + base;
+        const FT *Fb = a.F + base;
+        S *nxt = a.nxt + base;
+        // faces on the domain boundary: the clamped neighbour lies in the item
+        const int ebits = (y0 == 0 ? 1 : 0) | (y0 + H == ny ? 2 : 0) | (z0 == 0 ? 4 : 0) |
+                          (z0 + D == nz ? 8 : 0);
+        const bool col_ok = lx < W;
+        const int toff = lz0 * plane + ly0 * nx + lx;
+
+        // (1) loads, all issued before any is used
+        S raw[NOWN];
+        FT fv[NOWN];
+#pragma unroll
+        for (int q = 0; q < NOWN; ++q) {
+            const bool ok = col_ok && (!PARTIAL || (ly0 + dly(q) < H && lz0 + dlz(q) < D));
+            if (ok) {
+                const int u = dlz(q) * plane + dly(q) * nx;  // uniform
+                raw[q] = (cur + u)[toff];
+                fv[q] = (Fb + u)[toff];
+            }
+        }
+        S hv[NHALO];
+        int hlds[NHALO];
+        bool hok[NHALO];
+#pragma unroll
+        for (int q = 0; q < NHALO; ++q) {
+            const int h = lr + q * RP;  // y-face rows (2 per z) first, then z-face rows
+            int ly, lz, lyc, lzc, face;
+            bool ok;
+            if (h < 2 * TZ) {
+                lz = h >> 1;
+                face = h & 1;
+                ly = face ? H : -1;
+                lyc = face ? H - 1 : 0;
+                lzc = lz;
+                ok = lz < D;
+            } else {
+                const int hh = h - 2 * TZ;
+                ly = hh >> 1;
+                face = 2 + (hh & 1);
+                lz = (hh & 1) ? D : -1;
+                lzc = (hh & 1) ? D - 1 : 0;
+                lyc = ly;
+                ok = hh < 2 * TY && ly < H;
+            }
+            ok = ok && col_ok;
+            hok[q] = ok;
+            hlds[q] = (lz + 1) * SXY + (ly + 1) * SX + lx + 1;
+            const bool hi = face & 1, zf = face & 2;
+            const bool clamp = (ebits >> (face & 3)) & 1;
+            const uint32_t mk = zf ? (hi ? m3 : m2) : (hi ? m1 : m0);
+            const bool in = clamp || ((mk >> lt) & 1u);
+            const int o = clamp ? (lzc * plane + lyc * nx + lx) : (lz * plane + ly * nx + lx);
+            if (ok && in) hv[q] = cur[o];
+            if (ok && !in) hv[q] = orig[o];
+        }
+        S xv;
+        const bool xrow_ok = xok && (!PARTIAL || (xly < H && xlz < D));
+        const int cx = xside ? (x0 + W < nx ? W : W - 1) : (x0 > 0 ? -1 : 0);
+        {
+            const bool in = (cx >= 0 && cx < W) || ((mx >> xside) & 1u);
+            const int o = xlz * plane + xly * nx + cx;
+            if (xrow_ok && in) xv = cur[o];
+            if (xrow_ok && !in) xv = orig[o];
+        }
+
+        // (2) to LDS
+        if (col_ok) {
+#pragma unroll
+            for (int q = 0; q < NOWN; ++q)
+                if (!PARTIAL || (ly0 + dly(q) < H && lz0 + dlz(q) < D))
+                    box[lbase + dlz(q) * SXY + dly(q) * SX] = Codec<S>::load(raw[q], a.scale);
+        }
+#pragma unroll
+        for (int q = 0; q < NHALO; ++q)
+            if (hok[q]) box[hlds[q]] = Codec<S>::load(hv[q], a.scale);
+        if (xrow_ok)
+            box[(xlz + 1) * SXY + (xly + 1) * SX + (xside ? W + 1 : 0)] = Codec<S>::load(xv, a.scale);
+        __syncthreads();  // box complete
+
+        // (3) update
+        if (col_ok) {
+#pragma unroll
+            for (int q = 0; q < NOWN; ++q) {
+                if (PARTIAL && !(ly0 + dly(q) < H && lz0 + dlz(q) < D)) continue;
+                const int o = lbase + dlz(q) * SXY + dly(q) * SX;
+                const C f = static_cast<C>(fv[q]);
+                const C v = upwind_point<C, EXACT>(box[o], box[o - 1], box[o + 1], box[o - SX],
+                                                   box[o + SX], box[o - SXY], box[o + SXY], f, dx,
+                                                   dt, dtdx);
+                const S out = (f == C(0)) ? raw[q] : Codec<S>::store(v, a.scale);
+                (nxt + dlz(q) * plane + dly(q) * nx)[toff] = out;
+            }
+        }
+        __syncthreads();  // box free for the next item
+    }
+}
+
+}  // namespace ls

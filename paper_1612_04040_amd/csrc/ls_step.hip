@@ -18,89 +18,9 @@
 
 #include "ls_compact.h"
 #include "ls_stats.h"
+#include "ls_stencil.h"
 
 namespace ls {
-
-constexpr int kMaxOwn = 16;   // grid points owned by one thread per item
-constexpr int kMaxHalo = 8;   // y/z halo points loaded by one thread per item
-constexpr int kMaxRun = 32;   // tiles per work item (4*kMaxRun + 2 <= kBlock)
-
-struct StepGeom {
-    int nx, ny, nz;
-    int tx, ty, tz;
-    int ntx, nty, ntz;
-    int ntiles;  // tiles of the grid (the list capacity)
-    int R;       // tiles per work item (x-run length cap)
-    int xl;      // threads per grid row (power of two >= R*tx)
-    int xl_log;  // log2(xl)
-    int sx, sy;  // LDS box strides: sx = R*tx + 2, sy = ty + 2
-};
-
-// Fast form (f32, f16s): unscaled differences, dt/dx folded into one factor.
-// Exact form (f64): the definition term by term (D = difference / dx, the
-// squares summed x, then y, then z), no contraction.
-template <class C, bool EXACT>
-__device__ inline C upwind_point(C c, C xm, C xp, C ym, C yp, C zm, C zp, C f, C dx, C dt,
-                                 C dtdx) {
-    if constexpr (EXACT) {
-#pragma clang fp contract(off)
-        const C dmx = (c - xm) / dx, dpx = (xp - c) / dx;
-        const C dmy = (c - ym) / dx, dpy = (yp - c) / dx;
-        const C dmz = (c - zm) / dx, dpz = (zp - c) / dx;
-        const C zero = C(0);
-        auto mx = [](C a, C b) { return a > b ? a : b; };
-        auto mn = [](C a, C b) { return a < b ? a : b; };
-        if (f > zero) {
-            const C px = mx(dmx, zero) * mx(dmx, zero) + mn(dpx, zero) * mn(dpx, zero);
-            const C py = mx(dmy, zero) * mx(dmy, zero) + mn(dpy, zero) * mn(dpy, zero);
-            const C pz = mx(dmz, zero) * mx(dmz, zero) + mn(dpz, zero) * mn(dpz, zero);
-            const C g = sqrt((px + py) + pz);
-            return c - dt * f * g;
-        } else {
-            const C qx = mx(dpx, zero) * mx(dpx, zero) + mn(dmx, zero) * mn(dmx, zero);
-            const C qy = mx(dpy, zero) * mx(dpy, zero) + mn(dmy, zero) * mn(dmy, zero);
-            const C qz = mx(dpz, zero) * mx(dpz, zero) + mn(dmz, zero) * mn(dmz, zero);
-            const C g = sqrt((qx + qy) + qz);
-            return c - dt * f * g;
-        }
-    } else {
-        const bool pos = f > C(0);
-        const C ax = c - xm, bx = xp - c;
-        const C ay = c - ym, by = yp - c;
-        const C az = c - zm, bz = zp - c;
-        // upwind pair: F > 0 takes (max(D-,0), min(D+,0)); F < 0 (max(D+,0), min(D-,0))
-        const C px = fmaxf(pos ? ax : bx, 0.f), qx = fminf(pos ? bx : ax, 0.f);
-        const C py = fmaxf(pos ? ay : by, 0.f), qy = fminf(pos ? by : ay, 0.f);
-        const C pz = fmaxf(pos ? az : bz, 0.f), qz = fminf(pos ? bz : az, 0.f);
-        const C s = px * px + qx * qx + py * py + qy * qy + pz * pz + qz * qz;
-        return c - (dtdx * f) * __builtin_amdgcn_sqrtf(s);
-    }
-}
-
-template <class S, class FT>
-struct StepArgs {
-    const S *cur;
-    const S *orig;
-    S *nxt;
-    const FT *F;
-    const int32_t *rec;     // work-item records, kItemWords int32 each
-    const int32_t *nitems;  // number of records (device)
-    typename Codec<S>::C dx, dt, dtdx, scale;
-};
-
-// Slice of the item list of this block: contiguous, XCD-aware.
-// Workgroups are dispatched to the 8 XCDs round-robin (block b on XCD b % 8),
-// so XCD x gets the x-th eighth of the list and its blocks split that eighth
-// into contiguous slices: neighbouring items share an L2.
-__device__ inline void block_slice(int nitems, int *w0, int *w1) {
-    const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
-    const int gx = gridDim.x >> 3;
-    const int xs = static_cast<int>((static_cast<int64_t>(nitems) * x) >> 3);
-    const int xe = static_cast<int>((static_cast<int64_t>(nitems) * (x + 1)) >> 3);
-    const int per = (xe - xs + gx - 1) / gx;
-    *w0 = min(xs + j * per, xe);
-    *w1 = min(*w0 + per, xe);
-}
 
 // One persistent block walks its slice of work items.  Per item:
 //  (1) every thread issues the global loads of its own grid points (phi and
@@ -110,8 +30,6 @@ __device__ inline void block_slice(int nitems, int *w0, int *w1) {
 //      evaluates its own points from the box and stores them.
 // Thread t owns column lx = t mod xl of rows lr + q*rp (rows enumerate (y, z)
 // of a full tile, y fastest), so its row offsets are fixed for the launch.
-constexpr int cpow2(int v) { return v <= 1 ? 1 : 2 * cpow2((v + 1) / 2); }
-constexpr int clog2(int v) { return v <= 1 ? 0 : 1 + clog2(v / 2); }
 
 // Tile shape of a launch: compile-time when CTX > 0 (every index below then
 // folds to constants), else taken from g at run time.
@@ -135,7 +53,7 @@ __global__ __launch_bounds__(kBlock) void upwind_kernel(StepGeom g, StepArgs<S, 
 
     const int nitems = *a.nitems;
     int w0, w1;
-    block_slice(nitems, &w0, &w1);
+    block_slice(0, nitems, &w0, &w1);
 
     const int TX = SH::tx(g), TY = SH::ty(g), TZ = SH::tz(g);
     const int lx = threadIdx.x & (SH::xl(g) - 1);
@@ -282,240 +200,6 @@ __global__ __launch_bounds__(kBlock) void upwind_kernel(StepGeom g, StepArgs<S, 
     }
 }
 
-// Fast kernel for a compile-time tile shape (TX, TY, TZ), R tiles per work
-// item, and grids whose y and z extents are whole tiles (only the x extent of
-// an item varies: W = len*TX, or less at the high x face).  Every index is a
-// per-thread constant or a uniform value: global loads and stores take a
-// uniform item base plus a per-thread offset, LDS accesses a per-thread base
-// plus immediates, and the only per-item lane predicate is lx < W.
-//
-// Software pipeline: while item w is evaluated from LDS, the global loads of
-// item w+1 (into registers) and the record of item w+2 are in flight, so each
-// persistent block always has memory traffic outstanding.  Records are read
-// with vector loads (lane k holds word k) so that waiting for LDS never waits
-// for them.  Same results as upwind_kernel, bit for bit.
-template <class S, class FT, bool EXACT, int TX, int TY, int TZ, int R>
-struct FastCfg {
-    static constexpr int XL = cpow2(R * TX);
-    static constexpr int RP = kBlock / XL;      // grid rows per pass
-    static constexpr int ROWS = TY * TZ;
-    static constexpr int NOWN = ROWS / RP;      // own points per thread
-    static constexpr int NHR = 2 * (TY + TZ);   // halo rows of the y and z faces
-    static constexpr int NHALO = (NHR + RP - 1) / RP;
-    static constexpr int SX = R * TX + 2, SXY = SX * (TY + 2);
-    using C = typename Codec<S>::C;
-    static constexpr bool RAW = sizeof(S) != sizeof(C);  // keep stored bits for F == 0
-    static constexpr size_t box_bytes = sizeof(C) * SXY * (TZ + 2);
-    static constexpr size_t f_bytes = sizeof(FT) * NOWN * kBlock;
-    static constexpr size_t raw_bytes = RAW ? sizeof(S) * NOWN * kBlock : 0;
-    static constexpr size_t lds = box_bytes + f_bytes + raw_bytes;
-    static_assert(XL <= kBlock && ROWS % RP == 0, "shape does not tile the block");
-    static_assert(RP % TY == 0 || TY % RP == 0, "rows per pass must divide or be divided by TY");
-    static_assert(ROWS <= kBlock, "x-face points exceed two per thread");
-    static_assert(box_bytes % 16 == 0 || true, "");
-};
-
-// Geometry of one work item of the fast kernel (all uniform).  The record's
-// neighbour masks stay in the record register (lane k = word k) and are read
-// with readlane where used, so no per-lane selection ever indexes memory.
-struct FastItem {
-    bool valid;
-    int x0, W, lo_x_in, hi_x_in;
-    int ebits;  // bit f set: face f (y-, y+, z-, z+) lies on the domain boundary
-    int64_t base;
-};
-
-template <int TX, int TY, int TZ>
-__device__ inline FastItem fast_decode(const StepGeom &g, int rv) {
-    FastItem it;
-    const int t0 = __builtin_amdgcn_readlane(rv, 0);
-    it.valid = t0 >= 0 && t0 < g.ntiles;
-    const int tt = it.valid ? t0 : 0;
-    const int len = __builtin_amdgcn_readlane(rv, 1);
-    const int ti0 = tt % g.ntx;
-    const int rr = tt / g.ntx;
-    const int tj = rr % g.nty, tk = rr / g.nty;
-    it.x0 = ti0 * TX;
-    const int y0 = tj * TY, z0 = tk * TZ;
-    it.W = min(len * TX, g.nx - it.x0);
-    it.base = (static_cast<int64_t>(z0) * g.ny + y0) * g.nx + it.x0;
-    it.ebits = (y0 == 0 ? 1 : 0) | (y0 + TY == g.ny ? 2 : 0) | (z0 == 0 ? 4 : 0) |
-               (z0 + TZ == g.nz ? 8 : 0);
-    it.lo_x_in = it.x0 > 0 ? -1 : 0;                    // clamped x- neighbour column
-    it.hi_x_in = it.x0 + it.W < g.nx ? it.W : it.W - 1;  // clamped x+ neighbour column
-    return it;
-}
-
-template <class S, class FT, bool EXACT, int TX, int TY, int TZ, int R>
-__global__ __launch_bounds__(kBlock) void upwind_fast_kernel(StepGeom g, StepArgs<S, FT> a) {
-    using K = FastCfg<S, FT, EXACT, TX, TY, TZ, R>;
-    using C = typename K::C;
-    constexpr int XL = K::XL, RP = K::RP, ROWS = K::ROWS, NOWN = K::NOWN, NHALO = K::NHALO;
-    constexpr int SX = K::SX, SXY = K::SXY;
-
-    extern __shared__ __align__(16) unsigned char smem[];
-    C *box = reinterpret_cast<C *>(smem);
-    FT *fbox = reinterpret_cast<FT *>(smem + K::box_bytes);
-    S *rbox = reinterpret_cast<S *>(smem + K::box_bytes + K::f_bytes);
-
-    const int nitems = *a.nitems;
-    int w0, w1;
-    block_slice(nitems, &w0, &w1);
-
-    const int lane = threadIdx.x & 63;
-    const int lx = threadIdx.x % XL;
-    const int lr = threadIdx.x / XL;
-    const int lt = lx / TX;
-    const int nx = g.nx, plane = g.ny * g.nx;
-
-    // own points: row lr + q*RP  ->  (ly, lz) = (ly0 + dly(q), lz0 + dlz(q))
-    const int ly0 = (RP % TY == 0) ? lr % TY : lr;
-    const int lz0 = (RP % TY == 0) ? lr / TY : 0;
-    const int toff = lz0 * plane + ly0 * nx + lx;
-    const int lbase = (lz0 + 1) * SXY + (ly0 + 1) * SX + lx + 1;
-    auto dly = [](int q) { return (RP % TY == 0) ? 0 : (q % (TY / RP)) * RP; };
-    auto dlz = [](int q) { return (RP % TY == 0) ? q * (RP / TY) : q / (TY / RP); };
-
-    // halo rows of this thread: h = lr + q*RP (y faces first, then z faces)
-    int hoff[NHALO], hoffc[NHALO], hlds[NHALO], hface[NHALO];
-#pragma unroll
-    for (int q = 0; q < NHALO; ++q) {
-        const int h = lr + q * RP;
-        int ly, lz, lyc, lzc, face;
-        if (h < 2 * TZ) {
-            lz = h >> 1;
-            face = h & 1;
-            ly = face ? TY : -1;
-            lyc = face ? TY - 1 : 0;  // clamped into the item at a domain face
-            lzc = lz;
-        } else {
-            const int hh = h - 2 * TZ;
-            ly = hh >> 1;
-            face = 2 + (hh & 1);
-            lz = (hh & 1) ? TZ : -1;
-            lzc = (hh & 1) ? TZ - 1 : 0;
-            lyc = ly;
-            if (hh >= 2 * TY) face = -1;
-        }
-        hface[q] = face;
-        hoff[q] = lz * plane + ly * nx + lx;
-        hoffc[q] = lzc * plane + lyc * nx + lx;
-        hlds[q] = (lz + 1) * SXY + (ly + 1) * SX + lx + 1;
-    }
-    // x-face point of this thread (threads below 2*ROWS): side tid & 1, row tid >> 1
-    const bool xok = threadIdx.x < 2 * ROWS;
-    const int xside = threadIdx.x & 1;
-    const int xrow = threadIdx.x >> 1;
-    const int xoff = (xrow / TY) * plane + (xrow % TY) * nx;
-    const int xlds = (xrow / TY + 1) * SXY + (xrow % TY + 1) * SX;
-
-    S raw[NOWN];
-    FT fv[NOWN];
-    S hv[NHALO];
-    S xv;
-
-    auto issue = [&](const FastItem &it, int rv) __attribute__((always_inline)) {
-        const uint32_t m0 = __builtin_amdgcn_readlane(rv, 2), m1 = __builtin_amdgcn_readlane(rv, 3);
-        const uint32_t m2 = __builtin_amdgcn_readlane(rv, 4), m3 = __builtin_amdgcn_readlane(rv, 5);
-        const uint32_t mx = __builtin_amdgcn_readlane(rv, 6);
-        const S *cur = a.cur + it.base;
-        const S *orig = a.orig + it.base;
-        const FT *Fb = a.F + it.base;
-        if (lx < it.W) {
-#pragma unroll
-            for (int q = 0; q < NOWN; ++q) {
-                const int u = dlz(q) * plane + dly(q) * nx;  // uniform
-                raw[q] = (cur + u)[toff];
-                fv[q] = (Fb + u)[toff];
-            }
-#pragma unroll
-            for (int q = 0; q < NHALO; ++q) {
-                const int face = hface[q];
-                if (face >= 0) {
-                    // face is per thread: select without indexing (no scratch)
-                    const bool hi = face & 1, zf = face & 2;
-                    const bool clamp = (it.ebits >> face) & 1;
-                    const uint32_t mk = zf ? (hi ? m3 : m2) : (hi ? m1 : m0);
-                    const bool in = clamp || ((mk >> lt) & 1u);
-                    const int o = clamp ? hoffc[q] : hoff[q];
-                    if (in)
-                        hv[q] = cur[o];
-                    else
-                        hv[q] = orig[o];
-                }
-            }
-        }
-        if (xok) {
-            const int cx = xside ? it.hi_x_in : it.lo_x_in;
-            const bool in = (cx >= 0 && cx < it.W) || ((mx >> xside) & 1u);
-            if (in)
-                xv = cur[xoff + cx];
-            else
-                xv = orig[xoff + cx];
-        }
-    };
-    auto stage = [&](const FastItem &it) __attribute__((always_inline)) {
-        if (lx < it.W) {
-#pragma unroll
-            for (int q = 0; q < NOWN; ++q) {
-                box[lbase + dlz(q) * SXY + dly(q) * SX] = Codec<S>::load(raw[q], a.scale);
-                fbox[q * kBlock + threadIdx.x] = fv[q];
-                if constexpr (K::RAW) rbox[q * kBlock + threadIdx.x] = raw[q];
-            }
-#pragma unroll
-            for (int q = 0; q < NHALO; ++q)
-                if (hface[q] >= 0) box[hlds[q]] = Codec<S>::load(hv[q], a.scale);
-        }
-        if (xok) box[xlds + (xside ? it.W + 1 : 0)] = Codec<S>::load(xv, a.scale);
-    };
-    auto compute = [&](const FastItem &it) __attribute__((always_inline)) {
-        S *nxt = a.nxt + it.base;
-        if (lx < it.W) {
-#pragma unroll
-            for (int q = 0; q < NOWN; ++q) {
-                const int o = lbase + dlz(q) * SXY + dly(q) * SX;
-                const C c = box[o];
-                const C f = static_cast<C>(fbox[q * kBlock + threadIdx.x]);
-                const C v = upwind_point<C, EXACT>(c, box[o - 1], box[o + 1], box[o - SX],
-                                                   box[o + SX], box[o - SXY], box[o + SXY], f,
-                                                   a.dx, a.dt, a.dtdx);
-                S keep;
-                if constexpr (K::RAW)
-                    keep = rbox[q * kBlock + threadIdx.x];
-                else
-                    keep = Codec<S>::store(c, a.scale);  // identity codec: the stored bits
-                const S out = (f == C(0)) ? keep : Codec<S>::store(v, a.scale);
-                (nxt + dlz(q) * plane + dly(q) * nx)[toff] = out;
-            }
-        }
-    };
-    auto load_rec = [&](int w) __attribute__((always_inline)) {
-        int v = -1;
-        if (w < w1 && lane < kItemWords) v = a.rec[static_cast<int64_t>(w) * kItemWords + lane];
-        return v;
-    };
-
-    if (w0 >= w1) return;  // uniform
-    int rv = load_rec(w0);
-    FastItem cur_it = fast_decode<TX, TY, TZ>(g, rv);
-    if (cur_it.valid) issue(cur_it, rv);
-    rv = load_rec(w0 + 1);
-    for (int w = w0; w < w1; ++w) {
-        if (cur_it.valid) stage(cur_it);
-        __syncthreads();  // box complete
-        FastItem nxt_it;
-        nxt_it.valid = false;
-        if (w + 1 < w1) {
-            nxt_it = fast_decode<TX, TY, TZ>(g, rv);
-            if (nxt_it.valid) issue(nxt_it, rv);
-            rv = load_rec(w + 2);
-        }
-        if (cur_it.valid) compute(cur_it);
-        __syncthreads();  // box free for the next item
-        cur_it = nxt_it;
-    }
-}
-
 // Copies the band points of src into dst (used when nsteps is odd).
 template <class S>
 __global__ __launch_bounds__(kBlock) void band_copy_kernel(StepGeom g, const S *__restrict__ src,
@@ -524,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void band_copy_kernel(StepGeom g, const S *
                                                            const int32_t *nitems_dev) {
     const int nitems = *nitems_dev;
     int w0, w1;
-    block_slice(nitems, &w0, &w1);
+    block_slice(0, nitems, &w0, &w1);
     const int lx = threadIdx.x & (g.xl - 1);
     const int lr = threadIdx.x >> g.xl_log;
     const int rp = kBlock >> g.xl_log;
@@ -643,10 +327,11 @@ template <class S, class FT, bool EXACT>
 static UpwindFn<S, FT, EXACT> select_upwind_kernel(const StepGeom &sg, int nown, int nhalo,
                                                    size_t *lds) {
     const bool whole_yz = sg.ny % sg.ty == 0 && sg.nz % sg.tz == 0;
-#define LS_FAST(TX_, TY_, TZ_, R_)                                                   \
-    if (whole_yz && sg.tx == TX_ && sg.ty == TY_ && sg.tz == TZ_ && sg.R == R_) {    \
-        *lds = FastCfg<S, FT, EXACT, TX_, TY_, TZ_, R_>::lds;                        \
-        return upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_>;                  \
+#define LS_FAST(TX_, TY_, TZ_, R_)                                                          \
+    if (sg.tx == TX_ && sg.ty == TY_ && sg.tz == TZ_ && sg.R == R_) {                       \
+        *lds = FastCfg<S, FT, TX_, TY_, TZ_, R_>::lds;                                      \
+        if (whole_yz) return upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, false>; \
+        return upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, true>;             \
     }
     LS_FAST(8, 8, 8, 4)
     LS_FAST(8, 8, 8, 2)
@@ -747,6 +432,8 @@ static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const 
     args.F = F;
     args.rec = items;
     args.nitems = nitems;
+    args.range = nullptr;
+    args.inst = nullptr;
     args.orig = phi;
     args.dx = dx;
     args.dt = dt;
@@ -772,6 +459,17 @@ static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const 
 }
 
 int fill_zero(uint8_t *p, int64_t bytes, hipStream_t stream);  // ls_band.hip
+
+// One FP32 step of the plan the workspace holds (the band of the last build),
+// phi updated in place through scratch.
+int plan_step_f32(float *phi, const float *F, const Geom &G, float dx, float dt, float *scratch,
+                  uint8_t *ws, hipStream_t stream) {
+    StepGeom sg;
+    size_t lds = 0;
+    int rc = make_step_geom<float>(G, &sg, &lds);
+    if (rc != LS_OK) return rc;
+    return upwind_launch<float, float>(phi, F, 1.0f, G, sg, dx, dt, 1, scratch, ws, stream);
+}
 
 template <class S, class FT>
 static int upwind_step(S *phi, const FT *F, typename Codec<S>::C scale, const ls_grid *grid,
@@ -834,7 +532,8 @@ template <class S>
 int band_rebuild(const S *phi, typename Codec<S>::C scale, const ls_grid *grid,
                  typename Codec<S>::C gamma, const int32_t *prev_tiles,
                  const int32_t *prev_ntiles_dev, int32_t *tiles, int64_t capacity,
-                 int32_t *ntiles_dev, void *workspace, int64_t ws_bytes, void *stream_);
+                 int32_t *ntiles_dev, void *workspace, int64_t ws_bytes, void *stream_,
+                 bool flags_valid);
 
 __global__ void accumulate_kernel(int64_t *acc, const int32_t *count, int nsteps) {
     if (threadIdx.x == 0 && blockIdx.x == 0)
@@ -888,7 +587,8 @@ static int band_run(S *phi, const FT *F, typename Codec<S>::C scale, const ls_gr
                                workspace, ws_bytes, stream_);
         else
             rc = band_rebuild<S>(phi, scale, grid, gamma, lists[cur ^ 1], counts[cur ^ 1],
-                                 lists[cur], capacity, counts[cur], workspace, ws_bytes, stream_);
+                                 lists[cur], capacity, counts[cur], workspace, ws_bytes, stream_,
+                                 true);
         if (rc != LS_OK) return rc;
         if (tile_steps_dev) {
             hipLaunchKernelGGL(accumulate_kernel, dim3(1), dim3(64), 0, stream, tile_steps_dev,

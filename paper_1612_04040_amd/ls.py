@@ -38,6 +38,19 @@ class ls_tuning(ctypes.Structure):
     _fields_ = [("run_width", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
 
 
+class ls_instance(ctypes.Structure):
+    _fields_ = [("grid", ls_grid), ("offset", ctypes.c_int64), ("dx", ctypes.c_float),
+                ("dt", ctypes.c_float), ("gamma", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
+def instances(items):
+    """ctypes array of ls_instance from (dims, tile, offset, dx, dt, gamma) tuples."""
+    arr = (ls_instance * len(items))()
+    for k, (dims, tile, offset, dx, dt, gamma) in enumerate(items):
+        arr[k] = ls_instance(grid(dims, tile), int(offset), float(dx), float(dt), float(gamma), 0)
+    return arr
+
+
 def grid(dims, tile=(8, 8, 8)):
     """ls_grid for dims = (nx, ny, nz) and tile = (tx, ty, tz)."""
     nx, ny, nz = (int(v) for v in dims)
@@ -77,10 +90,29 @@ _SIGNATURES = {
     "ls_get_tuning": (_I32, [ctypes.c_void_p]),
     "ls_upwind_launch_info": (_I32, [_G, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
                                      ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "ls_batch_workspace_bytes": (_I64, [_VP, _I32]),
+    "ls_batch_layout": (_I32, [_VP, _I32, _VP, _VP]),
+    "ls_batch_setup": (_I32, [_VP, _I32, _VP, _I64, _VP]),
+    "ls_batch_run_f32": (_I32, [_VP, _I32, _VP, _VP, _VP, _I32, _I32, _VP, _VP, _I64, _VP]),
+    "ls_batch_band": (_I32, [_VP, _I32, _VP, _I64, _VP, _VP]),
+    "ls_graph_begin": (_I32, [_VP]),
+    "ls_graph_end": (_I32, [_VP, _VP]),
+    "ls_graph_launch": (_I32, [_VP, _VP]),
+    "ls_graph_destroy": (_I32, [_VP]),
     "ls_stats_enable": (_I32, [_I32]),
     "ls_copy_f32": (_I32, [_VP, _VP, _I64, _VP]),
     "ls_stats_read": (_I32, [_I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                              ctypes.POINTER(_F64)]),
+    "ls_closure_param_count": (_I64, []),
+    "ls_closure_workspace_bytes": (_I64, [_G]),
+    "ls_restrict4_f32": (_I32, [_VP, _G, _VP, _VP]),
+    "ls_closure_forward_f32": (_I32, [_VP, _VP, _G, _F32, _F32, _F32, _F32, _VP, _VP, _VP, _VP,
+                                      _I64, _VP, _VP, _VP, _I64, _VP, _I64, _VP]),
+    "ls_closure_backward_f32": (_I32, [_VP, _VP, _VP, _G, _F32, _F32, _F32, _F32, _VP, _VP, _VP,
+                                       _VP, _I64, _VP, _VP, _VP, _I64, _VP, _I64, _VP]),
+    "ls_adam_step": (_I32, [_VP, _VP, _VP, _VP, _I64, _F32, _F32, _F32, _F32, _I32, _VP]),
+    "ls_closure_run_f32": (_I32, [_VP, _VP, _G, _F32, _F32, _F32, _F32, _VP, _I32, _I32, _VP,
+                                  _I64, _VP, _VP, _VP, _VP, _I64, _VP, _I64, _VP]),
 }
 
 LS_KERNEL_UPWIND = 0
@@ -279,3 +311,97 @@ def ls_upwind_launch_info(g, precision):
 
 def ls_copy_f32(dst, src, n, stream=None):
     return _check(lib().ls_copy_f32(_ptr(dst), _ptr(src), int(n), _stream(stream)))
+
+
+def ls_batch_workspace_bytes(inst, n):
+    return _check(lib().ls_batch_workspace_bytes(ctypes.addressof(inst), n))
+
+
+def ls_batch_layout(inst, n):
+    """(tile_base list, total tiles) of the batch layout."""
+    base = (ctypes.c_int64 * n)()
+    total = ctypes.c_int64()
+    _check(lib().ls_batch_layout(ctypes.addressof(inst), n, ctypes.addressof(base),
+                                 ctypes.byref(total)))
+    return list(base), total.value
+
+
+def ls_batch_setup(inst, n, workspace, workspace_bytes, stream=None):
+    return _check(lib().ls_batch_setup(ctypes.addressof(inst), n, _ptr(workspace), workspace_bytes,
+                                       _stream(stream)))
+
+
+def ls_batch_run_f32(inst, n, phi, F, scratch, nsteps, window, tile_steps_dev, workspace,
+                     workspace_bytes, stream=None):
+    return _check(lib().ls_batch_run_f32(ctypes.addressof(inst), n, _ptr(phi), _ptr(F),
+                                         _ptr(scratch), nsteps, window, _ptr(tile_steps_dev),
+                                         _ptr(workspace), workspace_bytes, _stream(stream)))
+
+
+def ls_batch_band(inst, n, workspace, workspace_bytes):
+    """(device address of the last band list, device address of its length)."""
+    t, c = ctypes.c_void_p(), ctypes.c_void_p()
+    _check(lib().ls_batch_band(ctypes.addressof(inst), n, _ptr(workspace), workspace_bytes,
+                               ctypes.byref(t), ctypes.byref(c)))
+    return t.value, c.value
+
+
+def ls_graph_begin(stream):
+    return _check(lib().ls_graph_begin(_stream(stream)))
+
+
+def ls_graph_end(stream):
+    h = ctypes.c_void_p()
+    _check(lib().ls_graph_end(_stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def ls_graph_launch(graph, stream=None):
+    return _check(lib().ls_graph_launch(graph, _stream(stream)))
+
+
+def ls_graph_destroy(graph):
+    return _check(lib().ls_graph_destroy(graph))
+
+
+def ls_closure_param_count():
+    return int(lib().ls_closure_param_count())
+
+
+def ls_closure_workspace_bytes(g):
+    return _check(lib().ls_closure_workspace_bytes(_g(g)))
+
+
+def ls_restrict4_f32(fine, fine_grid, coarse, stream=None):
+    return _check(lib().ls_restrict4_f32(_ptr(fine), _g(fine_grid), _ptr(coarse), _stream(stream)))
+
+
+def ls_closure_forward_f32(phi, F, g, dx, dt, gamma, fmax, params, r, plain, tiles, capacity,
+                           ntiles_dev, scratch, ws, ws_bytes, cws, cws_bytes, stream=None):
+    return _check(lib().ls_closure_forward_f32(
+        _ptr(phi), _ptr(F), _g(g), dx, dt, gamma, fmax, _ptr(params), _ptr(r), _ptr(plain),
+        _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(scratch), _ptr(ws), ws_bytes, _ptr(cws),
+        cws_bytes, _stream(stream)))
+
+
+def ls_closure_backward_f32(phi, target, F, g, dx, dt, gamma, fmax, params, grad, loss_dev, tiles,
+                            capacity, ntiles_dev, scratch, ws, ws_bytes, cws, cws_bytes,
+                            stream=None):
+    return _check(lib().ls_closure_backward_f32(
+        _ptr(phi), _ptr(target), _ptr(F), _g(g), dx, dt, gamma, fmax, _ptr(params), _ptr(grad),
+        _ptr(loss_dev), _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(scratch), _ptr(ws),
+        ws_bytes, _ptr(cws), cws_bytes, _stream(stream)))
+
+
+def ls_adam_step(params, grad, m, v, n, lr, beta1, beta2, eps, t, stream=None):
+    return _check(lib().ls_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(n), lr,
+                                     beta1, beta2, eps, int(t), _stream(stream)))
+
+
+def ls_closure_run_f32(phi, F, g, dx, dt, gamma, fmax, params, nsteps, window, tiles, capacity,
+                       ntiles_dev, fallbacks_dev, scratch, ws, ws_bytes, cws, cws_bytes,
+                       stream=None):
+    return _check(lib().ls_closure_run_f32(
+        _ptr(phi), _ptr(F), _g(g), dx, dt, gamma, fmax, _ptr(params), int(nsteps), int(window),
+        _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(fallbacks_dev), _ptr(scratch), _ptr(ws),
+        ws_bytes, _ptr(cws), cws_bytes, _stream(stream)))

@@ -278,3 +278,40 @@ def ellipsoid_batch(count=256, nmin=32, nmax=192, seed=4, steps=100, base=64, si
         dt = float(np.float32(stable_dt(F, dx)))
         out.append(Instance(n, phi, F, dx, dt, float(np.float32(6 * dx))))
     return out
+
+
+class ClosureCase:
+    """One closure problem: 1-4 spheres (radii U(0.1, 0.2), centres
+    U(0.25, 0.75)^3) and F = a prod_d sin(2 pi k_d x_d + p_d) + b with
+    k_d in {1, 2}, a in [0.3, 1], b in [-0.5, 0.5]; the same analytic fields
+    sampled on a fine grid and on the grid `ratio` times coarser (both
+    cell-centred on [0, 1]^3).  dt_fine = 0.5 dx_fine / max|F| (FP32),
+    dt_coarse = ratio * dt_fine (the same CFL number)."""
+
+    def __init__(self, seed, n_fine=512, ratio=4):
+        rng = np.random.default_rng(seed)
+        count = int(rng.integers(1, 5))
+        self.seed = seed
+        self.centers = rng.uniform(0.25, 0.75, size=(count, 3))
+        self.radii = rng.uniform(0.1, 0.2, size=count)
+        self.k = tuple(int(v) for v in rng.integers(1, 3, size=3))
+        self.phase = tuple(float(v) for v in rng.uniform(0, 2 * np.pi, size=3))
+        self.amp = float(rng.uniform(0.3, 1.0))
+        self.bias = float(rng.uniform(-0.5, 0.5))
+        self.n_fine, self.ratio = n_fine, ratio
+        self.n_coarse = n_fine // ratio
+        self.dx_fine = 1.0 / n_fine
+        self.dx_coarse = ratio / n_fine
+        # max|F| over the continuum bounds every sample; the same scalar serves both grids
+        self.fmax = float(np.float32(self.amp + abs(self.bias)))
+        self.dt_fine = float(np.float32(0.5 * self.dx_fine / self.fmax))
+        self.dt_coarse = float(np.float32(ratio * self.dt_fine))
+        self.gamma_fine = float(np.float32(6 * self.dx_fine))
+        self.gamma_coarse = float(np.float32(6 * self.dx_coarse))
+
+    def phi(self, n):
+        return sphere_union((n, n, n), 1.0 / n, self.centers, self.radii, dtype=np.float32)
+
+    def F(self, n):
+        return sinusoid3((n, n, n), 1.0 / n, amp=self.amp, k=self.k, phase=self.phase,
+                         bias=self.bias, dtype=np.float32)

@@ -180,3 +180,25 @@ def test_rebuild_errors():
     bad = list(base)
     bad[6] = 3
     assert _status(ls.ls_band_rebuild_f32, *bad) == ls.LS_ERR_CAPACITY
+
+
+def test_batch_layout_host():
+    """Layout: grids ordered by tile shape, tile bases cumulative; errors."""
+    items = [((20, 20, 20), (16, 4, 4), 0, 0.05, 0.02, 0.3),
+             ((17, 9, 8), (8, 8, 8), 8000, 0.05, 0.02, 0.3),
+             ((33, 33, 33), (16, 4, 4), 9280, 0.03, 0.01, 0.2)]
+    inst = ls.instances(items)
+    base, total = ls.ls_batch_layout(inst, 3)
+    t = [ls.ls_grid_tiles(ls.grid(d, tl)) for d, tl, *_ in items]
+    assert total == sum(t)
+    # 8x8x8 sorts before 16x4x4: grid 1 first, then grids 0 and 2 in order
+    assert base == [t[1], 0, t[1] + t[0]]
+    assert ls.ls_batch_workspace_bytes(inst, 3) > 0
+    bad = ls.instances([items[0], (items[1][0], items[1][1], 10, 0.05, 0.02, 0.3)])
+    with pytest.raises(ls.LsError):  # overlapping grids
+        ls.ls_batch_layout(bad, 2)
+    bad = ls.instances([((20, 20, 20), (5, 3, 2), 0, 0.05, 0.02, 0.3)])
+    with pytest.raises(ls.LsError) as e:  # no batched kernel for this shape
+        ls.ls_batch_layout(bad, 1)
+    assert e.value.status == ls.LS_ERR_UNSUPPORTED
+    assert ls.lib().ls_graph_begin(None) == ls.LS_ERR_ARG

@@ -1,0 +1,207 @@
+"""The learned closure on the GPU against the FP64 reference.
+
+* band lists of the closure calls equal the oracle's, bit for bit;
+* the network output r on the active tiles and the gradient of the loss with
+  respect to every parameter match the FP64 reference evaluated on the same
+  BF16-rounded weights and features (relative L2 <= 2e-2, cosine >= 0.999);
+* with the last layer zero the corrected run equals the plain band driver
+  (value for value: the sign of a zero may differ);
+* a correction above 1/2 makes every active tile fall back to the plain step,
+  and an accepted constant correction adds exactly dx/4 on the active tiles;
+* Adam and the restriction match the reference.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import closure as CL
+from gpu_util import dev, fp32_step_bound, host, report, to_dev
+from paper_1612_04040_amd import closure as C
+from paper_1612_04040_amd import workloads as W
+from paper_1612_04040_amd.band import BandGrid
+
+pytestmark = pytest.mark.gpu
+
+TILE = (8, 8, 8)
+
+
+def bf16(a):
+    """Round to the nearest BF16 value (ties to even), returned as float64."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _case(n=48, seed=7):
+    wl = W.three_spheres_f32(n, 1, seed=seed)
+    fmax = float(np.max(np.abs(wl.F)))
+    return wl, fmax
+
+
+def _params(seed, last_scale=0.3):
+    rng = np.random.default_rng(seed)
+    p = C.unflatten(C.init_params(rng).astype(np.float64))
+    p["w2"] = rng.standard_normal(p["w2"].shape) * last_scale / np.sqrt(27 * 16)
+    p["b0"] = rng.standard_normal(16) * 0.1
+    p["b1"] = rng.standard_normal(16) * 0.1
+    p["b2"] = rng.standard_normal(1) * 0.05
+    return C.flatten(p)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _cos(a, b):
+    return float(np.dot(a.ravel(), b.ravel()) /
+                 max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30))
+
+
+def _tile_mask(shape, tiles):
+    nz, ny, nx = shape
+    ntx, nty = nx // 8, ny // 8
+    m = np.zeros(shape, bool)
+    for t in tiles:
+        ti, tj, tk = t % ntx, (t // ntx) % nty, t // (ntx * nty)
+        m[tk * 8:(tk + 1) * 8, tj * 8:(tj + 1) * 8, ti * 8:(ti + 1) * 8] = True
+    return m
+
+
+def _reference_inputs(wl, fmax, plain, params):
+    """Features from the GPU's plain step (FP64, then BF16) and BF16 weights."""
+    phi = wl.phi.astype(np.float64)
+    feat = CL.features(phi, wl.F, plain.astype(np.float64) - phi, wl.dx, np.float32(wl.gamma),
+                       np.float32(fmax))
+    feat = bf16(feat.astype(np.float32))
+    p = {k: bf16(v.astype(np.float32)) for k, v in C.unflatten(params).items()}
+    for k in ("b0", "b1", "b2"):  # biases stay FP32 on the GPU
+        p[k] = C.unflatten(params)[k].astype(np.float32).astype(np.float64)
+    return feat, p
+
+
+def test_forward_matches_reference():
+    wl, fmax = _case()
+    params = _params(3)
+    cg = C.ClosureGrid(wl.phi.shape[::-1])
+    pd, Fd = to_dev(wl.phi), to_dev(wl.F)
+    r = torch.empty_like(pd)
+    plain = torch.empty_like(pd)
+    cg.forward(pd, Fd, wl.dx, wl.dt, wl.gamma, fmax, to_dev(params), r=r, plain=plain)
+    band = cg.band_list().numpy()
+    want_band = oracle.band_tiles(wl.phi, TILE, np.float32(wl.gamma), True)
+    assert band.tolist() == want_band.tolist()
+    active = oracle.band_tiles(wl.phi, TILE, np.float32(wl.gamma), False)
+    pl = host(plain)
+    ref_plain = oracle.upwind_steps(wl.phi.astype(np.float64), wl.F, wl.dx, wl.dt, want_band, 1)
+    assert np.max(np.abs(pl - ref_plain)) <= fp32_step_bound(wl.phi, wl.F, wl.dx, wl.dt, 1)
+    feat, p = _reference_inputs(wl, fmax, pl, params)
+    want, _ = CL.forward(p, feat)
+    got = host(r)
+    m = _tile_mask(wl.phi.shape, active)
+    assert np.all(got[~m] == 0)
+    rel, cos = _rel(got[m], want[m]), _cos(got[m], want[m])
+    report("closure_forward", rel_l2=rel, cosine=cos, active_tiles=int(len(active)),
+           max_abs=float(np.max(np.abs(got[m] - want[m]))), r_rms=float(np.sqrt(np.mean(want[m] ** 2))))
+    assert rel <= 2e-2 and cos >= 0.999, (rel, cos)
+
+
+def test_gradients_match_reference():
+    wl, fmax = _case(seed=11)
+    params = _params(5)
+    cg = C.ClosureGrid(wl.phi.shape[::-1])
+    pd, Fd = to_dev(wl.phi), to_dev(wl.F)
+    plain = torch.empty_like(pd)
+    cg.forward(pd, Fd, wl.dx, wl.dt, wl.gamma, fmax, to_dev(params), plain=plain)
+    pl = host(plain)
+    # a target one step later that the plain step misses by a smooth field
+    n = wl.phi.shape[0]
+    x = (np.arange(n) + 0.5) * wl.dx
+    bump = (np.sin(2 * np.pi * x)[:, None, None] * np.cos(2 * np.pi * x)[None, :, None] *
+            np.sin(4 * np.pi * x)[None, None, :])
+    target = (pl + 0.2 * wl.dx * bump).astype(np.float32)
+    cg.backward(pd, to_dev(target), Fd, wl.dx, wl.dt, wl.gamma, fmax, to_dev(params))
+    grad = host(cg.grad).astype(np.float64)
+    loss = float(host(cg.loss)[0])
+    active = oracle.band_tiles(wl.phi, TILE, np.float32(wl.gamma), False)
+    feat, p = _reference_inputs(wl, fmax, pl, params)
+    rstar = (target.astype(np.float64) - pl.astype(np.float64)) / wl.dx
+    mask = _tile_mask(wl.phi.shape, active)
+    want_loss, want = CL.loss_and_grad(p, feat, rstar, mask)
+    got = C.unflatten(grad)
+    out = {"loss_rel": abs(loss - want_loss) / want_loss}
+    for k, _ in C.PARAM_SHAPES:
+        out[k] = (_rel(got[k], want[k]), _cos(got[k], want[k]))
+    report("closure_gradients", **{k: v for k, v in out.items()})
+    assert out["loss_rel"] <= 2e-2
+    for k, _ in C.PARAM_SHAPES:
+        rel, cos = out[k]
+        assert rel <= 2e-2 and cos >= 0.999, (k, rel, cos)
+
+
+def test_zero_last_layer_is_the_plain_driver():
+    wl, fmax = _case(n=64, seed=2)
+    params = C.init_params(np.random.default_rng(0))  # last layer zero
+    cg = C.ClosureGrid(wl.phi.shape[::-1])
+    pd, Fd = to_dev(wl.phi), to_dev(wl.F)
+    cg.fallbacks.zero_()
+    cg.run(pd, Fd, wl.dx, wl.dt, wl.gamma, fmax, to_dev(params), 25, 10)
+    bg = BandGrid(wl.phi.shape[::-1], TILE, "f32")
+    pp = to_dev(wl.phi)
+    bg.run(pp, Fd, wl.dx, wl.dt, wl.gamma, 25, 10)
+    a, b = host(pd), host(pp)
+    assert np.array_equal(a, b)  # value equality: -0.0 == 0.0
+    assert int(host(cg.fallbacks)[0]) == 0
+    assert cg.band_list().tolist() == bg.band_list().tolist()
+
+
+def test_fallback_and_constant_correction():
+    wl, fmax = _case(n=48, seed=4)
+    cg = C.ClosureGrid(wl.phi.shape[::-1])
+    Fd = to_dev(wl.F)
+    band = oracle.band_tiles(wl.phi, TILE, np.float32(wl.gamma), True)
+    active = oracle.band_tiles(wl.phi, TILE, np.float32(wl.gamma), False)
+    bg = BandGrid(wl.phi.shape[::-1], TILE, "f32")
+    pp = to_dev(wl.phi)
+    bg.step(pp, Fd, wl.dx, wl.dt, 1, tiles=to_dev(band), ntiles=to_dev(np.array([len(band)],
+                                                                                np.int32)))
+    plain = host(pp)
+    p = C.unflatten(C.init_params(np.random.default_rng(1)))
+    p["b2"][:] = 0.75  # |r| > 1/2 on every active tile
+    pd = to_dev(wl.phi)
+    cg.fallbacks.zero_()
+    cg.run(pd, Fd, wl.dx, wl.dt, wl.gamma, fmax, to_dev(C.flatten(p)), 1, 10)
+    assert int(host(cg.fallbacks)[0]) == len(active)
+    assert np.array_equal(host(pd), plain)
+    p["b2"][:] = 0.25  # accepted everywhere: plain + dx/4 on the active tiles
+    pd = to_dev(wl.phi)
+    cg.fallbacks.zero_()
+    cg.run(pd, Fd, wl.dx, wl.dt, wl.gamma, fmax, to_dev(C.flatten(p)), 1, 10)
+    assert int(host(cg.fallbacks)[0]) == 0
+    m = _tile_mask(wl.phi.shape, active)
+    want = plain.copy()
+    want[m] = plain[m] + np.float32(wl.dx) * np.float32(0.25)
+    assert np.array_equal(host(pd), want)
+
+
+def test_adam_matches_reference():
+    rng = np.random.default_rng(9)
+    w = rng.standard_normal(1000)
+    pd = to_dev(w.astype(np.float32))
+    opt = C.Adam(pd, lr=1e-2)
+    ref = {"w": w.astype(np.float32).astype(np.float64)}
+    state = {}
+    for _ in range(3):
+        g = rng.standard_normal(1000).astype(np.float32)
+        opt.step(to_dev(g))
+        CL.adam_step(ref, {"w": g.astype(np.float64)}, state, lr=1e-2)
+    assert np.allclose(host(pd), ref["w"], rtol=1e-5, atol=1e-6)
+
+
+def test_restrict4_matches_reference():
+    rng = np.random.default_rng(3)
+    fine = rng.standard_normal((32, 24, 40)).astype(np.float32)
+    got = host(C.restrict4(to_dev(fine)))
+    want = CL.restrict4(fine.astype(np.float64))
+    assert got.shape == (8, 6, 10)
+    assert np.max(np.abs(got - want)) <= 4 * np.finfo(np.float32).eps * np.max(np.abs(fine))

@@ -155,3 +155,38 @@ def test_torus_f16s_reduced():
     print(f"[f16s {n}^3] max|err| near front {err.max() / wl.dx:.3e} dx, "
           f"bound {bound / wl.dx:.3e} dx", flush=True)
     assert err.max() <= bound
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("n", [256])
+def test_torus_f16s_error_report(n):
+    """The scaled-FP16 torus recipe, 500 steps: error against the FP64 oracle
+    on the unquantised inputs, reported (near the front, over the tube, and
+    the Hausdorff distance of the fronts), bounded by FP16 rounding."""
+    from paper_1612_04040_amd import metrics as M
+
+    steps = 500
+    wl = W.torus_grf(n, steps, base=128)
+    s = np.float32(wl.scale)
+    h = W.quantize_f16s(wl.phi, s)
+    bg = BandGrid((n, n, n), wl.tile, "f16s")
+    hd = torch.from_numpy(h).to(dev())
+    bg.run(hd, to_dev(wl.F), wl.dx, wl.dt, wl.gamma, steps, wl.window, scale=float(s))
+    got = oracle.dequant_f16s(host(hd), s).astype(np.float64)
+    want = oracle.run_band(wl.phi.astype(np.float64), wl.F, wl.dx, wl.dt, np.float32(wl.gamma),
+                           steps, window=wl.window)
+    err = np.abs(got - want)
+    front = np.abs(want) < wl.dx
+    tube = np.abs(want) < wl.gamma
+    haus = M.hausdorff(M.zero_crossings(got, wl.dx), M.zero_crossings(want, wl.dx)) / wl.dx
+    # worst case: each store rounds to half an FP16 ulp of |phi|/s, times s
+    bound_front = steps * 2.0 ** -12 * float(s)
+    rec = dict(n=n, steps=steps, max_err_front_dx=float(err[front].max() / wl.dx),
+               max_err_tube_dx=float(err[tube].max() / wl.dx),
+               rms_err_front_dx=float(np.sqrt(np.mean(err[front] ** 2)) / wl.dx),
+               hausdorff_dx=haus, bound_front_dx=bound_front / wl.dx,
+               by_abs_phi_dx=error_by_band_distance(err, want, wl.dx))
+    report("torus_f16s_error", **rec)
+    print(f"[f16s torus {n}^3] {rec}", flush=True)
+    assert err[front].max() <= bound_front
+    assert haus <= 1.0
