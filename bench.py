@@ -1,20 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the narrow-band first-order upwind level-set update on one MI355X.
 
-Workload: the 512^3 FP32 union of three spheres (seeded), speed
-F = 0.5 sin(2 pi x) sin(2 pi y) sin(2 pi z), band half-width 6 dx in 8^3
-tiles, rebuilt every 10 steps, 200 steps.  One bench "step" is one window of
-the narrow-band algorithm (Sec. 1.1, Steps 1-2): a band rebuild (a full scan
-of phi for the first window, the exact incremental rescan of the previous
-band afterwards; dilation; ordered compaction) and 10 upwind steps (Eq. 3-5)
-on the band, so --steps 20 is the whole 200-step run, one driver call.  Inputs are resident in HBM before
-the timed region starts; the run restarts from the initial field after the
-warm-up windows.
+Default workload (spheres512): the 512^3 FP32 union of three spheres
+(seeded), speed F = 0.5 sin(2 pi x) sin(2 pi y) sin(2 pi z), band half-width
+6 dx in 8^3 tiles, rebuilt every 10 steps, 200 steps.  One bench "step" is one
+window of the narrow-band algorithm (Sec. 1.1, Steps 1-2): a band rebuild (a
+full scan of phi for the first window, the exact incremental rescan of the
+previous band afterwards; dilation; ordered compaction) and 10 upwind steps
+(Eq. 3-5) on the band, so the default 20 steps are the whole 200-step run, one
+driver call.  Inputs are resident in HBM before the timed region starts; the
+run restarts from the initial field after the warm-up windows.
+
+Other workloads (--workload): torus1024_f16s, the 1024^3 torus with phi
+stored as scaled FP16 (500 steps); batch256, 256 uneven grids (32^3..192^3,
+random ellipsoids, tile shapes from the autotuner, 100 steps) captured in one
+HIP graph and timed on replay.
 
 Prints one JSON line: whole-job band GLUPS (band point-updates per second
 including rebuilds), the roofline of the dominant kernel (the band step,
-timed per launch with HIP events on its stream) and the oracle timed on the
-host cores on a bounded sample of the same workload.
+timed per launch with HIP events on its stream) and, for the default
+workload, the oracle timed on the host cores on a bounded sample of the same
+workload.
 """
 import argparse
 import hashlib
@@ -32,15 +38,25 @@ BYTES_PER_POINT = {"f32": 12, "f64": 24, "f16s": 8}  # phi read, F read, phi wri
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20, help="timed windows (10 upwind steps each)")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed windows of 10 upwind steps (default: the whole run of the "
+                         "workload: 20 for spheres512, 50 for torus1024_f16s, 10 for batch256)")
     ap.add_argument("--warmup", type=int, default=2, help="untimed warm-up windows")
-    ap.add_argument("--n", type=int, default=512, help="grid points per axis")
+    ap.add_argument("--workload", default="spheres512",
+                    choices=["spheres512", "torus1024_f16s", "batch256"],
+                    help="spheres512: the 512^3 FP32 three-sphere run (default); "
+                         "torus1024_f16s: the 1024^3 scaled-FP16 torus run; "
+                         "batch256: 256 uneven grids, autotuned tile shapes, one HIP graph")
+    ap.add_argument("--n", type=int, default=None, help="grid points per axis (single grids)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU work budget of the oracle baseline (0 disables it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed region, run the plain 1 GiB dword copy kernel "
                          "(the reference for calibrating the traffic counters)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.steps is None:
+        args.steps = {"spheres512": 20, "torus1024_f16s": 50, "batch256": 10}[args.workload]
+    return args
 
 
 def kernel_source_digest():
@@ -97,6 +113,154 @@ def cpu_baseline(wl, budget_s):
     }
 
 
+def _single_grid(args, torch, ls, W, BandGrid, dev):
+    """The band driver on one grid: (result fields, workload, precision)."""
+    if args.workload == "spheres512":
+        n = args.n or 512
+        wl = W.three_spheres_f32(n, steps=10 * args.steps)
+        prec, phi_host, scale = "f32", wl.phi, None
+    else:
+        n = args.n or 1024
+        wl = W.torus_grf(n, steps=10 * args.steps)
+        scale = float(np.float32(wl.scale))
+        prec, phi_host = "f16s", W.quantize_f16s(wl.phi, scale)
+    assert all(n % t == 0 for t in wl.tile), "bench grid must be a whole number of tiles"
+    pts_per_tile = int(np.prod(wl.tile))
+    bg = BandGrid((n, n, n), wl.tile, prec, device=dev)
+    phi0 = torch.from_numpy(phi_host).to(dev)
+    F = torch.from_numpy(wl.F).to(dev)
+    phi = phi0.clone()
+    gamma = float(np.float32(wl.gamma))
+    stream = torch.cuda.current_stream(dev)
+
+    # the narrow-band driver: first window from a full scan of phi, later
+    # windows from the exact incremental rebuild; tile_steps counts band
+    # tiles x steps on the device
+    tile_steps = torch.zeros(1, dtype=torch.int64, device=dev)
+    if args.warmup > 0:
+        bg.run(phi, F, wl.dx, wl.dt, gamma, args.warmup * wl.window, wl.window, scale=scale,
+               tile_steps=tile_steps, stream=stream)
+    phi.copy_(phi0)
+    tile_steps.zero_()
+    torch.cuda.synchronize()
+
+    ls.ls_stats_enable(True)
+    t0 = time.perf_counter()
+    bg.run(phi, F, wl.dx, wl.dt, gamma, args.steps * wl.window, wl.window, scale=scale,
+           tile_steps=tile_steps, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ls.ls_stats_enable(False)
+
+    updates = int(tile_steps.item()) * pts_per_tile
+    launches, timed, upd_ms = ls.ls_stats_read(ls.LS_KERNEL_UPWIND)
+    _, ftimed, flag_ms = ls.ls_stats_read(ls.LS_KERNEL_BAND_FLAG)
+    assert launches == timed == args.steps * wl.window
+    fields = {
+        "elapsed": t1 - t0,
+        "updates": updates,
+        "upd_ms": upd_ms,
+        "launches": launches,
+        "config": {
+            "workload": wl.name,
+            "grid": [n, n, n],
+            "tile": list(wl.tile),
+            "band_halfwidth_dx": 6,
+            "steps_per_window": wl.window,
+            "upwind_steps": args.steps * wl.window,
+            "storage": prec,
+            "parallelism": "single GPU",
+        },
+        "extra": {
+            "band_tiles_last_window": int(bg.ntiles.item()),
+            "band_scan_avg_us": round(flag_ms * 1e3 / max(ftimed, 1), 3),
+        },
+        "kernel": f"ls::upwind_fast_kernel ({prec}, 8x8x8 tiles)",
+        "data": ("synthetic (seeded three-sphere signed distance, sinusoidal speed)"
+                 if prec == "f32" else
+                 "synthetic (torus signed distance stored as scaled FP16, speed 1 + 0.3 GRF)"),
+    }
+    return fields, wl, prec
+
+
+def _batch(args, torch, ls, W, dev):
+    """256 uneven grids, tile shapes from the autotuner, the whole run
+    captured in one HIP graph and timed on replay."""
+    from paper_1612_04040_amd.autotune import shape_for, tune
+    from paper_1612_04040_amd.batch import Batch
+
+    insts = W.ellipsoid_batch()
+    table = tune([it.n for it in insts])
+    specs = [((it.n,) * 3, shape_for(it.n, table), it.dx, it.dt, it.gamma) for it in insts]
+    b = Batch(specs, device=dev)
+    b.load([it.phi for it in insts], [it.F for it in insts])
+    phi0 = b.phi.clone()
+    nsteps, window = 10 * args.steps, 10
+    tile_steps = torch.zeros(1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.Stream(dev)
+    # eager pass with per-launch kernel timing (roofline), then the graph
+    with torch.cuda.stream(stream):
+        if args.warmup > 0:
+            b.run(args.warmup * window, window, stream=stream)
+        ls.ls_copy_f32(b.phi, phi0, b.phi.numel(), stream)
+        torch.cuda.synchronize()
+        ls.ls_stats_enable(True)
+        b.run(nsteps, window, tile_steps=tile_steps, stream=stream)
+        torch.cuda.synchronize()
+        ls.ls_stats_enable(False)
+    launches, timed, upd_ms = ls.ls_stats_read(ls.LS_KERNEL_UPWIND)
+    updates_eager = int(tile_steps.item())
+    ls.ls_graph_begin(stream)
+    ls.ls_copy_f32(b.phi, phi0, b.phi.numel(), stream)
+    b.run(nsteps, window, tile_steps=tile_steps, stream=stream)
+    graph = ls.ls_graph_end(stream)
+    try:
+        ls.ls_graph_launch(graph, stream)  # warm replay
+        torch.cuda.synchronize()
+        tile_steps.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ls.ls_graph_launch(graph, stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    finally:
+        ls.ls_graph_destroy(graph)
+    assert int(tile_steps.item()) == updates_eager
+    shapes = sorted({tuple(s[1]) for s in specs})
+    per_tile = [int(np.prod(s[1])) for s in specs]
+    # tile-steps are counted over all grids; points per tile differ by shape,
+    # so weight them by the band share of each grid's tiles (tile-rounded)
+    lists = b.band_lists()
+    pts_last = sum(len(l) * p for l, p in zip(lists, per_tile))
+    tiles_last = sum(len(l) for l in lists)
+    mean_pts = pts_last / max(tiles_last, 1)
+    updates = int(round(updates_eager * mean_pts))
+    fields = {
+        "elapsed": t1 - t0,
+        "updates": updates,
+        "upd_ms": upd_ms,
+        "launches": launches,
+        "config": {
+            "workload": "ellipsoid_batch256",
+            "instances": len(insts),
+            "sizes": [int(min(it.n for it in insts)), int(max(it.n for it in insts))],
+            "total_points": int(sum(it.n ** 3 for it in insts)),
+            "tile_shapes": [list(t) for t in shapes],
+            "band_halfwidth_dx": 6,
+            "steps_per_window": window,
+            "upwind_steps": nsteps,
+            "storage": "f32",
+            "parallelism": "single GPU",
+        },
+        "extra": {"timed_as": "one HIP graph replay of the whole run (phi reset included)",
+                  "updates_counting": "band tiles x steps x points per tile (tile-rounded)"},
+        "kernel": "ls::upwind_fast_kernel (f32, batched, all tile shapes)",
+        "data": "synthetic (seeded random-ellipsoid signed distances, speed u + 0.2 GRF)",
+        "updates_per_launch_alg": updates / max(launches, 1),
+    }
+    return fields
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -113,49 +277,19 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
-    wl = W.three_spheres_f32(args.n, steps=10 * args.steps)
-    n = args.n
-    assert all(n % t == 0 for t in wl.tile), "bench grid must be a whole number of tiles"
-    pts_per_tile = int(np.prod(wl.tile))
-    bg = BandGrid((n, n, n), wl.tile, "f32", device=dev)
-    phi0 = torch.from_numpy(wl.phi).to(dev)
-    F = torch.from_numpy(wl.F).to(dev)
-    phi = phi0.clone()
-    gamma = float(np.float32(wl.gamma))
-    stream = torch.cuda.current_stream(dev)
-
-    # the narrow-band driver: first window from a full scan of phi, later
-    # windows from the exact incremental rebuild; tile_steps counts band
-    # tiles x steps on the device
-    tile_steps = torch.zeros(1, dtype=torch.int64, device=dev)
-    if args.warmup > 0:
-        bg.run(phi, F, wl.dx, wl.dt, gamma, args.warmup * wl.window, wl.window,
-               tile_steps=tile_steps, stream=stream)
-    phi.copy_(phi0)
-    tile_steps.zero_()
-    torch.cuda.synchronize()
-
-    ls.ls_stats_enable(True)
-    t0 = time.perf_counter()
-    bg.run(phi, F, wl.dx, wl.dt, gamma, args.steps * wl.window, wl.window,
-           tile_steps=tile_steps, stream=stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ls.ls_stats_enable(False)
-
-    elapsed = t1 - t0
-    updates = int(tile_steps.item()) * pts_per_tile
-    value = updates / elapsed / 1e9
-
-    launches, timed, upd_ms = ls.ls_stats_read(ls.LS_KERNEL_UPWIND)
-    flaunches, ftimed, flag_ms = ls.ls_stats_read(ls.LS_KERNEL_BAND_FLAG)
-    assert launches == timed == args.steps * wl.window
-    avg_launch_s = upd_ms / 1e3 / max(timed, 1)
-    pts_per_launch = updates / max(launches, 1)
-    bytes_per_launch = BYTES_PER_POINT["f32"] * pts_per_launch
+    wl = None
+    if args.workload == "batch256":
+        f = _batch(args, torch, ls, W, dev)
+        prec = "f32"
+    else:
+        f, wl, prec = _single_grid(args, torch, ls, W, BandGrid, dev)
+    value = f["updates"] / f["elapsed"] / 1e9
+    avg_launch_s = f["upd_ms"] / 1e3 / max(f["launches"], 1)
+    pts_per_launch = f["updates"] / max(f["launches"], 1)
+    bytes_per_launch = BYTES_PER_POINT[prec] * pts_per_launch
     achieved = bytes_per_launch / avg_launch_s / 1e9
     digest = kernel_source_digest()
-    traffic = measured_traffic("upwind", wl.name, digest)
+    traffic = measured_traffic("upwind", f["config"]["workload"], digest)
 
     result = {
         "metric": "band GLUPS (narrow-band first-order upwind update, incl. band rebuilds)",
@@ -164,27 +298,18 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(elapsed / max(args.steps, 1) * 1e3, 4),
+        "ms_per_step": round(f["elapsed"] / max(args.steps, 1) * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic (seeded three-sphere signed distance, sinusoidal speed)",
-        "config": {
-            "workload": wl.name,
-            "grid": [n, n, n],
-            "tile": list(wl.tile),
-            "band_halfwidth_dx": 6,
-            "steps_per_window": wl.window,
-            "upwind_steps": args.steps * wl.window,
-            "parallelism": "single GPU",
-        },
+        "dtype": prec,
+        "data": f["data"],
+        "config": f["config"],
         "kernel_glups": round(pts_per_launch / avg_launch_s / 1e9, 3),
-        "band_tiles_last_window": int(bg.ntiles.item()),
-        "band_scan_avg_us": round(flag_ms * 1e3 / max(ftimed, 1), 3),
+        **f["extra"],
         "roofline": {
             "bound": "hbm",
-            "kernel": "ls::upwind_fast_kernel (f32, 8x8x8 tiles)",
+            "kernel": f["kernel"],
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -199,11 +324,12 @@ def main():
         a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
         for _ in range(3):
-            ls.ls_copy_f32(b, a, a.numel(), stream=stream)
+            ls.ls_copy_f32(b, a, a.numel(), stream=torch.cuda.current_stream(dev))
         torch.cuda.synchronize()
         del a, b
     if rank == 0:
-        result["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        result["cpu_baseline"] = (cpu_baseline(wl, args.cpu_seconds)
+                                  if args.workload == "spheres512" else None)
         print(json.dumps(result), flush=True)
     return 0
 

@@ -202,3 +202,28 @@ def test_batch_layout_host():
         ls.ls_batch_layout(bad, 1)
     assert e.value.status == ls.LS_ERR_UNSUPPORTED
     assert ls.lib().ls_graph_begin(None) == ls.LS_ERR_ARG
+
+
+def test_closure_parameter_layout_and_cases():
+    """The flat parameter vector holds the layers in the documented order and
+    the library agrees on its length; closure problems are deterministic and
+    their speed bound covers every sample."""
+    import numpy as np
+    from oracle import closure as CL
+    from paper_1612_04040_amd import closure as C
+    from paper_1612_04040_amd import workloads as W
+
+    assert ls.ls_closure_param_count() == C.NPARAMS == 8673
+    p = CL.init_params(np.random.default_rng(0), scale=0.5)
+    back = C.unflatten(C.flatten(p))
+    for k, shape in C.PARAM_SHAPES:
+        assert back[k].shape == shape
+        assert np.array_equal(back[k], p[k].astype(np.float32))
+    a, b = W.ClosureCase(7, n_fine=64), W.ClosureCase(7, n_fine=64)
+    assert np.array_equal(a.phi(16), b.phi(16))
+    assert float(np.max(np.abs(a.F(64)))) <= a.fmax
+    assert a.dt_coarse == 4 * a.dt_fine
+    g = ls.grid((64, 64, 64))
+    assert ls.ls_closure_workspace_bytes(g) > 0
+    with pytest.raises(ls.LsError):
+        ls.ls_closure_workspace_bytes(ls.grid((60, 64, 64)))
