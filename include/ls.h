@@ -213,10 +213,11 @@ int ls_batch_setup(const ls_instance *inst, int n, void *workspace, int64_t work
  * rescan of the previous bands afterwards) and `window` steps of all grids;
  * equal, grid by grid, to ls_band_run_f32 on each grid alone with its tile
  * shape, bit for bit.  tile_steps_dev as in ls_band_run_f32 (summed over the
- * grids).  Asynchronous, no host synchronisation: capturable in a HIP graph. */
+ * grids); point_steps_dev (may be NULL) accumulates steps x in-domain points
+ * of every band tile (partial tiles at the high faces count their points).  Asynchronous, no host synchronisation: capturable in a HIP graph. */
 int ls_batch_run_f32(const ls_instance *inst, int n, float *phi, const float *F, float *scratch,
-                     int nsteps, int window, int64_t *tile_steps_dev, void *workspace,
-                     int64_t workspace_bytes, void *stream);
+                     int nsteps, int window, int64_t *tile_steps_dev, int64_t *point_steps_dev,
+                     void *workspace, int64_t workspace_bytes, void *stream);
 /* Device pointers (inside the workspace) to the batch's last band list and
  * its length. */
 int ls_batch_band(const ls_instance *inst, int n, void *workspace, int64_t workspace_bytes,
@@ -252,6 +253,19 @@ typedef struct ls_tuning {
 } ls_tuning;
 int ls_set_tuning(const ls_tuning *t);
 int ls_get_tuning(ls_tuning *t);
+
+/* Tile-shape autotuner (native): for each size in sizes[0..n) (cubic grids
+ * of that many points per axis), the tile shape with the shortest time per
+ * window of the FP32 band driver, measured once per size bucket of 32 points
+ * on a synthetic n^3 ellipsoid (sizes bucket*32 + 16) over the shapes the
+ * batched step is compiled for: 8x8x8, 16x4x4, 32x4x4, 16x8x8, 4x4x4.  out[i]
+ * receives the grid (sizes[i]^3) with the chosen tile.  Results are cached in
+ * the text file cache_path (NULL: no cache), keyed by device name and bucket;
+ * force != 0 re-measures every bucket asked for.  Unlike every other call,
+ * the measurement allocates (and frees) its own device buffers and
+ * synchronises its own stream; precision must be 0 (FP32). */
+int ls_autotune(const int32_t *sizes, int n, int precision, const char *cache_path, ls_grid *out,
+                int force);
 
 /* Launch configuration the band step would use for grid g on the current
  * device: precision 0 = f32, 1 = f64, 2 = f16s.  Outputs (any may be NULL):
@@ -292,10 +306,13 @@ int ls_copy_f32(float *dst, const float *src, int64_t n, void *stream);
  *     c0 = clip(phi / gamma, -2, 2),  c1 = F / fmax,  c2 = (plain - phi) / dx
  * (plain = phi after one plain step, Eq. 3) to a correction r, and the
  * corrected step is
- *     phi^{n+1} = plain + dx * r    on the active tiles A (Eq. 6 in tile form),
- *     phi^{n+1} = plain             elsewhere in the band U,
- * except that an active tile any of whose r is non-finite or above 1/2 in
- * magnitude takes the plain step (a fallback, counted).  Activations outside
+ *     phi^{n+1} = plain + dx * c(phi) * r    on the active tiles A (Eq. 6 in
+ *                                            tile form),
+ *     phi^{n+1} = plain                      elsewhere in the band U,
+ * with c the cut-off function of Eq. 8 for beta = gamma / 2 (1 near the
+ * front, 0 from |phi| = gamma on), except that an active tile where some
+ * c(phi) * r is non-finite or above 1/2 in magnitude takes the plain step (a
+ * fallback, counted).  Activations outside
  * U count as zero; since A lies one tile inside U and the network sees three
  * points around a point, r on A equals the network's value with no band.
  * Weights and activations are BF16 on the matrix cores with FP32
@@ -326,24 +343,23 @@ int ls_restrict4_f32(const float *fine, const ls_grid *fine_grid, float *coarse,
 
 /* One network evaluation at phi: builds A and U from phi, the plain step into
  * `plain` (dense, may be NULL) and r into `r` (dense; zero outside A; may be
- * NULL).  phi is not modified.  scratch: one grid of FP32. */
+ * NULL).  phi is not modified. */
 int ls_closure_forward_f32(const float *phi, const float *F, const ls_grid *g, float dx, float dt,
                            float gamma, float fmax, const float *params, float *r, float *plain,
-                           int32_t *tiles, int64_t capacity, int32_t *ntiles_dev, float *scratch,
-                           void *ws, int64_t ws_bytes, void *cws, int64_t cws_bytes,
-                           void *stream);
+                           int32_t *tiles, int64_t capacity, int32_t *ntiles_dev, void *ws,
+                           int64_t ws_bytes, void *cws, int64_t cws_bytes, void *stream);
 
 /* Training loss and gradient at phi toward target (the fine solution one
  * coarse step later, restricted): loss = mean over the points of A of
- * (r - r*)^2 with r* = (target - plain) / dx, written to *loss_dev (may be
+ * (c(phi) r - r*)^2 with r* = (target - plain) / dx, written to *loss_dev (may be
  * NULL); grad (8673 floats, overwritten) is d loss / d params, computed by
  * the backward kernels (data gradients through the transposed convolutions,
  * weight gradients as per-tile partial sums reduced in tile order). */
 int ls_closure_backward_f32(const float *phi, const float *target, const float *F,
                             const ls_grid *g, float dx, float dt, float gamma, float fmax,
                             const float *params, float *grad, float *loss_dev, int32_t *tiles,
-                            int64_t capacity, int32_t *ntiles_dev, float *scratch, void *ws,
-                            int64_t ws_bytes, void *cws, int64_t cws_bytes, void *stream);
+                            int64_t capacity, int32_t *ntiles_dev, void *ws, int64_t ws_bytes,
+                            void *cws, int64_t cws_bytes, void *stream);
 
 /* One Adam update (Kingma and Ba) of n FP32 parameters with step count t >= 1:
  * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
@@ -359,8 +375,8 @@ int ls_adam_step(float *params, const float *grad, float *m, float *v, int64_t n
 int ls_closure_run_f32(float *phi, const float *F, const ls_grid *g, float dx, float dt,
                        float gamma, float fmax, const float *params, int nsteps, int window,
                        int32_t *tiles, int64_t capacity, int32_t *ntiles_dev,
-                       int32_t *fallbacks_dev, float *scratch, void *ws, int64_t ws_bytes,
-                       void *cws, int64_t cws_bytes, void *stream);
+                       int32_t *fallbacks_dev, void *ws, int64_t ws_bytes, void *cws,
+                       int64_t cws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -15,11 +15,16 @@ Conventions (readings of a spec addition; the paper has no network):
                conv3^3(16->1) + b; zero padding at the grid faces;
                cross-correlation: out[o,z,y,x] = sum_{c,dz,dy,dx}
                w[o,c,dz,dy,dx] * in[c, z+dz-1, y+dy-1, x+dx-1].
-  update       on the active tiles: phi + delta_plain + dx_c * r; elsewhere
-               in the band the plain step; a tile whose r is non-finite or
-               exceeds 1/2 in magnitude falls back to the plain step.
+  gate         the correction is weighted by the cut-off function of Eq. 8,
+               c(phi) = 1 for |phi| <= beta, (|phi| - gamma)^2 (2|phi| + gamma
+               - 3 beta) / (gamma - beta)^3 for beta < |phi| <= gamma, 0 beyond,
+               with beta = gamma / 2: it acts near the front only.
+  update       on the active tiles: phi + delta_plain + dx_c * c(phi) * r;
+               elsewhere in the band the plain step; a tile where some
+               c(phi) * r is non-finite or exceeds 1/2 in magnitude falls back
+               to the plain step.
   loss         mean over active points of (phi_pred - phi_target)^2 / dx_c^2
-               = mean (r - r*)^2 with r* = (phi_target - phi - delta_plain)/dx_c.
+               = mean (c r - r*)^2 with r* = (phi_target - phi - delta_plain)/dx_c.
 """
 import numpy as np
 
@@ -83,6 +88,14 @@ def conv3_backward(x, w, gout):
     return gxp[:, 1:-1, 1:-1, 1:-1], gw, gb
 
 
+def cutoff(phi, beta, gamma):
+    """The cut-off function of Eq. 8 (1 inside |phi| <= beta, a cubic down to
+    0 at |phi| = gamma, 0 beyond)."""
+    a = np.abs(np.asarray(phi, dtype=np.float64))
+    mid = (a - gamma) ** 2 * (2 * a + gamma - 3 * beta) / (gamma - beta) ** 3
+    return np.where(a <= beta, 1.0, np.where(a <= gamma, mid, 0.0))
+
+
 def silu(z):
     return z / (1.0 + np.exp(-z))
 
@@ -117,14 +130,16 @@ def forward(params, feat):
     return r, (feat, z0, a0, z1, a1)
 
 
-def loss_and_grad(params, feat, rstar, mask):
-    """Mean over mask of (r - r*)^2 and its gradient w.r.t. every parameter."""
+def loss_and_grad(params, feat, rstar, mask, gate=None):
+    """Mean over mask of (c r - r*)^2 (c = gate, 1 if None) and its gradient
+    w.r.t. every parameter."""
     r, (x, z0, a0, z1, a1) = forward(params, feat)
     m = mask.astype(np.float64)
+    c = np.ones_like(r) if gate is None else np.asarray(gate, np.float64)
     cnt = max(m.sum(), 1.0)
-    diff = (r - rstar) * m
+    diff = (c * r - rstar) * m
     loss = float((diff ** 2).sum() / cnt)
-    gr = (2.0 / cnt) * diff
+    gr = (2.0 / cnt) * diff * c
     g = {}
     ga1, g["w2"], g["b2"] = conv3_backward(a1, params["w2"], gr[None])
     gz1 = ga1 * silu_grad(z1)
@@ -150,11 +165,13 @@ def adam_step(params, grads, state, lr, beta1=0.9, beta2=0.999, eps=1e-8):
 
 
 def closure_step(params, phi_c, F_c, dx, dt, gamma, fmax, band, active, tile=(8, 8, 8)):
-    """One corrected coarse step: plain on the band, plus dx*r on the active
-    tiles whose correction is finite and at most 1/2 (else plain)."""
+    """One corrected coarse step: plain on the band, plus dx*c(phi)*r on the
+    active tiles whose gated correction is finite and at most 1/2 (else
+    plain)."""
     delta = plain_increment(phi_c, F_c, dx, dt, band, tile)
     feat = features(phi_c, F_c, delta, dx, gamma, fmax)
     r, _ = forward(params, feat)
+    r = cutoff(phi_c, 0.5 * gamma, gamma) * r
     out = np.asarray(phi_c, np.float64) + delta
     nz, ny, nx = out.shape
     tx, ty, tz = tile

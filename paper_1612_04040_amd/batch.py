@@ -48,10 +48,10 @@ class Batch:
             self.view(self.phi, i).copy_(torch.from_numpy(np.ascontiguousarray(p, np.float32)))
             self.view(self.F, i).copy_(torch.from_numpy(np.ascontiguousarray(f, np.float32)))
 
-    def run(self, nsteps, window=10, tile_steps=None, phi=None, stream=None):
+    def run(self, nsteps, window=10, tile_steps=None, phi=None, stream=None, point_steps=None):
         ls.ls_batch_run_f32(self.inst, self.n, self.phi if phi is None else phi, self.F,
-                            self.scratch, nsteps, window, tile_steps, self.ws, self.ws_bytes,
-                            stream)
+                            self.scratch, nsteps, window, tile_steps, point_steps, self.ws,
+                            self.ws_bytes, stream)
 
     def ntiles(self, i):
         (nx, ny, nz), (tx, ty, tz) = self.specs[i][0], self.specs[i][1]

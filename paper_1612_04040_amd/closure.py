@@ -70,25 +70,24 @@ class ClosureGrid:
 
     def _band(self):
         b = self.bg
-        return b.tiles, b.capacity, b.ntiles, b.scratch, b.ws, b.ws_bytes
+        return b.tiles, b.capacity, b.ntiles, b.ws, b.ws_bytes
 
     def forward(self, phi, F, dx, dt, gamma, fmax, params, r=None, plain=None, stream=None):
-        t, cap, n, scr, ws, wsb = self._band()
+        t, cap, n, ws, wsb = self._band()
         ls.ls_closure_forward_f32(phi, F, self.g, dx, dt, gamma, fmax, params, r, plain, t, cap, n,
-                                  scr, ws, wsb, self.cws, self.cws_bytes, stream)
+                                  ws, wsb, self.cws, self.cws_bytes, stream)
 
     def backward(self, phi, target, F, dx, dt, gamma, fmax, params, stream=None):
         """Fills self.grad and self.loss (device)."""
-        t, cap, n, scr, ws, wsb = self._band()
+        t, cap, n, ws, wsb = self._band()
         ls.ls_closure_backward_f32(phi, target, F, self.g, dx, dt, gamma, fmax, params, self.grad,
-                                   self.loss, t, cap, n, scr, ws, wsb, self.cws, self.cws_bytes,
-                                   stream)
+                                   self.loss, t, cap, n, ws, wsb, self.cws, self.cws_bytes, stream)
 
     def run(self, phi, F, dx, dt, gamma, fmax, params, nsteps, window=10, stream=None):
         """Corrected narrow-band run; self.fallbacks accumulates (zero it first)."""
-        t, cap, n, scr, ws, wsb = self._band()
+        t, cap, n, ws, wsb = self._band()
         ls.ls_closure_run_f32(phi, F, self.g, dx, dt, gamma, fmax, params, nsteps, window, t, cap,
-                              n, self.fallbacks, scr, ws, wsb, self.cws, self.cws_bytes, stream)
+                              n, self.fallbacks, ws, wsb, self.cws, self.cws_bytes, stream)
 
     def band_list(self):
         return self.bg.band_list()

@@ -60,18 +60,35 @@ class Problem:
         self.snaps = fine_trajectory(self.case, nsteps, device) if with_trajectory else None
 
 
-def train(cg, problems, params, iters, lr, seed=0, log_every=200):
-    """Adam on random (seed, step) pairs; returns the loss log."""
+def train(cg, problems, params, iters, lr, seed=0, log_every=200, rollout_max=8,
+          rollout_from=0.25, rollout_prob=0.5):
+    """Adam on random (seed, step) pairs; returns the loss log.
+
+    After the first `rollout_from` of the iterations, with probability
+    `rollout_prob` the input of a pair is not the restricted fine field but the
+    corrected coarse run of the current network started k <= rollout_max steps
+    earlier from it (no gradient through the roll-out), so the network also
+    learns to correct its own drift; the target stays the restricted fine
+    field one step later."""
     rng = np.random.default_rng(seed)
     opt = C.Adam(params, lr=lr)
     log = []
     acc = torch.zeros(1, dtype=torch.float32, device=params.device)
+    tmp = torch.empty_like(problems[0].snaps[0])
     for it in range(iters):
         p = problems[rng.integers(len(problems))]
         n = int(rng.integers(p.snaps.shape[0] - 1))
         c = p.case
-        cg.backward(p.snaps[n], p.snaps[n + 1], p.F, c.dx_coarse, c.dt_coarse, c.gamma_coarse,
-                    c.fmax, params)
+        x = p.snaps[n]
+        if it >= rollout_from * iters and rng.random() < rollout_prob:
+            k = int(rng.integers(1, rollout_max + 1))
+            if n >= k:
+                tmp.copy_(p.snaps[n - k])
+                cg.run(tmp, p.F, c.dx_coarse, c.dt_coarse, c.gamma_coarse, c.fmax, params, k,
+                       10)
+                x = tmp
+        cg.backward(x, p.snaps[n + 1], p.F, c.dx_coarse, c.dt_coarse, c.gamma_coarse, c.fmax,
+                    params)
         # cosine decay to lr / 100
         lr_t = lr * (0.01 + 0.99 * 0.5 * (1 + math.cos(math.pi * it / max(1, iters))))
         opt.step(cg.grad, lr=lr_t)
@@ -202,7 +219,9 @@ def main(argv=None):
     ap.add_argument("--train-seeds", default="100-115")
     ap.add_argument("--val-seeds", default="200-203")
     ap.add_argument("--eval-seed", type=int, default=5)
-    ap.add_argument("--iters", type=int, default=4000)
+    ap.add_argument("--iters", type=int, default=8000)
+    ap.add_argument("--rollout-max", type=int, default=8)
+    ap.add_argument("--rollout-prob", type=float, default=0.5)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--init-seed", type=int, default=0)
     ap.add_argument("--params-out", default=None, help="save the trained parameters (.npy)")
@@ -228,7 +247,8 @@ def main(argv=None):
     params = zero.clone()
     report["val_loss_plain"] = one_step_loss(cg, val_p, zero)
     t0 = time.time()
-    report["train_log"] = train(cg, train_p, params, args.iters, args.lr, seed=args.init_seed)
+    report["train_log"] = train(cg, train_p, params, args.iters, args.lr, seed=args.init_seed,
+                                rollout_max=args.rollout_max, rollout_prob=args.rollout_prob)
     torch.cuda.synchronize()
     report["train_s"] = time.time() - t0
     report["val_loss_learned"] = one_step_loss(cg, val_p, params)

@@ -400,6 +400,32 @@ __global__ void batch_accumulate_kernel(int64_t *acc, const int32_t *count, int 
     if (threadIdx.x == 0 && blockIdx.x == 0) *acc += static_cast<int64_t>(*count) * nsteps;
 }
 
+// acc += nsteps * (in-domain points of the listed tiles); one block.
+__global__ __launch_bounds__(kBlock) void batch_point_count_kernel(
+    int64_t *acc, const int32_t *__restrict__ list, const int32_t *count,
+    const BatchInst *__restrict__ inst, int n, int total_tiles, int nsteps) {
+    __shared__ int64_t red[kBlock];
+    const int m = min(*count, total_tiles);
+    int64_t s = 0;
+    for (int p = threadIdx.x; p < m; p += kBlock) {
+        const int gt = list[p];
+        if (gt < 0 || gt >= total_tiles) continue;
+        const BatchInst &d = inst[find_inst(inst, n, gt, false)];
+        const int t = gt - d.tile_base;
+        const int ti = t % d.ntx, r = t / d.ntx;
+        const int tj = r % d.nty, tk = r / d.nty;
+        s += static_cast<int64_t>(min(d.tx, d.nx - ti * d.tx)) * min(d.ty, d.ny - tj * d.ty) *
+             min(d.tz, d.nz - tk * d.tz);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *acc += red[0] * nsteps;
+}
+
 // ---------------------------------------------------------------------------
 // host side
 
@@ -581,8 +607,8 @@ int ls_batch_setup(const ls_instance *inst, int n, void *workspace, int64_t work
 }
 
 int ls_batch_run_f32(const ls_instance *inst, int n, float *phi, const float *F, float *scratch,
-                     int nsteps, int window, int64_t *tile_steps_dev, void *workspace,
-                     int64_t workspace_bytes, void *stream_) {
+                     int nsteps, int window, int64_t *tile_steps_dev, int64_t *point_steps_dev,
+                     void *workspace, int64_t workspace_bytes, void *stream_) {
     ls::clear_error();
     ls::BatchLayout L;
     int rc = ls::make_layout(inst, n, &L);
@@ -618,6 +644,14 @@ int ls_batch_run_f32(const ls_instance *inst, int n, float *phi, const float *F,
             hipLaunchKernelGGL(ls::batch_accumulate_kernel, dim3(1), dim3(64), 0, stream,
                                tile_steps_dev, static_cast<const int32_t *>(counts[cur]), m);
             LS_LAUNCH_CHECK("batch_accumulate_kernel");
+        }
+        if (point_steps_dev) {
+            hipLaunchKernelGGL(ls::batch_point_count_kernel, dim3(1), dim3(ls::kBlock), 0, stream,
+                               point_steps_dev, static_cast<const int32_t *>(lists[cur]),
+                               static_cast<const int32_t *>(counts[cur]),
+                               reinterpret_cast<const ls::BatchInst *>(ws + w.inst), n,
+                               static_cast<int>(L.total_tiles), m);
+            LS_LAUNCH_CHECK("batch_point_count_kernel");
         }
         if ((rc = ls::batch_steps(L, phi, F, scratch, ws, w, m, stream)) != LS_OK) return rc;
     }

@@ -33,6 +33,14 @@ static_assert(kNParams == 8673, "parameter count");
 __device__ inline __bf16 to_bf16(float v) { return static_cast<__bf16>(v); }
 __device__ inline float from_bf16(__bf16 v) { return static_cast<float>(v); }
 __device__ inline float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+// Cut-off function of Eq. 8 with beta = gamma / 2, in u = |phi| / gamma:
+// 1 for u <= 1/2, 8 (u - 1)^2 (2u - 1/2) for 1/2 < u <= 1, 0 beyond.
+__device__ inline float cutoff_f(float phi, float inv_gamma) {
+    const float u = fabsf(phi) * inv_gamma;
+    if (u <= 0.5f) return 1.0f;
+    if (u <= 1.0f) return 8.0f * (u - 1.0f) * (u - 1.0f) * (2.0f * u - 0.5f);
+    return 0.0f;
+}
 __device__ inline float silu_grad_f(float z) {
     const float s = 1.0f / (1.0f + __expf(-z));
     return s * (1.0f + z * (1.0f - s));
@@ -104,8 +112,9 @@ enum { OUT_HIDDEN = 0, OUT_LAST = 1, OUT_GRAD = 2 };
 // One block per listed tile.  CIN: 16 (input bf16 x16 channel-last) or 4
 // (In4 source).  MODE: OUT_HIDDEN writes z (pre-activation) and a = SiLU(z),
 // bf16 x16; OUT_LAST writes r = row 0 (+ bias) as FP32 and, when `apply`,
-// corrects the plain step on the tile (phi_next += dx*r) unless some r of
-// the tile is non-finite or above 1/2 (then counts a fallback); OUT_GRAD
+// corrects the plain step on the tile (phi_next += dx*c(phi)*r, c the cut-off
+// of Eq. 8, phi from in4.phi) unless some c(phi)*r of the tile is non-finite
+// or above 1/2 (then counts a fallback); OUT_GRAD
 // writes acc * SiLU'(z) as bf16 x16 (z read from zin).
 template <int CIN, int MODE>
 __global__ __launch_bounds__(kBlock) void closure_conv_kernel(
@@ -236,6 +245,8 @@ __global__ __launch_bounds__(kBlock) void closure_conv_kernel(
                 rvals[gi8] = acc[0] + bias[0];
                 if (kq == 0) {
                     rout[gpt] = rvals[gi8];
+                    // the applied correction is c(phi) r (a NaN or inf r stays non-finite)
+                    if (in4.phi) rvals[gi8] *= cutoff_f(in4.phi[gpt], in4.inv_gamma);
                     if (!(fabsf(rvals[gi8]) <= 0.5f)) atomicOr(&bad_s, 1);  // NaN fails too
                 }
             }
@@ -261,6 +272,203 @@ __global__ __launch_bounds__(kBlock) void closure_conv_kernel(
             }
         }
         __syncthreads();  // patch free for the next tile
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fused inference: the whole network on one active tile per block, with the
+// activations in LDS.  Layer 1 runs on the 12^3 points within 2 of the tile
+// (from features of the 14^3 points within 3), layer 2 on the 10^3 points
+// within 1, layer 3 on the tile.  An active tile lies one tile inside the
+// band, so every point read is in the band or outside the grid (zero).
+
+constexpr int kF0 = kT + 6, kF1 = kT + 4, kF2 = kT + 2;  // 14, 12, 10
+constexpr size_t kFusedIn = size_t(kF0) * kF0 * kF0 * 4;  // bf16 elements
+constexpr size_t kFusedA0 = size_t(kF1) * kF1 * kF1 * 16;
+constexpr size_t kFusedA1 = size_t(kF2) * kF2 * kF2 * 16;
+constexpr size_t kFusedLds = 2 * (kFusedIn + kFusedA0 + kFusedA1);
+constexpr int kFusedBlock = 512, kFusedWaves = kFusedBlock / 64;
+
+__global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
+    ConvGeo g, const int32_t *__restrict__ tiles, const int32_t *__restrict__ ntiles_dev,
+    int ntiles_cap, In4 feat, const __bf16 *__restrict__ wp0, const __bf16 *__restrict__ wp1,
+    const __bf16 *__restrict__ wp2, const float *__restrict__ params, float *__restrict__ rout,
+    float *__restrict__ phi_next, float dx, int32_t *__restrict__ fallbacks) {
+    extern __shared__ __align__(16) unsigned char fsm[];
+    __bf16 *in = reinterpret_cast<__bf16 *>(fsm);
+    __bf16 *a0 = in + kFusedIn;
+    __bf16 *a1 = a0 + kFusedA0;
+    __shared__ int bad_s;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = lane & 15, kq = lane >> 4;
+    const int n = min(*ntiles_dev, ntiles_cap);
+
+    for (int p = blockIdx.x; p < n; p += gridDim.x) {
+        const int t = tiles[p];
+        if (t < 0 || t >= g.ntx * g.nty * g.ntz) continue;  // uniform
+        const int ti = t % g.ntx, rr = t / g.ntx;
+        const int x0 = ti * kT, y0 = (rr % g.nty) * kT, z0 = (rr / g.nty) * kT;
+        // features of the 14^3 points (zero outside the grid)
+        for (int q = threadIdx.x; q < kF0 * kF0 * kF0; q += kFusedBlock) {
+            const int px = q % kF0, py = (q / kF0) % kF0, pz = q / (kF0 * kF0);
+            const int gx = x0 + px - 3, gy = y0 + py - 3, gz = z0 + pz - 3;
+            float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+            if (gx >= 0 && gy >= 0 && gz >= 0 && gx < g.nx && gy < g.ny && gz < g.nz) {
+                const int64_t gi = (static_cast<int64_t>(gz) * g.ny + gy) * g.nx + gx;
+                const float ph = feat.phi[gi];
+                v0 = fminf(fmaxf(ph * feat.inv_gamma, -2.f), 2.f);
+                v1 = feat.F[gi] * feat.inv_fmax;
+                v2 = (feat.plain[gi] - ph) * feat.inv_dx;
+            }
+            __bf16 *d = in + q * 4;
+            d[0] = to_bf16(v0);
+            d[1] = to_bf16(v1);
+            d[2] = to_bf16(v2);
+            d[3] = to_bf16(0.f);
+        }
+        if (threadIdx.x == 0) bad_s = 0;
+        __syncthreads();
+
+        // layer 1: 12^3 outputs, 108 groups of 16
+        {
+            bf16x8 wa[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                wa[c] = *reinterpret_cast<const bf16x8 *>(wp0 + (c * 64 + lane) * 8);
+            float bb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bb[i] = params[kB0 + 4 * kq + i];
+            for (int grp = wave; grp < (kF1 * kF1 * kF1) / 16; grp += kFusedWaves) {
+                const int pt = grp * 16 + j;
+                const int lx = pt % kF1, ly = (pt / kF1) % kF1, lz = pt / (kF1 * kF1);
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    bf16x8 b;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int tap = 8 * c + 2 * kq + h;
+                        if (tap < kTaps) {
+                            const int dz = tap / 9, dy = (tap / 3) % 3, dxx = tap % 3;
+                            const int q = ((lz + dz) * kF0 + (ly + dy)) * kF0 + (lx + dxx);
+                            const uint2 v = *reinterpret_cast<const uint2 *>(in + q * 4);
+                            const __bf16 *e = reinterpret_cast<const __bf16 *>(&v);
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) b[4 * h + u] = e[u];
+                        } else {
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) b[4 * h + u] = to_bf16(0.f);
+                        }
+                    }
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[c], b, acc, 0, 0, 0);
+                }
+                const int gx = x0 + lx - 2, gy = y0 + ly - 2, gz = z0 + lz - 2;
+                const bool inside = gx >= 0 && gy >= 0 && gz >= 0 && gx < g.nx && gy < g.ny &&
+                                    gz < g.nz;
+                __bf16 ab[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) ab[i] = to_bf16(inside ? silu_f(acc[i] + bb[i]) : 0.f);
+                *reinterpret_cast<uint2 *>(a0 + pt * 16 + 4 * kq) = *reinterpret_cast<uint2 *>(ab);
+            }
+        }
+        __syncthreads();
+
+        // layer 2: 10^3 outputs, 63 groups of 16 (the last one partial)
+        {
+            bf16x8 wa[14];
+#pragma unroll
+            for (int c = 0; c < 14; ++c)
+                wa[c] = *reinterpret_cast<const bf16x8 *>(wp1 + (c * 64 + lane) * 8);
+            float bb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bb[i] = params[kB1 + 4 * kq + i];
+            constexpr int NP = kF2 * kF2 * kF2;
+            for (int grp = wave; grp < (NP + 15) / 16; grp += kFusedWaves) {
+                const int pt = grp * 16 + j;
+                const int ptc = min(pt, NP - 1);  // lanes past the end compute a copy
+                const int lx = ptc % kF2, ly = (ptc / kF2) % kF2, lz = ptc / (kF2 * kF2);
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int c = 0; c < 14; ++c) {
+                    const int tap = 2 * c + (kq >> 1);
+                    bf16x8 b;
+                    if (tap < kTaps) {
+                        const int dz = tap / 9, dy = (tap / 3) % 3, dxx = tap % 3;
+                        const int q = ((lz + dz) * kF1 + (ly + dy)) * kF1 + (lx + dxx);
+                        b = *reinterpret_cast<const bf16x8 *>(a0 + q * 16 + 8 * (kq & 1));
+                    } else {
+                        b = bf16x8{};
+                    }
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[c], b, acc, 0, 0, 0);
+                }
+                const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z0 + lz - 1;
+                const bool inside = gx >= 0 && gy >= 0 && gz >= 0 && gx < g.nx && gy < g.ny &&
+                                    gz < g.nz;
+                __bf16 ab[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) ab[i] = to_bf16(inside ? silu_f(acc[i] + bb[i]) : 0.f);
+                if (pt < NP)
+                    *reinterpret_cast<uint2 *>(a1 + pt * 16 + 4 * kq) =
+                        *reinterpret_cast<uint2 *>(ab);
+            }
+        }
+        __syncthreads();
+
+        // layer 3 on the tile: r, the gated correction and the fallback test
+        constexpr int NG3 = 512 / 16 / kFusedWaves;  // layer-3 groups per wave
+        float rv[NG3];
+        {
+            bf16x8 wa[14];
+#pragma unroll
+            for (int c = 0; c < 14; ++c)
+                wa[c] = *reinterpret_cast<const bf16x8 *>(wp2 + (c * 64 + lane) * 8);
+            const float b2 = params[kB2];
+#pragma unroll
+            for (int gi8 = 0; gi8 < NG3; ++gi8) {
+                const int pt = (wave + kFusedWaves * gi8) * 16 + j;
+                const int lx = pt & 7, ly = (pt >> 3) & 7, lz = pt >> 6;
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int c = 0; c < 14; ++c) {
+                    const int tap = 2 * c + (kq >> 1);
+                    bf16x8 b;
+                    if (tap < kTaps) {
+                        const int dz = tap / 9, dy = (tap / 3) % 3, dxx = tap % 3;
+                        const int q = ((lz + dz) * kF2 + (ly + dy)) * kF2 + (lx + dxx);
+                        b = *reinterpret_cast<const bf16x8 *>(a1 + q * 16 + 8 * (kq & 1));
+                    } else {
+                        b = bf16x8{};
+                    }
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[c], b, acc, 0, 0, 0);
+                }
+                rv[gi8] = acc[0] + b2;
+                if (kq == 0) {
+                    const int64_t gpt =
+                        (static_cast<int64_t>(z0 + lz) * g.ny + (y0 + ly)) * g.nx + (x0 + lx);
+                    if (rout) rout[gpt] = rv[gi8];
+                    rv[gi8] *= cutoff_f(feat.phi[gpt], feat.inv_gamma);
+                    if (!(fabsf(rv[gi8]) <= 0.5f)) atomicOr(&bad_s, 1);  // NaN fails too
+                }
+            }
+        }
+        __syncthreads();
+        if (phi_next) {
+            if (bad_s == 0) {
+                if (kq == 0) {
+#pragma unroll
+                    for (int gi8 = 0; gi8 < NG3; ++gi8) {
+                        const int pt = (wave + kFusedWaves * gi8) * 16 + j;
+                        const int lx = pt & 7, ly = (pt >> 3) & 7, lz = pt >> 6;
+                        const int64_t gpt =
+                            (static_cast<int64_t>(z0 + lz) * g.ny + (y0 + ly)) * g.nx + (x0 + lx);
+                        phi_next[gpt] += dx * rv[gi8];
+                    }
+                }
+            } else if (threadIdx.x == 0 && fallbacks) {
+                atomicAdd(fallbacks, 1);
+            }
+        }
+        __syncthreads();  // LDS free for the next tile
     }
 }
 
@@ -405,7 +613,7 @@ __global__ void restrict4_kernel(const float *__restrict__ fine, int nxf, int ny
 __global__ __launch_bounds__(kBlock) void closure_loss_kernel(
     ConvGeo g, const int32_t *__restrict__ tiles, const int32_t *__restrict__ ntiles_dev, int cap,
     const float *__restrict__ r, const float *__restrict__ phi, const float *__restrict__ plain,
-    const float *__restrict__ target, float inv_dx, float *__restrict__ gr,
+    const float *__restrict__ target, float inv_dx, float inv_gamma, float *__restrict__ gr,
     float *__restrict__ tile_loss) {
     const int n = min(*ntiles_dev, cap);
     const float inv_cnt = 1.0f / fmaxf(1.0f, static_cast<float>(n) * 512.f);
@@ -419,8 +627,9 @@ __global__ __launch_bounds__(kBlock) void closure_loss_kernel(
             const int lx = q & 7, ly = (q >> 3) & 7, lz = q >> 6;
             const int64_t gi = (static_cast<int64_t>(z0 + lz) * g.ny + (y0 + ly)) * g.nx + x0 + lx;
             const float rs = (target[gi] - plain[gi]) * inv_dx;
-            const float d = r[gi] - rs;
-            gr[gi] = 2.f * d * inv_cnt;
+            const float c = cutoff_f(phi[gi], inv_gamma);
+            const float d = c * r[gi] - rs;
+            gr[gi] = 2.f * c * d * inv_cnt;
             s += d * d;
         }
         red[threadIdx.x] = s;
@@ -474,8 +683,8 @@ template <class S>
 int band_build(const S *phi, typename Codec<S>::C scale, const ls_grid *grid,
                typename Codec<S>::C gamma, int dilate, int32_t *tiles, int64_t capacity,
                int32_t *ntiles_dev, void *workspace, int64_t ws_bytes, void *stream_);  // ls_band.hip
-int plan_step_f32(float *phi, const float *F, const Geom &G, float dx, float dt, float *scratch,
-                  uint8_t *ws, hipStream_t stream);                                   // ls_step.hip
+int plan_step_to_f32(const float *phi, float *out, const float *F, const Geom &G, float dx,
+                     float dt, uint8_t *ws, hipStream_t stream);                      // ls_step.hip
 
 constexpr int kPart = kTaps * 256 + 16;  // per-tile weight-gradient partial (floats)
 
@@ -617,13 +826,16 @@ static int closure_bands(const ClosureCall &c, const float *phi, const ls_grid *
                              ws_bytes, c.s);
 }
 
-// plain = phi + one plain step on the planned band (dense copy first, so the
-// points outside the band hold phi).
+// plain = one plain step of phi on the planned band; with `sync`, the points
+// outside the band are first copied from phi (a dense copy), else the caller
+// guarantees plain equals phi there.
 static int closure_plain(const ClosureCall &c, const float *phi, float *plain, const float *F,
-                         float dx, float dt, float *scratch) {
-    int rc = ls_copy_f32(plain, phi, c.G.npoints, c.s);
-    if (rc != LS_OK) return rc;
-    return plan_step_f32(plain, F, c.G, dx, dt, scratch, c.ws, c.s);
+                         float dx, float dt, bool sync) {
+    if (sync) {
+        int rc = ls_copy_f32(plain, phi, c.G.npoints, c.s);
+        if (rc != LS_OK) return rc;
+    }
+    return plan_step_to_f32(phi, plain, F, c.G, dx, dt, c.ws, c.s);
 }
 
 // The network on the band (L1, L2) and the active tiles (L3): r into the
@@ -651,11 +863,40 @@ static int closure_network(const ClosureCall &c, const float *phi, const float *
                        store_z ? at<__bf16>(c, c.w.z1) : nullptr, at<__bf16>(c, c.w.a1), nullptr,
                        nullptr, nullptr, 0.f, nullptr);
     LS_LAUNCH_CHECK("closure_conv_kernel (layer 2)");
+    In4 gate{phi, nullptr, nullptr, nullptr, 1.0f / gamma, 0.f, 0.f};
     hipLaunchKernelGGL((closure_conv_kernel<16, OUT_LAST>), dim3(c.blocks), dim3(kBlock), 0, c.s,
-                       cg, active, nactive, cap, umap, at<const __bf16>(c, c.w.a1), none,
+                       cg, active, nactive, cap, umap, at<const __bf16>(c, c.w.a1), gate,
                        at<const __bf16>(c, c.w.wp2), params + kB2, nullptr, nullptr, nullptr,
                        at<float>(c, c.w.r), apply, dx, fallbacks);
     LS_LAUNCH_CHECK("closure_conv_kernel (layer 3)");
+    return LS_OK;
+}
+
+// The fused network on the active tiles: r (raw, into rout if non-NULL) and,
+// with `apply`, the corrected step apply += dx * c(phi) * r per tile (with the
+// fallback test).
+static int closure_fused(const ClosureCall &c, const float *phi, const float *F, const float *plain,
+                         float dx, float gamma, float fmax, const float *params, float *rout,
+                         float *apply, int32_t *fallbacks) {
+    static bool lds_set = false;  // per process: the attribute is per kernel, not per device
+    if (!lds_set) {
+        LS_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(closure_fused_kernel),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         static_cast<int>(kFusedLds)));
+        lds_set = true;
+    }
+    DeviceInfo di;
+    int rc = device_info(&di);
+    if (rc != LS_OK) return rc;
+    const unsigned blocks =
+        static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(c.G.ntiles, di.cus)));
+    In4 feat{phi, F, plain, nullptr, 1.0f / gamma, 1.0f / fmax, 1.0f / dx};
+    hipLaunchKernelGGL(closure_fused_kernel, dim3(blocks), dim3(kFusedBlock), kFusedLds, c.s,
+                       conv_geo(c.G), at<const int32_t>(c, c.w.active),
+                       at<const int32_t>(c, c.w.counters), static_cast<int>(c.G.ntiles), feat,
+                       at<const __bf16>(c, c.w.wp0), at<const __bf16>(c, c.w.wp1),
+                       at<const __bf16>(c, c.w.wp2), params, rout, apply, dx, fallbacks);
+    LS_LAUNCH_CHECK("closure_fused_kernel");
     return LS_OK;
 }
 
@@ -704,15 +945,14 @@ int ls_restrict4_f32(const float *fine, const ls_grid *fine_grid, float *coarse,
 
 int ls_closure_forward_f32(const float *phi, const float *F, const ls_grid *g, float dx, float dt,
                            float gamma, float fmax, const float *params, float *r, float *plain,
-                           int32_t *tiles, int64_t capacity, int32_t *ntiles_dev, float *scratch,
-                           void *ws, int64_t ws_bytes, void *cws, int64_t cws_bytes,
-                           void *stream) {
+                           int32_t *tiles, int64_t capacity, int32_t *ntiles_dev, void *ws,
+                           int64_t ws_bytes, void *cws, int64_t cws_bytes, void *stream) {
     ls::clear_error();
     ls::ClosureCall c;
     int rc = ls::closure_setup(g, dx, dt, gamma, fmax, params, ws, ws_bytes, cws, cws_bytes,
                                stream, &c);
     if (rc != LS_OK) return rc;
-    if (!phi || !F || !tiles || !ntiles_dev || !scratch) {
+    if (!phi || !F || !tiles || !ntiles_dev) {
         ls::set_error("closure forward: NULL argument");
         return LS_ERR_ARG;
     }
@@ -725,11 +965,11 @@ int ls_closure_forward_f32(const float *phi, const float *F, const ls_grid *g, f
     float *rr = ls::at<float>(c, c.w.r);
     if ((rc = ls::closure_bands(c, phi, g, gamma, tiles, capacity, ntiles_dev, ws_bytes)) != LS_OK)
         return rc;
-    if ((rc = ls::closure_plain(c, phi, pl, F, dx, dt, scratch)) != LS_OK) return rc;
+    if ((rc = ls::closure_plain(c, phi, pl, F, dx, dt, true)) != LS_OK) return rc;
     if ((rc = ls::pack_all(c, params)) != LS_OK) return rc;
     if ((rc = ls::zero_f32(rr, c.G.npoints, c.s)) != LS_OK) return rc;
-    if ((rc = ls::closure_network(c, phi, F, pl, dx, gamma, fmax, tiles, ntiles_dev, params, false,
-                                  nullptr, nullptr)) != LS_OK)
+    if ((rc = ls::closure_fused(c, phi, F, pl, dx, gamma, fmax, params, rr, nullptr, nullptr)) !=
+        LS_OK)
         return rc;
     if (r && (rc = ls_copy_f32(r, rr, c.G.npoints, c.s)) != LS_OK) return rc;
     if (plain && (rc = ls_copy_f32(plain, pl, c.G.npoints, c.s)) != LS_OK) return rc;
@@ -739,14 +979,14 @@ int ls_closure_forward_f32(const float *phi, const float *F, const ls_grid *g, f
 int ls_closure_backward_f32(const float *phi, const float *target, const float *F,
                             const ls_grid *g, float dx, float dt, float gamma, float fmax,
                             const float *params, float *grad, float *loss_dev, int32_t *tiles,
-                            int64_t capacity, int32_t *ntiles_dev, float *scratch, void *ws,
-                            int64_t ws_bytes, void *cws, int64_t cws_bytes, void *stream) {
+                            int64_t capacity, int32_t *ntiles_dev, void *ws, int64_t ws_bytes,
+                            void *cws, int64_t cws_bytes, void *stream) {
     ls::clear_error();
     ls::ClosureCall c;
     int rc = ls::closure_setup(g, dx, dt, gamma, fmax, params, ws, ws_bytes, cws, cws_bytes,
                                stream, &c);
     if (rc != LS_OK) return rc;
-    if (!phi || !target || !F || !grad || !tiles || !ntiles_dev || !scratch) {
+    if (!phi || !target || !F || !grad || !tiles || !ntiles_dev) {
         ls::set_error("closure backward: NULL argument");
         return LS_ERR_ARG;
     }
@@ -765,7 +1005,7 @@ int ls_closure_backward_f32(const float *phi, const float *target, const float *
     float *part = ls::at<float>(c, c.w.partial);
     if ((rc = ls::closure_bands(c, phi, g, gamma, tiles, capacity, ntiles_dev, ws_bytes)) != LS_OK)
         return rc;
-    if ((rc = ls::closure_plain(c, phi, pl, F, dx, dt, scratch)) != LS_OK) return rc;
+    if ((rc = ls::closure_plain(c, phi, pl, F, dx, dt, true)) != LS_OK) return rc;
     if ((rc = ls::pack_all(c, params)) != LS_OK) return rc;
     if ((rc = ls::closure_network(c, phi, F, pl, dx, gamma, fmax, tiles, ntiles_dev, params, true,
                                   nullptr, nullptr)) != LS_OK)
@@ -774,7 +1014,7 @@ int ls_closure_backward_f32(const float *phi, const float *target, const float *
     if ((rc = ls::zero_f32(gr, c.G.npoints, c.s)) != LS_OK) return rc;
     hipLaunchKernelGGL(ls::closure_loss_kernel, dim3(c.blocks), dim3(ls::kBlock), 0, c.s, cg,
                        active, nactive, cap, ls::at<const float>(c, c.w.r), phi,
-                       static_cast<const float *>(pl), target, 1.0f / dx, gr,
+                       static_cast<const float *>(pl), target, 1.0f / dx, 1.0f / gamma, gr,
                        ls::at<float>(c, c.w.tile_loss));
     LS_LAUNCH_CHECK("closure_loss_kernel");
     if (loss_dev) {
@@ -841,14 +1081,14 @@ int ls_adam_step(float *params, const float *grad, float *m, float *v, int64_t n
 int ls_closure_run_f32(float *phi, const float *F, const ls_grid *g, float dx, float dt,
                        float gamma, float fmax, const float *params, int nsteps, int window,
                        int32_t *tiles, int64_t capacity, int32_t *ntiles_dev,
-                       int32_t *fallbacks_dev, float *scratch, void *ws, int64_t ws_bytes,
-                       void *cws, int64_t cws_bytes, void *stream) {
+                       int32_t *fallbacks_dev, void *ws, int64_t ws_bytes, void *cws,
+                       int64_t cws_bytes, void *stream) {
     ls::clear_error();
     ls::ClosureCall c;
     int rc = ls::closure_setup(g, dx, dt, gamma, fmax, params, ws, ws_bytes, cws, cws_bytes,
                                stream, &c);
     if (rc != LS_OK) return rc;
-    if (!phi || !F || !tiles || !ntiles_dev || !fallbacks_dev || !scratch) {
+    if (!phi || !F || !tiles || !ntiles_dev || !fallbacks_dev) {
         ls::set_error("closure run: NULL argument");
         return LS_ERR_ARG;
     }
@@ -862,17 +1102,19 @@ int ls_closure_run_f32(float *phi, const float *F, const ls_grid *g, float dx, f
         return LS_ERR_CAPACITY;
     }
     if ((rc = ls::pack_all(c, params)) != LS_OK) return rc;
+    // ping-pong between phi and a closure buffer; within a window the points
+    // outside the band are equal in both (one dense copy per window)
     float *buf[2] = {phi, ls::at<float>(c, c.w.plain)};
     int cur = 0;
     for (int s = 0; s < nsteps; ++s) {
-        if (s % window == 0 &&
-            (rc = ls::closure_bands(c, buf[cur], g, gamma, tiles, capacity, ntiles_dev,
-                                    ws_bytes)) != LS_OK)
+        const bool first = s % window == 0;
+        if (first && (rc = ls::closure_bands(c, buf[cur], g, gamma, tiles, capacity, ntiles_dev,
+                                             ws_bytes)) != LS_OK)
             return rc;
         float *x = buf[cur], *y = buf[cur ^ 1];
-        if ((rc = ls::closure_plain(c, x, y, F, dx, dt, scratch)) != LS_OK) return rc;
-        if ((rc = ls::closure_network(c, x, F, y, dx, gamma, fmax, tiles, ntiles_dev, params,
-                                      false, y, fallbacks_dev)) != LS_OK)
+        if ((rc = ls::closure_plain(c, x, y, F, dx, dt, first)) != LS_OK) return rc;
+        if ((rc = ls::closure_fused(c, x, F, y, dx, gamma, fmax, params, nullptr, y,
+                                    fallbacks_dev)) != LS_OK)
             return rc;
         cur ^= 1;
     }

@@ -335,6 +335,7 @@ static UpwindFn<S, FT, EXACT> select_upwind_kernel(const StepGeom &sg, int nown,
     }
     LS_FAST(8, 8, 8, 4)
     LS_FAST(8, 8, 8, 2)
+    LS_FAST(8, 8, 8, 8)
     LS_FAST(16, 4, 4, 2)
     LS_FAST(16, 4, 4, 4)
     LS_FAST(32, 4, 4, 1)
@@ -412,7 +413,8 @@ static int step_args(S *phi, const FT *F, const ls_grid *grid, typename Codec<S>
 template <class S, class FT>
 static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const Geom &G,
                          const StepGeom &sg, typename Codec<S>::C dx, typename Codec<S>::C dt,
-                         int nsteps, S *scratch, uint8_t *ws, hipStream_t stream) {
+                         int nsteps, S *scratch, uint8_t *ws, hipStream_t stream,
+                         bool land_in_scratch = false) {
     using C = typename Codec<S>::C;
     constexpr bool EXACT = sizeof(C) == 8;
     if (nsteps == 0) return LS_OK;
@@ -448,7 +450,7 @@ static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const 
         LS_LAUNCH_CHECK("upwind_kernel");
         if ((rc = stats_after(LS_KERNEL_UPWIND, stream, slot)) != LS_OK) return rc;
     }
-    if (nsteps & 1) {
+    if ((nsteps & 1) && !land_in_scratch) {
         hipLaunchKernelGGL(band_copy_kernel<S>, dim3(nblocks), dim3(kBlock), 0, stream, sg,
                            static_cast<const S *>(scratch), phi,
                            static_cast<const int32_t *>(items),
@@ -461,14 +463,16 @@ static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const 
 int fill_zero(uint8_t *p, int64_t bytes, hipStream_t stream);  // ls_band.hip
 
 // One FP32 step of the plan the workspace holds (the band of the last build),
-// phi updated in place through scratch.
-int plan_step_f32(float *phi, const float *F, const Geom &G, float dx, float dt, float *scratch,
-                  uint8_t *ws, hipStream_t stream) {
+// from phi into out: the band points of out get the step, the other points of
+// out are not written (the caller keeps them equal to phi).
+int plan_step_to_f32(const float *phi, float *out, const float *F, const Geom &G, float dx,
+                     float dt, uint8_t *ws, hipStream_t stream) {
     StepGeom sg;
     size_t lds = 0;
     int rc = make_step_geom<float>(G, &sg, &lds);
     if (rc != LS_OK) return rc;
-    return upwind_launch<float, float>(phi, F, 1.0f, G, sg, dx, dt, 1, scratch, ws, stream);
+    return upwind_launch<float, float>(const_cast<float *>(phi), F, 1.0f, G, sg, dx, dt, 1, out,
+                                       ws, stream, true);
 }
 
 template <class S, class FT>

@@ -93,7 +93,8 @@ _SIGNATURES = {
     "ls_batch_workspace_bytes": (_I64, [_VP, _I32]),
     "ls_batch_layout": (_I32, [_VP, _I32, _VP, _VP]),
     "ls_batch_setup": (_I32, [_VP, _I32, _VP, _I64, _VP]),
-    "ls_batch_run_f32": (_I32, [_VP, _I32, _VP, _VP, _VP, _I32, _I32, _VP, _VP, _I64, _VP]),
+    "ls_batch_run_f32": (_I32, [_VP, _I32, _VP, _VP, _VP, _I32, _I32, _VP, _VP, _VP, _I64,
+                                _VP]),
     "ls_batch_band": (_I32, [_VP, _I32, _VP, _I64, _VP, _VP]),
     "ls_graph_begin": (_I32, [_VP]),
     "ls_graph_end": (_I32, [_VP, _VP]),
@@ -103,16 +104,17 @@ _SIGNATURES = {
     "ls_copy_f32": (_I32, [_VP, _VP, _I64, _VP]),
     "ls_stats_read": (_I32, [_I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                              ctypes.POINTER(_F64)]),
+    "ls_autotune": (_I32, [_VP, _I32, _I32, ctypes.c_char_p, _VP, _I32]),
     "ls_closure_param_count": (_I64, []),
     "ls_closure_workspace_bytes": (_I64, [_G]),
     "ls_restrict4_f32": (_I32, [_VP, _G, _VP, _VP]),
     "ls_closure_forward_f32": (_I32, [_VP, _VP, _G, _F32, _F32, _F32, _F32, _VP, _VP, _VP, _VP,
-                                      _I64, _VP, _VP, _VP, _I64, _VP, _I64, _VP]),
+                                      _I64, _VP, _VP, _I64, _VP, _I64, _VP]),
     "ls_closure_backward_f32": (_I32, [_VP, _VP, _VP, _G, _F32, _F32, _F32, _F32, _VP, _VP, _VP,
-                                       _VP, _I64, _VP, _VP, _VP, _I64, _VP, _I64, _VP]),
+                                       _VP, _I64, _VP, _VP, _I64, _VP, _I64, _VP]),
     "ls_adam_step": (_I32, [_VP, _VP, _VP, _VP, _I64, _F32, _F32, _F32, _F32, _I32, _VP]),
     "ls_closure_run_f32": (_I32, [_VP, _VP, _G, _F32, _F32, _F32, _F32, _VP, _I32, _I32, _VP,
-                                  _I64, _VP, _VP, _VP, _VP, _I64, _VP, _I64, _VP]),
+                                  _I64, _VP, _VP, _VP, _I64, _VP, _I64, _VP]),
 }
 
 LS_KERNEL_UPWIND = 0
@@ -331,11 +333,12 @@ def ls_batch_setup(inst, n, workspace, workspace_bytes, stream=None):
                                        _stream(stream)))
 
 
-def ls_batch_run_f32(inst, n, phi, F, scratch, nsteps, window, tile_steps_dev, workspace,
-                     workspace_bytes, stream=None):
+def ls_batch_run_f32(inst, n, phi, F, scratch, nsteps, window, tile_steps_dev, point_steps_dev,
+                     workspace, workspace_bytes, stream=None):
     return _check(lib().ls_batch_run_f32(ctypes.addressof(inst), n, _ptr(phi), _ptr(F),
                                          _ptr(scratch), nsteps, window, _ptr(tile_steps_dev),
-                                         _ptr(workspace), workspace_bytes, _stream(stream)))
+                                         _ptr(point_steps_dev), _ptr(workspace), workspace_bytes,
+                                         _stream(stream)))
 
 
 def ls_batch_band(inst, n, workspace, workspace_bytes):
@@ -377,20 +380,19 @@ def ls_restrict4_f32(fine, fine_grid, coarse, stream=None):
 
 
 def ls_closure_forward_f32(phi, F, g, dx, dt, gamma, fmax, params, r, plain, tiles, capacity,
-                           ntiles_dev, scratch, ws, ws_bytes, cws, cws_bytes, stream=None):
+                           ntiles_dev, ws, ws_bytes, cws, cws_bytes, stream=None):
     return _check(lib().ls_closure_forward_f32(
         _ptr(phi), _ptr(F), _g(g), dx, dt, gamma, fmax, _ptr(params), _ptr(r), _ptr(plain),
-        _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(scratch), _ptr(ws), ws_bytes, _ptr(cws),
-        cws_bytes, _stream(stream)))
+        _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(ws), ws_bytes, _ptr(cws), cws_bytes,
+        _stream(stream)))
 
 
 def ls_closure_backward_f32(phi, target, F, g, dx, dt, gamma, fmax, params, grad, loss_dev, tiles,
-                            capacity, ntiles_dev, scratch, ws, ws_bytes, cws, cws_bytes,
-                            stream=None):
+                            capacity, ntiles_dev, ws, ws_bytes, cws, cws_bytes, stream=None):
     return _check(lib().ls_closure_backward_f32(
         _ptr(phi), _ptr(target), _ptr(F), _g(g), dx, dt, gamma, fmax, _ptr(params), _ptr(grad),
-        _ptr(loss_dev), _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(scratch), _ptr(ws),
-        ws_bytes, _ptr(cws), cws_bytes, _stream(stream)))
+        _ptr(loss_dev), _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(ws), ws_bytes, _ptr(cws),
+        cws_bytes, _stream(stream)))
 
 
 def ls_adam_step(params, grad, m, v, n, lr, beta1, beta2, eps, t, stream=None):
@@ -399,9 +401,19 @@ def ls_adam_step(params, grad, m, v, n, lr, beta1, beta2, eps, t, stream=None):
 
 
 def ls_closure_run_f32(phi, F, g, dx, dt, gamma, fmax, params, nsteps, window, tiles, capacity,
-                       ntiles_dev, fallbacks_dev, scratch, ws, ws_bytes, cws, cws_bytes,
-                       stream=None):
+                       ntiles_dev, fallbacks_dev, ws, ws_bytes, cws, cws_bytes, stream=None):
     return _check(lib().ls_closure_run_f32(
         _ptr(phi), _ptr(F), _g(g), dx, dt, gamma, fmax, _ptr(params), int(nsteps), int(window),
-        _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(fallbacks_dev), _ptr(scratch), _ptr(ws),
-        ws_bytes, _ptr(cws), cws_bytes, _stream(stream)))
+        _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(fallbacks_dev), _ptr(ws), ws_bytes,
+        _ptr(cws), cws_bytes, _stream(stream)))
+
+
+def ls_autotune(sizes, cache_path=None, force=False, precision=0):
+    """Tile shape per size (list of (tx, ty, tz)), measured or from the cache."""
+    n = len(sizes)
+    arr = (ctypes.c_int32 * n)(*[int(v) for v in sizes])
+    out = (ls_grid * n)()
+    path = cache_path.encode() if cache_path else None
+    _check(lib().ls_autotune(ctypes.addressof(arr), n, precision, path, ctypes.addressof(out),
+                             1 if force else 0))
+    return [(g.tx, g.ty, g.tz) for g in out]

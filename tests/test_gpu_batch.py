@@ -90,3 +90,22 @@ def test_batch_graph_replay_matches_eager():
             assert host(b.phi).tobytes() == eager.tobytes(), f"replay {rep}"
     finally:
         ls.ls_graph_destroy(graph)
+
+
+def test_batch_point_steps_count_in_domain_points():
+    """point_steps = steps x in-domain points of every band tile (partial
+    tiles at the high faces count only their points), summed over grids."""
+    specs, phis, Fs, _ = _specs(seed=13, count=7)
+    b = Batch(specs)
+    b.load(phis, Fs)
+    ps = torch.zeros(1, dtype=torch.int64, device=dev())
+    b.run(10, 10, point_steps=ps)  # one window: the band of the initial field
+    want = 0
+    for (dims, tile, dx, dt, gamma), p in zip(specs, phis):
+        nx, ny, nz = dims
+        tx, ty, tz = tile
+        ntx, nty = -(-nx // tx), -(-ny // ty)
+        for t in oracle.band_tiles(p, tile, np.float32(gamma), True):
+            ti, tj, tk = t % ntx, (t // ntx) % nty, t // (ntx * nty)
+            want += (min(tx, nx - ti * tx) * min(ty, ny - tj * ty) * min(tz, nz - tk * tz))
+    assert int(ps.item()) == 10 * want

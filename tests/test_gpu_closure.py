@@ -6,8 +6,11 @@
   BF16-rounded weights and features (relative L2 <= 2e-2, cosine >= 0.999);
 * with the last layer zero the corrected run equals the plain band driver
   (value for value: the sign of a zero may differ);
-* a correction above 1/2 makes every active tile fall back to the plain step,
-  and an accepted constant correction adds exactly dx/4 on the active tiles;
+* a gated correction c(phi) r above 1/2 makes every active tile fall back to
+  the plain step, and an accepted constant r = 1/4 adds dx c(phi) / 4 on the
+  active tiles (c the cut-off of Eq. 8);
+* three windows of the corrected driver (the fused network kernel) match the
+  reference run step by step;
 * Adam and the restriction match the reference.
 """
 import numpy as np
@@ -16,7 +19,7 @@ import torch
 
 import oracle
 from oracle import closure as CL
-from gpu_util import dev, fp32_step_bound, host, report, to_dev
+from gpu_util import EPS32, dev, fp32_step_bound, host, report, to_dev
 from paper_1612_04040_amd import closure as C
 from paper_1612_04040_amd import workloads as W
 from paper_1612_04040_amd.band import BandGrid
@@ -127,7 +130,8 @@ def test_gradients_match_reference():
     feat, p = _reference_inputs(wl, fmax, pl, params)
     rstar = (target.astype(np.float64) - pl.astype(np.float64)) / wl.dx
     mask = _tile_mask(wl.phi.shape, active)
-    want_loss, want = CL.loss_and_grad(p, feat, rstar, mask)
+    gate = CL.cutoff(wl.phi.astype(np.float64), 0.5 * wl.gamma, wl.gamma)
+    want_loss, want = CL.loss_and_grad(p, feat, rstar, mask, gate)
     got = C.unflatten(grad)
     out = {"loss_rel": abs(loss - want_loss) / want_loss}
     for k, _ in C.PARAM_SHAPES:
@@ -166,22 +170,62 @@ def test_fallback_and_constant_correction():
     bg.step(pp, Fd, wl.dx, wl.dt, 1, tiles=to_dev(band), ntiles=to_dev(np.array([len(band)],
                                                                                 np.int32)))
     plain = host(pp)
+    gate = CL.cutoff(wl.phi.astype(np.float64), 0.5 * wl.gamma, wl.gamma)
+    m = _tile_mask(wl.phi.shape, active)
     p = C.unflatten(C.init_params(np.random.default_rng(1)))
-    p["b2"][:] = 0.75  # |r| > 1/2 on every active tile
+    p["b2"][:] = 1e6  # gated correction above 1/2 wherever c > 5e-7: every active tile
     pd = to_dev(wl.phi)
     cg.fallbacks.zero_()
     cg.run(pd, Fd, wl.dx, wl.dt, wl.gamma, fmax, to_dev(C.flatten(p)), 1, 10)
     assert int(host(cg.fallbacks)[0]) == len(active)
     assert np.array_equal(host(pd), plain)
-    p["b2"][:] = 0.25  # accepted everywhere: plain + dx/4 on the active tiles
+    p["b2"][:] = 0.25  # accepted everywhere: plain + dx c(phi) / 4 on the active tiles
     pd = to_dev(wl.phi)
     cg.fallbacks.zero_()
     cg.run(pd, Fd, wl.dx, wl.dt, wl.gamma, fmax, to_dev(C.flatten(p)), 1, 10)
     assert int(host(cg.fallbacks)[0]) == 0
-    m = _tile_mask(wl.phi.shape, active)
-    want = plain.copy()
-    want[m] = plain[m] + np.float32(wl.dx) * np.float32(0.25)
-    assert np.array_equal(host(pd), want)
+    got = host(pd).astype(np.float64)
+    want = plain.astype(np.float64) + np.where(m, 0.25 * wl.dx * gate, 0.0)
+    assert np.array_equal(got[~m], plain[~m].astype(np.float64))
+    # FP32 gate and update: a few ulp of the value and of the correction
+    tol = 4 * EPS32 * (np.abs(want[m]) + 0.25 * wl.dx)
+    assert np.all(np.abs(got[m] - want[m]) <= tol)
+
+
+def test_multistep_run_matches_reference():
+    """Three windows of the corrected driver with a non-zero network against
+    the FP64 reference step by step (BF16 weights in both; the features are
+    BF16 on the GPU only, so a small relative tolerance on the correction)."""
+    wl, fmax = _case(n=48, seed=6)
+    params = _params(8, last_scale=0.05)
+    p = {k: bf16(v.astype(np.float32)) for k, v in C.unflatten(params).items()}
+    for k in ("b0", "b1", "b2"):
+        p[k] = C.unflatten(params)[k].astype(np.float32).astype(np.float64)
+    cg = C.ClosureGrid(wl.phi.shape[::-1])
+    pd = to_dev(wl.phi)
+    cg.fallbacks.zero_()
+    nsteps, window = 12, 5
+    cg.run(pd, to_dev(wl.F), wl.dx, wl.dt, wl.gamma, fmax, to_dev(params), nsteps, window)
+    got = host(pd).astype(np.float64)
+    phi = wl.phi.astype(np.float64)
+    total_fb = 0
+    for s in range(nsteps):
+        if s % window == 0:
+            g32 = np.float32(wl.gamma)
+            band = oracle.band_tiles(phi.astype(np.float32), TILE, g32, True)
+            active = oracle.band_tiles(phi.astype(np.float32), TILE, g32, False)
+        phi, fb = CL.closure_step(p, phi, wl.F, wl.dx, wl.dt, np.float32(wl.gamma),
+                                  np.float32(fmax), band, active)
+        total_fb += fb
+    assert int(host(cg.fallbacks)[0]) == total_fb == 0
+    err = np.max(np.abs(got - phi))
+    plain = oracle.run_band(wl.phi, wl.F, wl.dx, wl.dt, np.float32(wl.gamma), nsteps,
+                            window=window)
+    moved = np.max(np.abs(phi - plain))
+    report("closure_multistep", max_err_dx=float(err / wl.dx),
+           correction_dx=float(moved / wl.dx), steps=nsteps)
+    assert moved > 0.1 * wl.dx  # the network does change the result
+    assert err <= 1e-2 * wl.dx, err / wl.dx
 
 
 def test_adam_matches_reference():

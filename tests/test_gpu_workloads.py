@@ -160,9 +160,11 @@ def test_torus_f16s_reduced():
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("n", [256])
 def test_torus_f16s_error_report(n):
-    """The scaled-FP16 torus recipe, 500 steps: error against the FP64 oracle
-    on the unquantised inputs, reported (near the front, over the tube, and
-    the Hausdorff distance of the fronts), bounded by FP16 rounding."""
+    """The scaled-FP16 torus recipe, 500 steps, against the FP64 oracle on the
+    unquantised inputs.  (a) With the GPU's band lists fed to the oracle the
+    difference is the storage precision alone: reported and bounded by FP16
+    rounding.  (b) With the oracle's own FP64 band decisions the lists can
+    differ at the band margin, which moves stale values; reported."""
     from paper_1612_04040_amd import metrics as M
 
     steps = 500
@@ -170,23 +172,45 @@ def test_torus_f16s_error_report(n):
     s = np.float32(wl.scale)
     h = W.quantize_f16s(wl.phi, s)
     bg = BandGrid((n, n, n), wl.tile, "f16s")
-    hd = torch.from_numpy(h).to(dev())
-    bg.run(hd, to_dev(wl.F), wl.dx, wl.dt, wl.gamma, steps, wl.window, scale=float(s))
+    hd, Fd = torch.from_numpy(h).to(dev()), to_dev(wl.F)
+    lists = []
+    for _ in range(steps // wl.window):
+        bg.build(hd, wl.gamma, dilate=True, scale=float(s))
+        lists.append(bg.band_list().numpy())
+        bg.step(hd, Fd, wl.dx, wl.dt, wl.window, scale=float(s))
     got = oracle.dequant_f16s(host(hd), s).astype(np.float64)
-    want = oracle.run_band(wl.phi.astype(np.float64), wl.F, wl.dx, wl.dt, np.float32(wl.gamma),
-                           steps, window=wl.window)
-    err = np.abs(got - want)
-    front = np.abs(want) < wl.dx
-    tube = np.abs(want) < wl.gamma
-    haus = M.hausdorff(M.zero_crossings(got, wl.dx), M.zero_crossings(want, wl.dx)) / wl.dx
-    # worst case: each store rounds to half an FP16 ulp of |phi|/s, times s
-    bound_front = steps * 2.0 ** -12 * float(s)
-    rec = dict(n=n, steps=steps, max_err_front_dx=float(err[front].max() / wl.dx),
-               max_err_tube_dx=float(err[tube].max() / wl.dx),
-               rms_err_front_dx=float(np.sqrt(np.mean(err[front] ** 2)) / wl.dx),
-               hausdorff_dx=haus, bound_front_dx=bound_front / wl.dx,
-               by_abs_phi_dx=error_by_band_distance(err, want, wl.dx))
+    same = wl.phi.astype(np.float64)
+    for tl in lists:
+        same = oracle.upwind_steps(same, wl.F, wl.dx, wl.dt, tl, wl.window, wl.tile)
+    own, own_lists = oracle.run_band(wl.phi.astype(np.float64), wl.F, wl.dx, wl.dt,
+                                     np.float32(wl.gamma), steps, window=wl.window,
+                                     record_tiles=True)
+    crossings = M.zero_crossings(got, wl.dx)
+    rec = dict(n=n, steps=steps,
+               windows_with_other_lists=int(sum(a.tolist() != b.tolist()
+                                                for a, b in zip(lists, own_lists))))
+    for name, want in (("same_lists", same), ("own_lists", own)):
+        err = np.abs(got - want)
+        front = np.abs(want) < wl.dx
+        tube = np.abs(want) < wl.gamma
+        rec[name] = dict(
+            max_err_front_dx=float(err[front].max() / wl.dx),
+            max_err_tube_dx=float(err[tube].max() / wl.dx),
+            rms_err_front_dx=float(np.sqrt(np.mean(err[front] ** 2)) / wl.dx),
+            hausdorff_dx=M.hausdorff(crossings, M.zero_crossings(want, wl.dx)) / wl.dx,
+            by_abs_phi_dx=error_by_band_distance(err, want, wl.dx))
+    # worst case: the update is non-expansive in the max norm, and each step
+    # adds at most one store rounding, half an FP16 ulp of the largest |phi|/s
+    # in the band, times s (plus the initial quantisation, the same size)
+    nx = ny = nz = n
+    band = np.zeros((nz // 8, ny // 8, nx // 8), bool)
+    for tl in lists:
+        band.reshape(-1)[tl] = True
+    mask = np.repeat(np.repeat(np.repeat(band, 8, 0), 8, 1), 8, 2)
+    hmax = float(max(np.abs(same[mask]).max(), np.abs(wl.phi[mask]).max())) / float(s)
+    half_ulp = 2.0 ** (np.floor(np.log2(hmax)) - 11)
+    rec["bound_dx"] = (steps + 1) * half_ulp * float(s) / wl.dx
     report("torus_f16s_error", **rec)
     print(f"[f16s torus {n}^3] {rec}", flush=True)
-    assert err[front].max() <= bound_front
-    assert haus <= 1.0
+    assert np.abs(got - same).max() <= rec["bound_dx"] * wl.dx
+    assert rec["same_lists"]["hausdorff_dx"] <= 1.0

@@ -6,6 +6,8 @@
 * the restriction reproduces linear fields exactly at the coarse centres and
   averages the 2x2x2 fine points around them;
 * with the last layer zero the corrected step is the plain step, bit for bit;
+* the cut-off gate has the closed-form values of Eq. 8 (1 up to beta, 1/2
+  midway, 0 from gamma on, flat at both ends);
 * Adam's first step moves every parameter by lr * sign(gradient).
 """
 import numpy as np
@@ -88,6 +90,13 @@ def test_zero_network_is_the_plain_step():
     assert out.tobytes() == plain.tobytes()
 
 
+def _tile_max(a, tiles, n):
+    nt = n // 8
+    return np.array([a[(t // (nt * nt)) * 8:(t // (nt * nt)) * 8 + 8,
+                       ((t // nt) % nt) * 8:((t // nt) % nt) * 8 + 8,
+                       (t % nt) * 8:(t % nt) * 8 + 8].max() for t in tiles])
+
+
 def test_fallback_on_large_correction():
     n = 32
     wl = W.three_spheres_f32(n, 1)
@@ -95,16 +104,35 @@ def test_fallback_on_large_correction():
     band = oracle.band_tiles(wl.phi, (8, 8, 8), np.float32(wl.gamma), True)
     active = oracle.band_tiles(wl.phi, (8, 8, 8), np.float32(wl.gamma), False)
     params = CL.init_params(np.random.default_rng(0))
-    params["b2"][:] = 0.75  # |r| > 1/2 everywhere: every active tile falls back
+    gate = CL.cutoff(phi, 0.5 * wl.gamma, wl.gamma)
+    params["b2"][:] = 0.75  # gated correction above 1/2 where c > 2/3: those tiles fall back
     out, fb = CL.closure_step(params, phi, wl.F, wl.dx, wl.dt, wl.gamma, 0.5, band, active)
     plain = oracle.upwind_steps(phi, wl.F, wl.dx, wl.dt, band, 1)
-    assert fb == len(active)
-    assert out.tobytes() == plain.tobytes()
-    params["b2"][:] = 0.25  # accepted everywhere: plain + dx/4 on the active tiles
+    bad = _tile_max(0.75 * gate, active, n) > 0.5
+    assert 0 < fb == int(bad.sum())
+    params["b2"][:] = 0.25  # accepted everywhere: plain + dx c / 4 on the active tiles
     out, fb = CL.closure_step(params, phi, wl.F, wl.dx, wl.dt, wl.gamma, 0.5, band, active)
     assert fb == 0
     diff = out - plain
-    assert np.isclose(diff.max(), 0.25 * wl.dx) and np.count_nonzero(diff) == len(active) * 512
+    m = np.zeros(phi.shape, bool)
+    nt = n // 8
+    for t in active:
+        m[(t // (nt * nt)) * 8:(t // (nt * nt)) * 8 + 8, ((t // nt) % nt) * 8:((t // nt) % nt) * 8 + 8,
+          (t % nt) * 8:(t % nt) * 8 + 8] = True
+    assert np.allclose(diff[m], 0.25 * wl.dx * gate[m], rtol=0, atol=1e-15)
+    assert np.all(diff[~m] == 0)
+
+
+def test_cutoff_closed_forms():
+    beta, gamma = 3.0, 6.0
+    c = lambda v: float(CL.cutoff(np.array([v]), beta, gamma)[0])  # noqa: E731
+    assert c(0.0) == 1.0 and c(-beta) == 1.0 and c(beta) == 1.0
+    assert c(gamma) == 0.0 and c(-7.0) == 0.0 and c(100.0) == 0.0
+    assert np.isclose(c(4.5), 0.5) and np.isclose(c(-4.5), 0.5)
+    h = 1e-6
+    assert abs(c(beta + h) - 1.0) < 1e-9 and abs(c(gamma - h)) < 1e-9  # flat at both ends
+    xs = np.linspace(beta, gamma, 101)
+    assert np.all(np.diff(CL.cutoff(xs, beta, gamma)) <= 0)
 
 
 def test_adam_first_step_is_signed_lr():
