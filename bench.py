@@ -59,14 +59,17 @@ def parse():
     return args
 
 
+STEP_KERNEL_SOURCES = ("ls_internal.h", "ls_stencil.h", "ls_step.hip")
+
+
 def kernel_source_digest():
+    """Digest of the sources the band step kernel is compiled from."""
     here = os.path.dirname(os.path.abspath(__file__))
     csrc = os.path.join(here, "paper_1612_04040_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(f.encode() + fh.read())
+    for f in STEP_KERNEL_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
