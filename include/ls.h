@@ -244,12 +244,16 @@ int ls_graph_destroy(void *graph);
  * (a run of run_width / tx consecutive band tiles of one tile row, at least
  * one tile, at most 32); blocks_per_cu: workgroups launched per compute unit
  * by the band step (0 = the occupancy limit).  Zero fields select the
- * defaults (run_width 32).  Results do not depend on the tuning, only speed
+ * defaults (run_width 32).  pipeline: whether a workgroup issues the loads of
+ * its next work item before updating the current one (software pipelining;
+ * it pays on grids that stream from HBM, where workgroups own several items,
+ * and costs registers).  Results do not depend on the tuning, only speed
  * does.  Not thread-safe against concurrent launches.
  * ------------------------------------------------------------------------- */
 typedef struct ls_tuning {
     int32_t run_width;
     int32_t blocks_per_cu;
+    int32_t pipeline; /* 0 auto (on when phi exceeds 1 GiB), 1 off, 2 on */
 } ls_tuning;
 int ls_set_tuning(const ls_tuning *t);
 int ls_get_tuning(ls_tuning *t);

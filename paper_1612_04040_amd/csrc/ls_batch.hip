@@ -431,11 +431,14 @@ __global__ __launch_bounds__(kBlock) void batch_point_count_kernel(
 
 using BatchFn = void (*)(StepGeom, StepArgs<float, float>);
 
-static BatchFn batch_kernel(const Shape4 &s, size_t *lds) {
-#define LS_BFAST(TX_, TY_, TZ_, R_)                                                   \
-    if (s.tx == TX_ && s.ty == TY_ && s.tz == TZ_ && s.R == R_) {                     \
-        *lds = FastCfg<float, float, TX_, TY_, TZ_, R_>::lds;                         \
-        return upwind_fast_kernel<float, float, false, TX_, TY_, TZ_, R_, true, true>; \
+bool use_pipeline(int64_t phi_bytes);  // ls_step.hip
+
+static BatchFn batch_kernel(const Shape4 &s, bool pipe, size_t *lds) {
+#define LS_BFAST(TX_, TY_, TZ_, R_)                                                          \
+    if (s.tx == TX_ && s.ty == TY_ && s.tz == TZ_ && s.R == R_) {                            \
+        *lds = FastCfg<float, float, TX_, TY_, TZ_, R_>::lds;                                \
+        return pipe ? upwind_fast_kernel<float, float, false, TX_, TY_, TZ_, R_, true, true, true> \
+                    : upwind_fast_kernel<float, float, false, TX_, TY_, TZ_, R_, true, true, false>; \
     }
     LS_BFAST(8, 8, 8, 4)
     LS_BFAST(8, 8, 8, 2)
@@ -538,12 +541,14 @@ static int batch_steps(const BatchLayout &L, float *phi, const float *F, float *
     args.dx = args.dt = args.dtdx = 0.f;
     args.scale = 1.f;
     const int64_t G = std::max<int64_t>(8, (int64_t(di.cus) * 32) & ~int64_t(7));
+    // the batch's phi as a whole decides, as for one grid
+    const bool pipe = use_pipeline(L.max_points * int64_t(sizeof(float)));
     for (int s = 0; s < nsteps; ++s) {
         args.cur = (s & 1) ? scratch : phi;
         args.nxt = (s & 1) ? phi : scratch;
         for (size_t gi = 0; gi < L.groups.size(); ++gi) {
             size_t lds = 0;
-            BatchFn k = batch_kernel(L.groups[gi].shape, &lds);
+            BatchFn k = batch_kernel(L.groups[gi].shape, pipe, &lds);
             args.range = ranges + gi;
             int64_t slot;
             if ((rc = stats_before(LS_KERNEL_UPWIND, stream, &slot)) != LS_OK) return rc;

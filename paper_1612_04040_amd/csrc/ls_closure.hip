@@ -320,46 +320,47 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
                 v1 = feat.F[gi] * feat.inv_fmax;
                 v2 = (feat.plain[gi] - ph) * feat.inv_dx;
             }
-            __bf16 *d = in + q * 4;
-            d[0] = to_bf16(v0);
-            d[1] = to_bf16(v1);
-            d[2] = to_bf16(v2);
-            d[3] = to_bf16(0.f);
+            __bf16 d[4] = {to_bf16(v0), to_bf16(v1), to_bf16(v2), to_bf16(0.f)};
+            *reinterpret_cast<uint2 *>(in + q * 4) = *reinterpret_cast<const uint2 *>(d);
         }
         if (threadIdx.x == 0) bad_s = 0;
         __syncthreads();
 
-        // layer 1: 12^3 outputs, 108 groups of 16
+        // layer 1: 12^3 outputs, 108 groups of 16.  Per lane, the LDS offset of
+        // each tap it feeds is fixed (tap = 8c + 2(lane/16) + h): precomputed.
         {
             bf16x8 wa[4];
+            int off[4][2];
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
+            for (int c = 0; c < 4; ++c) {
                 wa[c] = *reinterpret_cast<const bf16x8 *>(wp0 + (c * 64 + lane) * 8);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int tap = 8 * c + 2 * kq + h;
+                    off[c][h] = tap < kTaps
+                                    ? ((tap / 9) * kF0 + (tap / 3) % 3) * kF0 + tap % 3
+                                    : -1;
+                }
+            }
             float bb[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) bb[i] = params[kB0 + 4 * kq + i];
             for (int grp = wave; grp < (kF1 * kF1 * kF1) / 16; grp += kFusedWaves) {
                 const int pt = grp * 16 + j;
                 const int lx = pt % kF1, ly = (pt / kF1) % kF1, lz = pt / (kF1 * kF1);
+                const int q0 = (lz * kF0 + ly) * kF0 + lx;
                 f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    bf16x8 b;
+                    uint2 v[2];
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
-                        const int tap = 8 * c + 2 * kq + h;
-                        if (tap < kTaps) {
-                            const int dz = tap / 9, dy = (tap / 3) % 3, dxx = tap % 3;
-                            const int q = ((lz + dz) * kF0 + (ly + dy)) * kF0 + (lx + dxx);
-                            const uint2 v = *reinterpret_cast<const uint2 *>(in + q * 4);
-                            const __bf16 *e = reinterpret_cast<const __bf16 *>(&v);
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) b[4 * h + u] = e[u];
-                        } else {
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) b[4 * h + u] = to_bf16(0.f);
-                        }
+                        v[h] = make_uint2(0, 0);
+                        if (off[c][h] >= 0)
+                            v[h] = *reinterpret_cast<const uint2 *>(in + (q0 + off[c][h]) * 4);
                     }
+                    const bf16x8 b =
+                        __builtin_bit_cast(bf16x8, make_uint4(v[0].x, v[0].y, v[1].x, v[1].y));
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[c], b, acc, 0, 0, 0);
                 }
                 const int gx = x0 + lx - 2, gy = y0 + ly - 2, gz = z0 + lz - 2;
@@ -373,12 +374,19 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
         }
         __syncthreads();
 
-        // layer 2: 10^3 outputs, 63 groups of 16 (the last one partial)
+        // layer 2: 10^3 outputs, 63 groups of 16 (the last one partial);
+        // tap = 2c + (lane/16)/2, channels 8 ((lane/16) & 1) .. +7
         {
             bf16x8 wa[14];
+            int off[14];
 #pragma unroll
-            for (int c = 0; c < 14; ++c)
+            for (int c = 0; c < 14; ++c) {
                 wa[c] = *reinterpret_cast<const bf16x8 *>(wp1 + (c * 64 + lane) * 8);
+                const int tap = 2 * c + (kq >> 1);
+                off[c] = tap < kTaps
+                             ? (((tap / 9) * kF1 + (tap / 3) % 3) * kF1 + tap % 3) * 16 + 8 * (kq & 1)
+                             : -1;
+            }
             float bb[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) bb[i] = params[kB1 + 4 * kq + i];
@@ -387,18 +395,12 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
                 const int pt = grp * 16 + j;
                 const int ptc = min(pt, NP - 1);  // lanes past the end compute a copy
                 const int lx = ptc % kF2, ly = (ptc / kF2) % kF2, lz = ptc / (kF2 * kF2);
+                const int q0 = ((lz * kF1 + ly) * kF1 + lx) * 16;
                 f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int c = 0; c < 14; ++c) {
-                    const int tap = 2 * c + (kq >> 1);
-                    bf16x8 b;
-                    if (tap < kTaps) {
-                        const int dz = tap / 9, dy = (tap / 3) % 3, dxx = tap % 3;
-                        const int q = ((lz + dz) * kF1 + (ly + dy)) * kF1 + (lx + dxx);
-                        b = *reinterpret_cast<const bf16x8 *>(a0 + q * 16 + 8 * (kq & 1));
-                    } else {
-                        b = bf16x8{};
-                    }
+                    bf16x8 b = bf16x8{};
+                    if (off[c] >= 0) b = *reinterpret_cast<const bf16x8 *>(a0 + q0 + off[c]);
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[c], b, acc, 0, 0, 0);
                 }
                 const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z0 + lz - 1;
@@ -419,26 +421,26 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
         float rv[NG3];
         {
             bf16x8 wa[14];
+            int off[14];
 #pragma unroll
-            for (int c = 0; c < 14; ++c)
+            for (int c = 0; c < 14; ++c) {
                 wa[c] = *reinterpret_cast<const bf16x8 *>(wp2 + (c * 64 + lane) * 8);
+                const int tap = 2 * c + (kq >> 1);
+                off[c] = tap < kTaps
+                             ? (((tap / 9) * kF2 + (tap / 3) % 3) * kF2 + tap % 3) * 16 + 8 * (kq & 1)
+                             : -1;
+            }
             const float b2 = params[kB2];
 #pragma unroll
             for (int gi8 = 0; gi8 < NG3; ++gi8) {
                 const int pt = (wave + kFusedWaves * gi8) * 16 + j;
                 const int lx = pt & 7, ly = (pt >> 3) & 7, lz = pt >> 6;
+                const int q0 = ((lz * kF2 + ly) * kF2 + lx) * 16;
                 f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int c = 0; c < 14; ++c) {
-                    const int tap = 2 * c + (kq >> 1);
-                    bf16x8 b;
-                    if (tap < kTaps) {
-                        const int dz = tap / 9, dy = (tap / 3) % 3, dxx = tap % 3;
-                        const int q = ((lz + dz) * kF2 + (ly + dy)) * kF2 + (lx + dxx);
-                        b = *reinterpret_cast<const bf16x8 *>(a1 + q * 16 + 8 * (kq & 1));
-                    } else {
-                        b = bf16x8{};
-                    }
+                    bf16x8 b = bf16x8{};
+                    if (off[c] >= 0) b = *reinterpret_cast<const bf16x8 *>(a1 + q0 + off[c]);
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[c], b, acc, 0, 0, 0);
                 }
                 rv[gi8] = acc[0] + b2;

@@ -136,12 +136,17 @@ struct FastCfg {
 //      point, all into registers before using any;
 //  (2) stores them to the LDS box; (3) after a barrier evaluates its own
 //      points from the box and stores them.
+// PIPE: the loads (1) of the block's next item are issued before (3) of the
+// current one, so their latency overlaps the update (software pipelining over
+// the block's slice of items; it pays when blocks own several items, as on
+// grids that stream from HBM, at the cost of registers).
 // BATCH: the item's grid comes from the descriptor its record names (word 7);
 // PARTIAL: tiles at the high y/z faces may be partial (predicated rows).
 // A neighbour in a band tile is read from the current buffer, one in a tile
 // outside the band from phi (its value frozen for the call), one outside the
 // grid is the clamped point inside the item (zero-gradient boundary).
-template <class S, class FT, bool EXACT, int TX, int TY, int TZ, int R, bool BATCH, bool PARTIAL>
+template <class S, class FT, bool EXACT, int TX, int TY, int TZ, int R, bool BATCH, bool PARTIAL,
+          bool PIPE>
 __global__ __launch_bounds__(kBlock) void upwind_fast_kernel(StepGeom g, StepArgs<S, FT> a) {
     using K = FastCfg<S, FT, TX, TY, TZ, R>;
     using C = typename K::C;
@@ -160,6 +165,7 @@ __global__ __launch_bounds__(kBlock) void upwind_fast_kernel(StepGeom g, StepArg
     }
     int w0, w1;
     block_slice(first, end, &w0, &w1);
+    if (w0 >= w1) return;  // uniform
 
     const int lane = threadIdx.x & 63;
     const int lx = threadIdx.x % XL;
@@ -176,7 +182,25 @@ __global__ __launch_bounds__(kBlock) void upwind_fast_kernel(StepGeom g, StepArg
     const int xside = threadIdx.x & 1;
     const int xly = (threadIdx.x >> 1) % TY, xlz = (threadIdx.x >> 1) / TY;
 
-    for (int w = w0; w < w1; ++w) {
+    // uniform description of one item, and the registers its loads fill
+    struct Item {
+        bool ok;
+        int nx, ny, plane, W, H, D;
+        int64_t base;
+        C dtdx, dx, dt;
+    };
+    struct Regs {
+        S raw[NOWN];
+        FT fv[NOWN];
+        S hv[NHALO];
+        int hlds[NHALO];
+        bool hok[NHALO];
+        S xv;
+        bool xrow_ok;
+    };
+
+    // record of item w -> geometry, then the global loads of this thread
+    auto fetch = [&](int w, Item &it, Regs &r) {
         int rv = 0;
         if (lane < kItemWords) rv = a.rec[static_cast<int64_t>(w) * kItemWords + lane];
         const int t0 = __builtin_amdgcn_readlane(rv, 0);
@@ -184,22 +208,24 @@ __global__ __launch_bounds__(kBlock) void upwind_fast_kernel(StepGeom g, StepArg
         const uint32_t m0 = __builtin_amdgcn_readlane(rv, 2), m1 = __builtin_amdgcn_readlane(rv, 3);
         const uint32_t m2 = __builtin_amdgcn_readlane(rv, 4), m3 = __builtin_amdgcn_readlane(rv, 5);
         const uint32_t mx = __builtin_amdgcn_readlane(rv, 6);
-
-        int nx, ny, nz, ntx, nty, ntiles;
+        int nz, ntx, nty, ntiles;
         int64_t goff = 0;
-        C dtdx = a.dtdx, dx = a.dx, dt = a.dt;
+        it.dtdx = a.dtdx, it.dx = a.dx, it.dt = a.dt;
         if constexpr (BATCH) {
             const BatchInst &d = a.inst[__builtin_amdgcn_readlane(rv, 7)];
-            nx = d.nx, ny = d.ny, nz = d.nz, ntx = d.ntx, nty = d.nty, ntiles = d.ntiles;
+            it.nx = d.nx, it.ny = d.ny, nz = d.nz, ntx = d.ntx, nty = d.nty, ntiles = d.ntiles;
             goff = d.offset;
-            dtdx = static_cast<C>(d.dtdx);
-            dx = static_cast<C>(d.dx);
-            dt = static_cast<C>(d.dt);
+            it.dtdx = static_cast<C>(d.dtdx);
+            it.dx = static_cast<C>(d.dx);
+            it.dt = static_cast<C>(d.dt);
         } else {
-            nx = g.nx, ny = g.ny, nz = g.nz, ntx = g.ntx, nty = g.nty, ntiles = g.ntiles;
+            it.nx = g.nx, it.ny = g.ny, nz = g.nz, ntx = g.ntx, nty = g.nty, ntiles = g.ntiles;
         }
-        if (t0 < 0 || t0 >= ntiles) continue;  // invalid id: skipped (uniform)
+        it.ok = t0 >= 0 && t0 < ntiles;  // an invalid id is skipped (uniform)
+        if (!it.ok) return;
+        const int nx = it.nx, ny = it.ny;
         const int plane = ny * nx;
+        it.plane = plane;
         const int ti0 = t0 % ntx;
         const int rr = t0 / ntx;
         const int tj = rr % nty, tk = rr / nty;
@@ -207,32 +233,25 @@ __global__ __launch_bounds__(kBlock) void upwind_fast_kernel(StepGeom g, StepArg
         const int W = min(len * TX, nx - x0);
         const int H = PARTIAL ? min(TY, ny - y0) : TY;
         const int D = PARTIAL ? min(TZ, nz - z0) : TZ;
-        const int64_t base = goff + (static_cast<int64_t>(z0) * ny + y0) * nx + x0;
-        const S *cur = a.cur + base;
-        const S *orig = a.orig + base;
-        const FT *Fb = a.F + base;
-        S *nxt = a.nxt + base;
+        it.W = W, it.H = H, it.D = D;
+        it.base = goff + (static_cast<int64_t>(z0) * ny + y0) * nx + x0;
+        const S *cur = a.cur + it.base;
+        const S *orig = a.orig + it.base;
+        const FT *Fb = a.F + it.base;
         // faces on the domain boundary: the clamped neighbour lies in the item
         const int ebits = (y0 == 0 ? 1 : 0) | (y0 + H == ny ? 2 : 0) | (z0 == 0 ? 4 : 0) |
                           (z0 + D == nz ? 8 : 0);
         const bool col_ok = lx < W;
         const int toff = lz0 * plane + ly0 * nx + lx;
-
-        // (1) loads, all issued before any is used
-        S raw[NOWN];
-        FT fv[NOWN];
 #pragma unroll
         for (int q = 0; q < NOWN; ++q) {
             const bool ok = col_ok && (!PARTIAL || (ly0 + dly(q) < H && lz0 + dlz(q) < D));
             if (ok) {
                 const int u = dlz(q) * plane + dly(q) * nx;  // uniform
-                raw[q] = (cur + u)[toff];
-                fv[q] = (Fb + u)[toff];
+                r.raw[q] = (cur + u)[toff];
+                r.fv[q] = (Fb + u)[toff];
             }
         }
-        S hv[NHALO];
-        int hlds[NHALO];
-        bool hok[NHALO];
 #pragma unroll
         for (int q = 0; q < NHALO; ++q) {
             const int h = lr + q * RP;  // y-face rows (2 per z) first, then z-face rows
@@ -255,55 +274,87 @@ __global__ __launch_bounds__(kBlock) void upwind_fast_kernel(StepGeom g, StepArg
                 ok = hh < 2 * TY && ly < H;
             }
             ok = ok && col_ok;
-            hok[q] = ok;
-            hlds[q] = (lz + 1) * SXY + (ly + 1) * SX + lx + 1;
+            r.hok[q] = ok;
+            r.hlds[q] = (lz + 1) * SXY + (ly + 1) * SX + lx + 1;
             const bool hi = face & 1, zf = face & 2;
             const bool clamp = (ebits >> (face & 3)) & 1;
             const uint32_t mk = zf ? (hi ? m3 : m2) : (hi ? m1 : m0);
             const bool in = clamp || ((mk >> lt) & 1u);
             const int o = clamp ? (lzc * plane + lyc * nx + lx) : (lz * plane + ly * nx + lx);
-            if (ok && in) hv[q] = cur[o];
-            if (ok && !in) hv[q] = orig[o];
+            if (ok && in) r.hv[q] = cur[o];
+            if (ok && !in) r.hv[q] = orig[o];
         }
-        S xv;
-        const bool xrow_ok = xok && (!PARTIAL || (xly < H && xlz < D));
+        r.xrow_ok = xok && (!PARTIAL || (xly < H && xlz < D));
         const int cx = xside ? (x0 + W < nx ? W : W - 1) : (x0 > 0 ? -1 : 0);
-        {
-            const bool in = (cx >= 0 && cx < W) || ((mx >> xside) & 1u);
-            const int o = xlz * plane + xly * nx + cx;
-            if (xrow_ok && in) xv = cur[o];
-            if (xrow_ok && !in) xv = orig[o];
-        }
+        const bool in = (cx >= 0 && cx < W) || ((mx >> xside) & 1u);
+        const int o = xlz * plane + xly * nx + cx;
+        if (r.xrow_ok && in) r.xv = cur[o];
+        if (r.xrow_ok && !in) r.xv = orig[o];
+    };
 
-        // (2) to LDS
-        if (col_ok) {
+    // (2) registers -> LDS box
+    auto stage = [&](const Item &it, const Regs &r) {
+        if (lx < it.W) {
 #pragma unroll
             for (int q = 0; q < NOWN; ++q)
-                if (!PARTIAL || (ly0 + dly(q) < H && lz0 + dlz(q) < D))
-                    box[lbase + dlz(q) * SXY + dly(q) * SX] = Codec<S>::load(raw[q], a.scale);
+                if (!PARTIAL || (ly0 + dly(q) < it.H && lz0 + dlz(q) < it.D))
+                    box[lbase + dlz(q) * SXY + dly(q) * SX] = Codec<S>::load(r.raw[q], a.scale);
         }
 #pragma unroll
         for (int q = 0; q < NHALO; ++q)
-            if (hok[q]) box[hlds[q]] = Codec<S>::load(hv[q], a.scale);
-        if (xrow_ok)
-            box[(xlz + 1) * SXY + (xly + 1) * SX + (xside ? W + 1 : 0)] = Codec<S>::load(xv, a.scale);
-        __syncthreads();  // box complete
+            if (r.hok[q]) box[r.hlds[q]] = Codec<S>::load(r.hv[q], a.scale);
+        if (r.xrow_ok)
+            box[(xlz + 1) * SXY + (xly + 1) * SX + (xside ? it.W + 1 : 0)] =
+                Codec<S>::load(r.xv, a.scale);
+    };
 
-        // (3) update
-        if (col_ok) {
+    // (3) update of the own points from the box
+    auto update = [&](const Item &it, const Regs &r) {
+        if (lx >= it.W) return;
+        S *nxt = a.nxt + it.base;
+        const int toff = lz0 * it.plane + ly0 * it.nx + lx;
 #pragma unroll
-            for (int q = 0; q < NOWN; ++q) {
-                if (PARTIAL && !(ly0 + dly(q) < H && lz0 + dlz(q) < D)) continue;
-                const int o = lbase + dlz(q) * SXY + dly(q) * SX;
-                const C f = static_cast<C>(fv[q]);
-                const C v = upwind_point<C, EXACT>(box[o], box[o - 1], box[o + 1], box[o - SX],
-                                                   box[o + SX], box[o - SXY], box[o + SXY], f, dx,
-                                                   dt, dtdx);
-                const S out = (f == C(0)) ? raw[q] : Codec<S>::store(v, a.scale);
-                (nxt + dlz(q) * plane + dly(q) * nx)[toff] = out;
+        for (int q = 0; q < NOWN; ++q) {
+            if (PARTIAL && !(ly0 + dly(q) < it.H && lz0 + dlz(q) < it.D)) continue;
+            const int o = lbase + dlz(q) * SXY + dly(q) * SX;
+            const C f = static_cast<C>(r.fv[q]);
+            const C v = upwind_point<C, EXACT>(box[o], box[o - 1], box[o + 1], box[o - SX],
+                                               box[o + SX], box[o - SXY], box[o + SXY], f, it.dx,
+                                               it.dt, it.dtdx);
+            const S out = (f == C(0)) ? r.raw[q] : Codec<S>::store(v, a.scale);
+            (nxt + dlz(q) * it.plane + dly(q) * it.nx)[toff] = out;
+        }
+    };
+
+    if constexpr (PIPE) {
+        Item cur;
+        Regs rc;
+        fetch(w0, cur, rc);
+        for (int w = w0; w < w1; ++w) {
+            if (cur.ok) stage(cur, rc);
+            __syncthreads();  // box complete
+            Item nx;
+            Regs rn;
+            const bool more = w + 1 < w1;  // uniform
+            if (more) fetch(w + 1, nx, rn);
+            if (cur.ok) update(cur, rc);
+            __syncthreads();  // box free for the next item
+            if (more) {
+                cur = nx;
+                rc = rn;
             }
         }
-        __syncthreads();  // box free for the next item
+    } else {
+        for (int w = w0; w < w1; ++w) {
+            Item cur;
+            Regs rc;
+            fetch(w, cur, rc);
+            if (!cur.ok) continue;  // uniform
+            stage(cur, rc);
+            __syncthreads();  // box complete
+            update(cur, rc);
+            __syncthreads();  // box free for the next item
+        }
     }
 }
 

@@ -246,9 +246,18 @@ __global__ __launch_bounds__(kBlock) void map_set_kernel(uint8_t *map, const int
 // host side
 
 // Process-wide launch tuning (ls_set_tuning); 0 fields mean the defaults.
-static ls_tuning g_tuning = {0, 0};
+static ls_tuning g_tuning = {0, 0, 0};
 constexpr int kDefaultRunWidth = 32;
 constexpr int kDefaultBlocksPerCu = 32;
+// Grids whose phi exceeds this stream from HBM (beyond the Infinity Cache)
+// with several work items per workgroup: the software-pipelined step pays.
+constexpr int64_t kPipelineBytes = int64_t(1) << 30;
+
+bool use_pipeline(int64_t phi_bytes) {
+    if (g_tuning.pipeline == 1) return false;
+    if (g_tuning.pipeline == 2) return true;
+    return phi_bytes > kPipelineBytes;
+}
 
 static int run_width() { return g_tuning.run_width > 0 ? g_tuning.run_width : kDefaultRunWidth; }
 
@@ -327,11 +336,15 @@ template <class S, class FT, bool EXACT>
 static UpwindFn<S, FT, EXACT> select_upwind_kernel(const StepGeom &sg, int nown, int nhalo,
                                                    size_t *lds) {
     const bool whole_yz = sg.ny % sg.ty == 0 && sg.nz % sg.tz == 0;
+    const bool pipe = use_pipeline(int64_t(sg.nx) * sg.ny * sg.nz * int64_t(sizeof(S)));
 #define LS_FAST(TX_, TY_, TZ_, R_)                                                          \
     if (sg.tx == TX_ && sg.ty == TY_ && sg.tz == TZ_ && sg.R == R_) {                       \
         *lds = FastCfg<S, FT, TX_, TY_, TZ_, R_>::lds;                                      \
-        if (whole_yz) return upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, false>; \
-        return upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, true>;             \
+        if (whole_yz)                                                                       \
+            return pipe ? upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, false, true>  \
+                        : upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, false, false>; \
+        return pipe ? upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, true, true>        \
+                    : upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, true, false>;      \
     }
     LS_FAST(8, 8, 8, 4)
     LS_FAST(8, 8, 8, 2)
@@ -611,7 +624,8 @@ extern "C" {
 
 int ls_set_tuning(const ls_tuning *t) {
     ls::clear_error();
-    if (!t || t->run_width < 0 || t->blocks_per_cu < 0 || t->blocks_per_cu > 64) {
+    if (!t || t->run_width < 0 || t->blocks_per_cu < 0 || t->blocks_per_cu > 64 ||
+        t->pipeline < 0 || t->pipeline > 2) {
         ls::set_error("tuning: NULL or out-of-range field");
         return LS_ERR_ARG;
     }
@@ -627,6 +641,7 @@ int ls_get_tuning(ls_tuning *t) {
     }
     t->run_width = ls::run_width();
     t->blocks_per_cu = ls::g_tuning.blocks_per_cu;
+    t->pipeline = ls::g_tuning.pipeline;
     return LS_OK;
 }
 

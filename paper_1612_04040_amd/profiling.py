@@ -51,17 +51,31 @@ def kernel_counters(db):
     return {key: (len(v), sum(v) / len(v)) for key, v in acc.items()}
 
 
-def traffic(fetch_db, write_db, kernel):
-    """HBM bytes per dispatch of `kernel`, calibrated by the copy kernel."""
+def _mean_over(counters, prefix, name):
+    """Dispatch-weighted mean of counter `name` over the kernels starting with prefix."""
+    n = tot = 0.0
+    for (k, c), (d, v) in counters.items():
+        if c == name and k.startswith(prefix):
+            n += d
+            tot += d * v
+    if n == 0:
+        raise KeyError(f"no {name} samples for kernels starting with {prefix}")
+    return tot / n, int(n)
+
+
+def traffic(fetch_db, write_db, prefix):
+    """HBM bytes per dispatch of the kernels starting with `prefix` (all their
+    variants together), calibrated by the copy kernel."""
     f = kernel_counters(fetch_db)
     w = kernel_counters(write_db)
     f_cal = f[(CALIB_KERNEL, "FETCH_SIZE")][1] * 1024.0
     w_cal = w[(CALIB_KERNEL, "WRITE_SIZE")][1] * 1024.0
     rf, wf = CALIB_BYTES / f_cal, CALIB_BYTES / w_cal
-    fk = f[(kernel, "FETCH_SIZE")][1] * 1024.0 * rf
-    wk = w[(kernel, "WRITE_SIZE")][1] * 1024.0 * wf
+    fm, nf = _mean_over(f, prefix, "FETCH_SIZE")
+    wm, nw = _mean_over(w, prefix, "WRITE_SIZE")
+    fk, wk = fm * 1024.0 * rf, wm * 1024.0 * wf
     return {"read_bytes": fk, "write_bytes": wk, "bytes_per_launch": fk + wk,
-            "fetch_scale": rf, "write_scale": wf}
+            "fetch_scale": rf, "write_scale": wf, "dispatches": [nf, nw]}
 
 
 def main(argv=None):
@@ -94,8 +108,8 @@ def main(argv=None):
         if not match:
             print(f"no kernel starting with {a.kernel}", file=sys.stderr)
             return 1
-        rec = traffic(a.fetch_db, a.write_db, match[0])
-        rec["kernel"] = match[0]
+        rec = traffic(a.fetch_db, a.write_db, a.kernel)
+        rec["kernels"] = match
         rec["source_digest"] = a.digest
         data = {}
         if os.path.exists(a.out):
