@@ -51,10 +51,10 @@ def fine_trajectory(case, nsteps, device):
 
 
 class Problem:
-    """Device inputs of one seed on the coarse grid."""
+    """Device inputs of one seed on the coarse grid (plane=True: a plane front)."""
 
-    def __init__(self, seed, n_fine, nsteps, device, with_trajectory=True):
-        self.case = W.ClosureCase(seed, n_fine)
+    def __init__(self, seed, n_fine, nsteps, device, with_trajectory=True, plane=False):
+        self.case = (W.PlaneCase if plane else W.ClosureCase)(seed, n_fine)
         nc = self.case.n_coarse
         self.F = _dev(self.case.F(nc), device)
         self.snaps = fine_trajectory(self.case, nsteps, device) if with_trajectory else None

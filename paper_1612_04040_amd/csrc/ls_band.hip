@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void band_flag_list_kernel(
     const S *__restrict__ phi, int nx, int ny, int nz, int tx, int ty, int tz, int ntx, int nty,
     int ntiles_cap, typename Codec<S>::C gamma, typename Codec<S>::C scale,
     const int32_t *__restrict__ list, const int32_t *__restrict__ list_count,
-    uint8_t *__restrict__ a_flags) {
+    uint8_t *__restrict__ a_flags, bool vec_rows) {
     const int n = min(*list_count, ntiles_cap);
     const int lane = threadIdx.x & 63;
     const int waves = gridDim.x * (kBlock / 64);
@@ -264,14 +264,31 @@ __global__ __launch_bounds__(kBlock) void band_flag_list_kernel(
         const int tj = r % nty, tk = r / nty;
         const int x0 = ti * tx, y0 = tj * ty, z0 = tk * tz;
         const int W = min(tx, nx - x0), H = min(ty, ny - y0), D = min(tz, nz - z0);
-        const int npts = W * H * D;
         bool hit = false;
+        constexpr int V = Vec16<S>::V;
+        if (vec_rows && W == tx) {
+            // whole 16-byte vectors along x: lane -> (row, vector of the row)
+            const int vpr = tx / V;  // vectors per row
+            const int nv = vpr * H * D;
+            for (int q = lane; q < nv; q += 64) {
+                const int c = q % vpr, rr = q / vpr;
+                const int ly = rr % H, lz = rr / H;
+                const int64_t gi =
+                    (static_cast<int64_t>(z0 + lz) * ny + (y0 + ly)) * nx + x0 + c * V;
+                const Vec16<S> v = *reinterpret_cast<const Vec16<S> *>(phi + gi);
+#pragma unroll
+                for (int e = 0; e < V; ++e) hit |= fabs(Codec<S>::load(v.v[e], scale)) < gamma;
+            }
+        } else {
+            const int npts = W * H * D;
 #pragma unroll 8
-        for (int q = lane; q < npts; q += 64) {
-            const int lx = q % W, rr = q / W;
-            const int ly = rr % H, lz = rr / H;
-            const int64_t gi = (static_cast<int64_t>(z0 + lz) * ny + (y0 + ly)) * nx + x0 + lx;
-            hit |= fabs(Codec<S>::load(phi[gi], scale)) < gamma;
+            for (int q = lane; q < npts; q += 64) {
+                const int lx = q % W, rr = q / W;
+                const int ly = rr % H, lz = rr / H;
+                const int64_t gi =
+                    (static_cast<int64_t>(z0 + lz) * ny + (y0 + ly)) * nx + x0 + lx;
+                hit |= fabs(Codec<S>::load(phi[gi], scale)) < gamma;
+            }
         }
         const bool any = __ballot(hit) != 0;
         if (lane == 0) a_flags[t] = any ? 1 : 0;
@@ -406,11 +423,15 @@ int band_rebuild(const S *phi, typename Codec<S>::C scale, const ls_grid *grid,
     if ((rc = device_info(&di)) != LS_OK) return rc;
     const unsigned blocks =
         static_cast<unsigned>(std::min<int64_t>(cdiv64(g.ntiles, kBlock / 64), int64_t(di.cus) * 16));
+    // rows of whole tiles load as 16-byte vectors when every row start is aligned
+    constexpr int V = Vec16<S>::V;
+    const bool vec_rows = g.tx % V == 0 && g.nx % V == 0 &&
+                          reinterpret_cast<uintptr_t>(phi) % 16 == 0;
     int64_t slot;
     if ((rc = stats_before(LS_KERNEL_BAND_FLAG, stream, &slot)) != LS_OK) return rc;
     hipLaunchKernelGGL(band_flag_list_kernel<S>, dim3(blocks), dim3(kBlock), 0, stream, phi, g.nx,
                        g.ny, g.nz, g.tx, g.ty, g.tz, g.ntx, g.nty, static_cast<int>(g.ntiles),
-                       gamma, scale, prev_tiles, prev_ntiles_dev, ws + w.a_flags);
+                       gamma, scale, prev_tiles, prev_ntiles_dev, ws + w.a_flags, vec_rows);
     LS_LAUNCH_CHECK("band_flag_list_kernel");
     if ((rc = stats_after(LS_KERNEL_BAND_FLAG, stream, slot)) != LS_OK) return rc;
     return band_finish(g, ws, 1, tiles, ntiles_dev, stream);

@@ -431,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void batch_point_count_kernel(
 
 using BatchFn = void (*)(StepGeom, StepArgs<float, float>);
 
-bool use_pipeline(int64_t phi_bytes);  // ls_step.hip
+bool pipeline_forced();  // ls_step.hip
 
 static BatchFn batch_kernel(const Shape4 &s, bool pipe, size_t *lds) {
 #define LS_BFAST(TX_, TY_, TZ_, R_)                                                          \
@@ -541,8 +541,9 @@ static int batch_steps(const BatchLayout &L, float *phi, const float *F, float *
     args.dx = args.dt = args.dtdx = 0.f;
     args.scale = 1.f;
     const int64_t G = std::max<int64_t>(8, (int64_t(di.cus) * 32) & ~int64_t(7));
-    // the batch's phi as a whole decides, as for one grid
-    const bool pipe = use_pipeline(L.max_points * int64_t(sizeof(float)));
+    // software pipelining is on only when asked for: measured slower on the
+    // 256-grid batch (its predicated kernels need the registers)
+    const bool pipe = pipeline_forced();
     for (int s = 0; s < nsteps; ++s) {
         args.cur = (s & 1) ? scratch : phi;
         args.nxt = (s & 1) ? phi : scratch;

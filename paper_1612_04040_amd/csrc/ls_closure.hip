@@ -287,6 +287,10 @@ constexpr size_t kFusedIn = size_t(kF0) * kF0 * kF0 * 4;  // bf16 elements
 constexpr size_t kFusedA0 = size_t(kF1) * kF1 * kF1 * 16;
 constexpr size_t kFusedA1 = size_t(kF2) * kF2 * kF2 * 16;
 constexpr size_t kFusedLds = 2 * (kFusedIn + kFusedA0 + kFusedA1);
+// activations are stored as two planes of 8 channels (channels 0-7, then
+// 8-15), 16 bytes per point: the 16 points of an MFMA column block read 256
+// contiguous bytes, free of LDS bank conflicts
+constexpr int kHalf0 = kF1 * kF1 * kF1 * 8, kHalf1 = kF2 * kF2 * kF2 * 8;
 constexpr int kFusedBlock = 512, kFusedWaves = kFusedBlock / 64;
 
 __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
@@ -369,7 +373,8 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
                 __bf16 ab[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) ab[i] = to_bf16(inside ? silu_f(acc[i] + bb[i]) : 0.f);
-                *reinterpret_cast<uint2 *>(a0 + pt * 16 + 4 * kq) = *reinterpret_cast<uint2 *>(ab);
+                *reinterpret_cast<uint2 *>(a0 + (kq >> 1) * kHalf0 + pt * 8 + 4 * (kq & 1)) =
+                    *reinterpret_cast<uint2 *>(ab);
             }
         }
         __syncthreads();
@@ -384,7 +389,8 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
                 wa[c] = *reinterpret_cast<const bf16x8 *>(wp1 + (c * 64 + lane) * 8);
                 const int tap = 2 * c + (kq >> 1);
                 off[c] = tap < kTaps
-                             ? (((tap / 9) * kF1 + (tap / 3) % 3) * kF1 + tap % 3) * 16 + 8 * (kq & 1)
+                             ? (((tap / 9) * kF1 + (tap / 3) % 3) * kF1 + tap % 3) * 8 +
+                                   (kq & 1) * kHalf0
                              : -1;
             }
             float bb[4];
@@ -395,7 +401,7 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
                 const int pt = grp * 16 + j;
                 const int ptc = min(pt, NP - 1);  // lanes past the end compute a copy
                 const int lx = ptc % kF2, ly = (ptc / kF2) % kF2, lz = ptc / (kF2 * kF2);
-                const int q0 = ((lz * kF1 + ly) * kF1 + lx) * 16;
+                const int q0 = ((lz * kF1 + ly) * kF1 + lx) * 8;
                 f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int c = 0; c < 14; ++c) {
@@ -410,7 +416,7 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
 #pragma unroll
                 for (int i = 0; i < 4; ++i) ab[i] = to_bf16(inside ? silu_f(acc[i] + bb[i]) : 0.f);
                 if (pt < NP)
-                    *reinterpret_cast<uint2 *>(a1 + pt * 16 + 4 * kq) =
+                    *reinterpret_cast<uint2 *>(a1 + (kq >> 1) * kHalf1 + pt * 8 + 4 * (kq & 1)) =
                         *reinterpret_cast<uint2 *>(ab);
             }
         }
@@ -427,7 +433,8 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
                 wa[c] = *reinterpret_cast<const bf16x8 *>(wp2 + (c * 64 + lane) * 8);
                 const int tap = 2 * c + (kq >> 1);
                 off[c] = tap < kTaps
-                             ? (((tap / 9) * kF2 + (tap / 3) % 3) * kF2 + tap % 3) * 16 + 8 * (kq & 1)
+                             ? (((tap / 9) * kF2 + (tap / 3) % 3) * kF2 + tap % 3) * 8 +
+                                   (kq & 1) * kHalf1
                              : -1;
             }
             const float b2 = params[kB2];
@@ -435,7 +442,7 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
             for (int gi8 = 0; gi8 < NG3; ++gi8) {
                 const int pt = (wave + kFusedWaves * gi8) * 16 + j;
                 const int lx = pt & 7, ly = (pt >> 3) & 7, lz = pt >> 6;
-                const int q0 = ((lz * kF2 + ly) * kF2 + lx) * 16;
+                const int q0 = ((lz * kF2 + ly) * kF2 + lx) * 8;
                 f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int c = 0; c < 14; ++c) {

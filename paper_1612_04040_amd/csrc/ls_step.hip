@@ -253,6 +253,8 @@ constexpr int kDefaultBlocksPerCu = 32;
 // with several work items per workgroup: the software-pipelined step pays.
 constexpr int64_t kPipelineBytes = int64_t(1) << 30;
 
+bool pipeline_forced() { return g_tuning.pipeline == 2; }
+
 bool use_pipeline(int64_t phi_bytes) {
     if (g_tuning.pipeline == 1) return false;
     if (g_tuning.pipeline == 2) return true;

@@ -315,3 +315,27 @@ class ClosureCase:
     def F(self, n):
         return sinusoid3((n, n, n), 1.0 / n, amp=self.amp, k=self.k, phase=self.phase,
                          bias=self.bias, dtype=np.float32)
+
+
+class PlaneCase(ClosureCase):
+    """A closure problem with a plane front phi = n.x - c (random unit normal,
+    c in [0.35, 0.65]) and a constant speed of either sign (|F| in [0.3, 1]):
+    the first-order scheme advances it exactly away from the grid faces, so
+    the correction it asks for is zero there."""
+
+    def __init__(self, seed, n_fine=512, ratio=4):
+        super().__init__(seed, n_fine, ratio)
+        rng = np.random.default_rng(10_000 + seed)
+        v = rng.standard_normal(3)
+        self.normal = v / np.linalg.norm(v)
+        self.offset = float(np.dot(self.normal, [0.5, 0.5, 0.5])) + float(rng.uniform(-0.15, 0.15))
+        self.speed = float(rng.uniform(0.3, 1.0)) * (1.0 if rng.random() < 0.5 else -1.0)
+        self.fmax = float(np.float32(abs(self.speed)))
+        self.dt_fine = float(np.float32(0.5 * self.dx_fine / self.fmax))
+        self.dt_coarse = float(np.float32(ratio * self.dt_fine))
+
+    def phi(self, n):
+        return plane((n, n, n), 1.0 / n, tuple(self.normal), self.offset, dtype=np.float32)
+
+    def F(self, n):
+        return np.full((n, n, n), self.speed, dtype=np.float32)
