@@ -311,11 +311,13 @@ int ls_copy_f32(float *dst, const float *src, int64_t n, void *stream);
  *     c0 = clip(phi / gamma, -2, 2),  c1 = F / fmax,  c2 = (plain - phi) / dx
  * (plain = phi after one plain step, Eq. 3) to a correction r, and the
  * corrected step is
- *     phi^{n+1} = plain + dx * c(phi) * r    on the active tiles A (Eq. 6 in
+ *     phi^{n+1} = plain + k,  k = dx * c(phi) * r clipped to
+ *                 |k| <= |plain - phi| / 2,  on the active tiles A (Eq. 6 in
  *                                            tile form),
  *     phi^{n+1} = plain                      elsewhere in the band U,
  * with c the cut-off function of Eq. 8 for beta = gamma / 2 (1 near the
- * front, 0 from |phi| = gamma on), except that an active tile where some
+ * front, 0 from |phi| = gamma on), and the clip a limiter (the correction
+ * never reverses or stalls the plain step), except that an active tile where some
  * c(phi) * r is non-finite or above 1/2 in magnitude takes the plain step (a
  * fallback, counted).  Activations outside
  * U count as zero; since A lies one tile inside U and the network sees three

@@ -19,10 +19,11 @@ Conventions (readings of a spec addition; the paper has no network):
                c(phi) = 1 for |phi| <= beta, (|phi| - gamma)^2 (2|phi| + gamma
                - 3 beta) / (gamma - beta)^3 for beta < |phi| <= gamma, 0 beyond,
                with beta = gamma / 2: it acts near the front only.
-  update       on the active tiles: phi + delta_plain + dx_c * c(phi) * r;
-               elsewhere in the band the plain step; a tile where some
-               c(phi) * r is non-finite or exceeds 1/2 in magnitude falls back
-               to the plain step.
+  update       on the active tiles: phi + delta_plain + k, with the correction
+               k = dx_c * c(phi) * r limited to |k| <= |delta_plain| / 2 (it
+               never reverses or stalls the plain step); elsewhere in the band
+               the plain step; a tile where some c(phi) * r is non-finite or
+               exceeds 1/2 in magnitude falls back to the plain step.
   loss         mean over active points of (phi_pred - phi_target)^2 / dx_c^2
                = mean (c r - r*)^2 with r* = (phi_target - phi - delta_plain)/dx_c.
 """
@@ -165,9 +166,9 @@ def adam_step(params, grads, state, lr, beta1=0.9, beta2=0.999, eps=1e-8):
 
 
 def closure_step(params, phi_c, F_c, dx, dt, gamma, fmax, band, active, tile=(8, 8, 8)):
-    """One corrected coarse step: plain on the band, plus dx*c(phi)*r on the
-    active tiles whose gated correction is finite and at most 1/2 (else
-    plain)."""
+    """One corrected coarse step: plain on the band, plus dx*c(phi)*r (limited
+    to half the plain increment) on the active tiles whose gated correction is
+    finite and at most 1/2 (else plain)."""
     delta = plain_increment(phi_c, F_c, dx, dt, band, tile)
     feat = features(phi_c, F_c, delta, dx, gamma, fmax)
     r, _ = forward(params, feat)
@@ -185,5 +186,6 @@ def closure_step(params, phi_c, F_c, dx, dt, gamma, fmax, band, active, tile=(8,
         if not np.all(np.isfinite(rt)) or np.max(np.abs(rt)) > 0.5:
             fallbacks += 1
             continue
-        out[sl] += dx * rt
+        lim = 0.5 * np.abs(delta[sl])
+        out[sl] += np.clip(dx * rt, -lim, lim)
     return out, fallbacks

@@ -291,13 +291,14 @@ constexpr size_t kFusedLds = 2 * (kFusedIn + kFusedA0 + kFusedA1);
 // 8-15), 16 bytes per point: the 16 points of an MFMA column block read 256
 // contiguous bytes, free of LDS bank conflicts
 constexpr int kHalf0 = kF1 * kF1 * kF1 * 8, kHalf1 = kF2 * kF2 * kF2 * 8;
+constexpr float kCorrLimit = 0.5f;  // |correction| <= kCorrLimit * |plain increment|
 constexpr int kFusedBlock = 512, kFusedWaves = kFusedBlock / 64;
 
 __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
     ConvGeo g, const int32_t *__restrict__ tiles, const int32_t *__restrict__ ntiles_dev,
     int ntiles_cap, In4 feat, const __bf16 *__restrict__ wp0, const __bf16 *__restrict__ wp1,
     const __bf16 *__restrict__ wp2, const float *__restrict__ params, float *__restrict__ rout,
-    float *__restrict__ phi_next, float dx, int32_t *__restrict__ fallbacks) {
+    float *__restrict__ corr, float dx, int32_t *__restrict__ fallbacks) {
     extern __shared__ __align__(16) unsigned char fsm[];
     __bf16 *in = reinterpret_cast<__bf16 *>(fsm);
     __bf16 *a0 = in + kFusedIn;
@@ -455,29 +456,55 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
                     const int64_t gpt =
                         (static_cast<int64_t>(z0 + lz) * g.ny + (y0 + ly)) * g.nx + (x0 + lx);
                     if (rout) rout[gpt] = rv[gi8];
-                    rv[gi8] *= cutoff_f(feat.phi[gpt], feat.inv_gamma);
+                    const float ph = feat.phi[gpt];
+                    rv[gi8] *= cutoff_f(ph, feat.inv_gamma);
                     if (!(fabsf(rv[gi8]) <= 0.5f)) atomicOr(&bad_s, 1);  // NaN fails too
+                    // limiter: the correction changes the plain increment by at
+                    // most half of it, so it never reverses or stalls the plain step
+                    const float lim = kCorrLimit * fabsf(feat.plain[gpt] - ph);
+                    rv[gi8] = fminf(fmaxf(dx * rv[gi8], -lim), lim);
                 }
             }
         }
         __syncthreads();
-        if (phi_next) {
-            if (bad_s == 0) {
-                if (kq == 0) {
+        if (corr) {
+            // the correction of the tile (zero when it falls back), added to
+            // the plain step by a later kernel: other blocks still read the
+            // plain step around their tiles
+            const bool ok = bad_s == 0;
+            if (kq == 0) {
 #pragma unroll
-                    for (int gi8 = 0; gi8 < NG3; ++gi8) {
-                        const int pt = (wave + kFusedWaves * gi8) * 16 + j;
-                        const int lx = pt & 7, ly = (pt >> 3) & 7, lz = pt >> 6;
-                        const int64_t gpt =
-                            (static_cast<int64_t>(z0 + lz) * g.ny + (y0 + ly)) * g.nx + (x0 + lx);
-                        phi_next[gpt] += dx * rv[gi8];
-                    }
+                for (int gi8 = 0; gi8 < NG3; ++gi8) {
+                    const int pt = (wave + kFusedWaves * gi8) * 16 + j;
+                    const int lx = pt & 7, ly = (pt >> 3) & 7, lz = pt >> 6;
+                    const int64_t gpt =
+                        (static_cast<int64_t>(z0 + lz) * g.ny + (y0 + ly)) * g.nx + (x0 + lx);
+                    corr[gpt] = ok ? rv[gi8] : 0.f;
                 }
-            } else if (threadIdx.x == 0 && fallbacks) {
-                atomicAdd(fallbacks, 1);
             }
+            if (!ok && threadIdx.x == 0 && fallbacks) atomicAdd(fallbacks, 1);
         }
         __syncthreads();  // LDS free for the next tile
+    }
+}
+
+// out += corr on every point of the listed tiles (8^3 tiles).
+__global__ __launch_bounds__(kBlock) void apply_corr_kernel(ConvGeo g,
+                                                            const int32_t *__restrict__ tiles,
+                                                            const int32_t *__restrict__ ntiles_dev,
+                                                            int cap, const float *__restrict__ corr,
+                                                            float *__restrict__ out) {
+    const int n = min(*ntiles_dev, cap);
+    for (int p = blockIdx.x; p < n; p += gridDim.x) {
+        const int t = tiles[p];
+        if (t < 0 || t >= g.ntx * g.nty * g.ntz) continue;
+        const int ti = t % g.ntx, rr = t / g.ntx;
+        const int x0 = ti * kT, y0 = (rr % g.nty) * kT, z0 = (rr / g.nty) * kT;
+        for (int q = threadIdx.x; q < kT * kT * kT; q += kBlock) {
+            const int lx = q & 7, ly = (q >> 3) & 7, lz = q >> 6;
+            const int64_t gi = (static_cast<int64_t>(z0 + lz) * g.ny + (y0 + ly)) * g.nx + x0 + lx;
+            out[gi] += corr[gi];
+        }
     }
 }
 
@@ -883,7 +910,8 @@ static int closure_network(const ClosureCall &c, const float *phi, const float *
 
 // The fused network on the active tiles: r (raw, into rout if non-NULL) and,
 // with `apply`, the corrected step apply += dx * c(phi) * r per tile (with the
-// fallback test).
+// fallback test), each point's correction limited to half of its plain
+// increment.
 static int closure_fused(const ClosureCall &c, const float *phi, const float *F, const float *plain,
                          float dx, float gamma, float fmax, const float *params, float *rout,
                          float *apply, int32_t *fallbacks) {
@@ -900,12 +928,21 @@ static int closure_fused(const ClosureCall &c, const float *phi, const float *F,
     const unsigned blocks =
         static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(c.G.ntiles, di.cus)));
     In4 feat{phi, F, plain, nullptr, 1.0f / gamma, 1.0f / fmax, 1.0f / dx};
+    // with `apply` the corrections go to the workspace's r field first
+    float *corr = apply ? at<float>(c, c.w.r) : nullptr;
     hipLaunchKernelGGL(closure_fused_kernel, dim3(blocks), dim3(kFusedBlock), kFusedLds, c.s,
                        conv_geo(c.G), at<const int32_t>(c, c.w.active),
                        at<const int32_t>(c, c.w.counters), static_cast<int>(c.G.ntiles), feat,
                        at<const __bf16>(c, c.w.wp0), at<const __bf16>(c, c.w.wp1),
-                       at<const __bf16>(c, c.w.wp2), params, rout, apply, dx, fallbacks);
+                       at<const __bf16>(c, c.w.wp2), params, rout, corr, dx, fallbacks);
     LS_LAUNCH_CHECK("closure_fused_kernel");
+    if (apply) {
+        hipLaunchKernelGGL(apply_corr_kernel, dim3(blocks * 4), dim3(kBlock), 0, c.s,
+                           conv_geo(c.G), at<const int32_t>(c, c.w.active),
+                           at<const int32_t>(c, c.w.counters), static_cast<int>(c.G.ntiles),
+                           static_cast<const float *>(corr), apply);
+        LS_LAUNCH_CHECK("apply_corr_kernel");
+    }
     return LS_OK;
 }
 

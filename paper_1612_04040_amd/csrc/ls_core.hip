@@ -33,6 +33,7 @@ int make_geom(const ls_grid *g, Geom *out) {
         return LS_ERR_ARG;
     }
     Geom r;
+    r.elem_bytes = 4;
     r.nx = g->nx, r.ny = g->ny, r.nz = g->nz;
     r.tx = g->tx, r.ty = g->ty, r.tz = g->tz;
     r.ntx = static_cast<int32_t>(cdiv64(g->nx, g->tx));

@@ -47,6 +47,7 @@ struct Geom {
     int32_t ntx, nty, ntz;
     int64_t ntiles;
     int64_t npoints;
+    int32_t elem_bytes;  // bytes of a stored phi value (sets the default run width); 4 if unset
 };
 
 // Validates g and fills out; returns LS_OK or a status with the message set.

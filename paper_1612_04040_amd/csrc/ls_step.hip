@@ -263,7 +263,13 @@ bool use_pipeline(int64_t phi_bytes) {
 
 static int run_width() { return g_tuning.run_width > 0 ? g_tuning.run_width : kDefaultRunWidth; }
 
-int plan_run_tiles(const Geom &g) { return std::max(1, std::min(kMaxRun, run_width() / g.tx)); }
+// Tiles per work item: the run width in points, by default 128 bytes of
+// stored phi (a full cache line per item row: 32 FP32, 64 FP16, 16 FP64 values).
+int plan_run_tiles(const Geom &g) {
+    const int eb = g.elem_bytes > 0 ? g.elem_bytes : 4;
+    const int width = g_tuning.run_width > 0 ? g_tuning.run_width : kDefaultRunWidth * 4 / eb;
+    return std::max(1, std::min(kMaxRun, width / g.tx));
+}
 
 template <class S>
 static int make_step_geom(const Geom &G, StepGeom *out, size_t *lds) {
@@ -397,6 +403,7 @@ static int step_args(S *phi, const FT *F, const ls_grid *grid, typename Codec<S>
     using C = typename Codec<S>::C;
     int rc = make_geom(grid, G);
     if (rc != LS_OK) return rc;
+    G->elem_bytes = static_cast<int32_t>(sizeof(S));
     if (!phi || !F || !scratch) {
         set_error("step: phi, F and scratch must be non-NULL");
         return LS_ERR_ARG;
@@ -526,6 +533,7 @@ static int launch_info(const ls_grid *grid, int32_t *blocks, int32_t *lds_bytes,
     Geom G;
     int rc = make_geom(grid, &G);
     if (rc != LS_OK) return rc;
+    G.elem_bytes = static_cast<int32_t>(sizeof(S));
     StepGeom sg;
     size_t lds = 0;
     if ((rc = make_step_geom<S>(G, &sg, &lds)) != LS_OK) return rc;

@@ -7,8 +7,8 @@
 * with the last layer zero the corrected run equals the plain band driver
   (value for value: the sign of a zero may differ);
 * a gated correction c(phi) r above 1/2 makes every active tile fall back to
-  the plain step, and an accepted constant r = 1/4 adds dx c(phi) / 4 on the
-  active tiles (c the cut-off of Eq. 8);
+  the plain step, and an accepted constant r = 1/4 adds dx c(phi) / 4, limited
+  to half the plain increment, on the active tiles (c the cut-off of Eq. 8);
 * three windows of the corrected driver (the fused network kernel) match the
   reference run step by step;
 * Adam and the restriction match the reference.
@@ -185,7 +185,8 @@ def test_fallback_and_constant_correction():
     cg.run(pd, Fd, wl.dx, wl.dt, wl.gamma, fmax, to_dev(C.flatten(p)), 1, 10)
     assert int(host(cg.fallbacks)[0]) == 0
     got = host(pd).astype(np.float64)
-    want = plain.astype(np.float64) + np.where(m, 0.25 * wl.dx * gate, 0.0)
+    lim = 0.5 * np.abs(plain.astype(np.float64) - wl.phi.astype(np.float64))
+    want = plain.astype(np.float64) + np.where(m, np.clip(0.25 * wl.dx * gate, -lim, lim), 0.0)
     assert np.array_equal(got[~m], plain[~m].astype(np.float64))
     # FP32 gate and update: a few ulp of the value and of the correction
     tol = 4 * EPS32 * (np.abs(want[m]) + 0.25 * wl.dx)

@@ -119,7 +119,14 @@ def test_fallback_on_large_correction():
     for t in active:
         m[(t // (nt * nt)) * 8:(t // (nt * nt)) * 8 + 8, ((t // nt) % nt) * 8:((t // nt) % nt) * 8 + 8,
           (t % nt) * 8:(t % nt) * 8 + 8] = True
-    assert np.allclose(diff[m], 0.25 * wl.dx * gate[m], rtol=0, atol=1e-15)
+    lim = 0.5 * np.abs(plain - phi)  # the limiter: at most half the plain increment
+    assert np.allclose(diff[m], np.clip(0.25 * wl.dx * gate[m], -lim[m], lim[m]), rtol=0,
+                       atol=1e-15)
+    # the corrected increment keeps the plain increment's sign and stays within 1/2..3/2 of it
+    inc, pinc = (out - phi)[m], (plain - phi)[m]
+    assert np.all(inc * pinc >= 0)
+    assert np.all(np.abs(inc) <= 1.5 * np.abs(pinc) + 1e-15)
+    assert np.all(np.abs(inc) >= 0.5 * np.abs(pinc) - 1e-15)
     assert np.all(diff[~m] == 0)
 
 
