@@ -253,8 +253,9 @@ int ls_graph_destroy(void *graph);
 typedef struct ls_tuning {
     int32_t run_width;
     int32_t blocks_per_cu;
-    int32_t pipeline; /* 0 auto (single grids: on when phi exceeds 1 GiB;
-                         batches: off), 1 off, 2 on */
+    int32_t pipeline; /* 0 auto (single grids: on when phi exceeds 1 GiB and a
+                         work item spans at most 4 tiles; batches: off),
+                         1 off, 2 on */
 } ls_tuning;
 int ls_set_tuning(const ls_tuning *t);
 int ls_get_tuning(ls_tuning *t);

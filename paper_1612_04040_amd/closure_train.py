@@ -220,9 +220,9 @@ def main(argv=None):
     ap.add_argument("--val-seeds", default="200-203")
     ap.add_argument("--eval-seed", type=int, default=5)
     ap.add_argument("--iters", type=int, default=8000)
-    ap.add_argument("--rollout-max", type=int, default=8)
-    ap.add_argument("--rollout-prob", type=float, default=0.5)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--rollout-max", type=int, default=2)
+    ap.add_argument("--rollout-prob", type=float, default=0.3)
+    ap.add_argument("--lr", type=float, default=3e-4)
     ap.add_argument("--init-seed", type=int, default=0)
     ap.add_argument("--params-out", default=None, help="save the trained parameters (.npy)")
     ap.add_argument("--out", default=None, help="write the JSON report here")

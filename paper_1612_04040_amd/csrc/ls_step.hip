@@ -255,10 +255,12 @@ constexpr int64_t kPipelineBytes = int64_t(1) << 30;
 
 bool pipeline_forced() { return g_tuning.pipeline == 2; }
 
-bool use_pipeline(int64_t phi_bytes) {
+bool use_pipeline(int64_t phi_bytes, int run_tiles) {
     if (g_tuning.pipeline == 1) return false;
     if (g_tuning.pipeline == 2) return true;
-    return phi_bytes > kPipelineBytes;
+    // measured: with runs of more than 4 tiles the kernel's own loads hide the
+    // latency and the second set of registers costs more than it gains
+    return phi_bytes > kPipelineBytes && run_tiles <= 4;
 }
 
 static int run_width() { return g_tuning.run_width > 0 ? g_tuning.run_width : kDefaultRunWidth; }
@@ -344,7 +346,7 @@ template <class S, class FT, bool EXACT>
 static UpwindFn<S, FT, EXACT> select_upwind_kernel(const StepGeom &sg, int nown, int nhalo,
                                                    size_t *lds) {
     const bool whole_yz = sg.ny % sg.ty == 0 && sg.nz % sg.tz == 0;
-    const bool pipe = use_pipeline(int64_t(sg.nx) * sg.ny * sg.nz * int64_t(sizeof(S)));
+    const bool pipe = use_pipeline(int64_t(sg.nx) * sg.ny * sg.nz * int64_t(sizeof(S)), sg.R);
 #define LS_FAST(TX_, TY_, TZ_, R_)                                                          \
     if (sg.tx == TX_ && sg.ty == TY_ && sg.tz == TZ_ && sg.R == R_) {                       \
         *lds = FastCfg<S, FT, TX_, TY_, TZ_, R_>::lds;                                      \
