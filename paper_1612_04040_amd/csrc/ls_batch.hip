@@ -433,10 +433,11 @@ using BatchFn = void (*)(StepGeom, StepArgs<float, float>);
 
 bool pipeline_forced();  // ls_step.hip
 
-static BatchFn batch_kernel(const Shape4 &s, bool pipe, size_t *lds) {
+static BatchFn batch_kernel(const Shape4 &s, bool pipe, size_t *lds, int *threads) {
 #define LS_BFAST(TX_, TY_, TZ_, R_)                                                          \
     if (s.tx == TX_ && s.ty == TY_ && s.tz == TZ_ && s.R == R_) {                            \
         *lds = FastCfg<float, float, TX_, TY_, TZ_, R_>::lds;                                \
+        *threads = FastCfg<float, float, TX_, TY_, TZ_, R_>::NT;                             \
         return pipe ? upwind_fast_kernel<float, float, false, TX_, TY_, TZ_, R_, true, true, true> \
                     : upwind_fast_kernel<float, float, false, TX_, TY_, TZ_, R_, true, true, false>; \
     }
@@ -549,11 +550,12 @@ static int batch_steps(const BatchLayout &L, float *phi, const float *F, float *
         args.nxt = (s & 1) ? phi : scratch;
         for (size_t gi = 0; gi < L.groups.size(); ++gi) {
             size_t lds = 0;
-            BatchFn k = batch_kernel(L.groups[gi].shape, pipe, &lds);
+            int threads = kBlock;
+            BatchFn k = batch_kernel(L.groups[gi].shape, pipe, &lds, &threads);
             args.range = ranges + gi;
             int64_t slot;
             if ((rc = stats_before(LS_KERNEL_UPWIND, stream, &slot)) != LS_OK) return rc;
-            hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(G)), dim3(kBlock), lds, stream, sg,
+            hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(G)), dim3(threads), lds, stream, sg,
                                args);
             LS_LAUNCH_CHECK("upwind_fast_kernel (batch)");
             if ((rc = stats_after(LS_KERNEL_UPWIND, stream, slot)) != LS_OK) return rc;

@@ -113,7 +113,10 @@ constexpr int clog2(int v) { return v <= 1 ? 0 : 1 + clog2(v / 2); }
 template <class S, class FT, int TX, int TY, int TZ, int R>
 struct FastCfg {
     static constexpr int XL = cpow2(R * TX);
-    static constexpr int RP = kBlock / XL;      // grid rows per pass
+    // threads per workgroup: 512 for item rows of 64 points and more, so that
+    // every thread keeps the same number of own points as with 32-point rows
+    static constexpr int NT = XL >= 64 ? 2 * kBlock : kBlock;
+    static constexpr int RP = NT / XL;          // grid rows per pass
     static constexpr int ROWS = TY * TZ;
     static constexpr int NOWN = ROWS / RP;      // own points per thread
     static constexpr int NHR = 2 * (TY + TZ);   // halo rows of the y and z faces
@@ -121,9 +124,9 @@ struct FastCfg {
     static constexpr int SX = R * TX + 2, SXY = SX * (TY + 2);
     using C = typename Codec<S>::C;
     static constexpr size_t lds = sizeof(C) * SXY * (TZ + 2);
-    static_assert(XL <= kBlock && ROWS % RP == 0, "shape does not tile the block");
+    static_assert(XL <= NT && ROWS % RP == 0, "shape does not tile the block");
     static_assert(RP % TY == 0 || TY % RP == 0, "rows per pass must divide or be divided by TY");
-    static_assert(ROWS <= kBlock, "x-face points exceed two per thread");
+    static_assert(ROWS <= NT, "x-face points exceed two per thread");
 };
 
 // Fast band-step kernel for a compile-time tile shape (TX, TY, TZ) and R tiles
@@ -147,7 +150,8 @@ struct FastCfg {
 // grid is the clamped point inside the item (zero-gradient boundary).
 template <class S, class FT, bool EXACT, int TX, int TY, int TZ, int R, bool BATCH, bool PARTIAL,
           bool PIPE>
-__global__ __launch_bounds__(kBlock) void upwind_fast_kernel(StepGeom g, StepArgs<S, FT> a) {
+__global__ __launch_bounds__((FastCfg<S, FT, TX, TY, TZ, R>::NT)) void upwind_fast_kernel(
+    StepGeom g, StepArgs<S, FT> a) {
     using K = FastCfg<S, FT, TX, TY, TZ, R>;
     using C = typename K::C;
     constexpr int XL = K::XL, RP = K::RP, ROWS = K::ROWS, NOWN = K::NOWN, NHALO = K::NHALO;

@@ -344,12 +344,14 @@ static UpwindFn<S, FT, EXACT> select_halo(int nhalo) {
 // shapes and run lengths, else the run-time-shape kernel.
 template <class S, class FT, bool EXACT>
 static UpwindFn<S, FT, EXACT> select_upwind_kernel(const StepGeom &sg, int nown, int nhalo,
-                                                   size_t *lds) {
+                                                   size_t *lds, int *threads) {
+    *threads = kBlock;
     const bool whole_yz = sg.ny % sg.ty == 0 && sg.nz % sg.tz == 0;
     const bool pipe = use_pipeline(int64_t(sg.nx) * sg.ny * sg.nz * int64_t(sizeof(S)), sg.R);
 #define LS_FAST(TX_, TY_, TZ_, R_)                                                          \
     if (sg.tx == TX_ && sg.ty == TY_ && sg.tz == TZ_ && sg.R == R_) {                       \
         *lds = FastCfg<S, FT, TX_, TY_, TZ_, R_>::lds;                                      \
+        *threads = FastCfg<S, FT, TX_, TY_, TZ_, R_>::NT;                                   \
         if (whole_yz)                                                                       \
             return pipe ? upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, false, true>  \
                         : upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, false, false>; \
@@ -378,13 +380,13 @@ static UpwindFn<S, FT, EXACT> select_upwind_kernel(const StepGeom &sg, int nown,
 }
 
 template <class K>
-static int persistent_grid(K kernel, size_t lds, int *grid, int *limit = nullptr,
+static int persistent_grid(K kernel, int threads, size_t lds, int *grid, int *limit = nullptr,
                            int64_t max_items = INT32_MAX) {
     DeviceInfo di;
     int rc = device_info(&di);
     if (rc != LS_OK) return rc;
     int per_cu = 0;
-    LS_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, lds));
+    LS_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds));
     if (per_cu < 1) per_cu = 1;
     if (limit) *limit = per_cu;
     // Default: about one block per work item, beyond what fits at once, so the
@@ -449,10 +451,12 @@ static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const 
     const int nown = pow2_at_least((G.ty * G.tz + rp - 1) / rp);
     const int nhalo = pow2_at_least((2 * (G.ty + G.tz) + rp - 1) / rp);
     size_t lds = static_cast<size_t>(sg.sx) * sg.sy * (G.tz + 2) * sizeof(C);
-    auto kernel = select_upwind_kernel<S, FT, EXACT>(sg, nown, nhalo, &lds);
+    int threads = kBlock;
+    auto kernel = select_upwind_kernel<S, FT, EXACT>(sg, nown, nhalo, &lds, &threads);
     int nblocks = 0;
     int rc;
-    if ((rc = persistent_grid(kernel, lds, &nblocks, nullptr, G.ntiles)) != LS_OK) return rc;
+    if ((rc = persistent_grid(kernel, threads, lds, &nblocks, nullptr, G.ntiles)) != LS_OK)
+        return rc;
 
     StepArgs<S, FT> args;
     args.F = F;
@@ -470,7 +474,7 @@ static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const 
         args.nxt = (s & 1) ? phi : scratch;
         int64_t slot;
         if ((rc = stats_before(LS_KERNEL_UPWIND, stream, &slot)) != LS_OK) return rc;
-        hipLaunchKernelGGL(kernel, dim3(nblocks), dim3(kBlock), lds, stream, sg, args);
+        hipLaunchKernelGGL(kernel, dim3(nblocks), dim3(threads), lds, stream, sg, args);
         LS_LAUNCH_CHECK("upwind_kernel");
         if ((rc = stats_after(LS_KERNEL_UPWIND, stream, slot)) != LS_OK) return rc;
     }
@@ -542,9 +546,10 @@ static int launch_info(const ls_grid *grid, int32_t *blocks, int32_t *lds_bytes,
     const int rp = kBlock / sg.xl;
     const int nown = pow2_at_least((G.ty * G.tz + rp - 1) / rp);
     const int nhalo = pow2_at_least((2 * (G.ty + G.tz) + rp - 1) / rp);
-    auto kernel = select_upwind_kernel<S, FT, EXACT>(sg, nown, nhalo, &lds);
+    int threads = kBlock;
+    auto kernel = select_upwind_kernel<S, FT, EXACT>(sg, nown, nhalo, &lds, &threads);
     int nb = 0, lim = 0;
-    if ((rc = persistent_grid(kernel, lds, &nb, &lim, G.ntiles)) != LS_OK) return rc;
+    if ((rc = persistent_grid(kernel, threads, lds, &nb, &lim, G.ntiles)) != LS_OK) return rc;
     if (blocks) *blocks = nb;
     if (lds_bytes) *lds_bytes = static_cast<int32_t>(lds);
     if (run_tiles) *run_tiles = sg.R;

@@ -31,7 +31,6 @@ def test_oracle_reproduces_golden():
 def test_gpu_f64_reproduces_golden():
     import torch
 
-    import oracle
     from paper_1612_04040_amd.band import BandGrid
 
     with open(GOLDEN) as fh:
@@ -56,4 +55,3 @@ def test_gpu_f64_reproduces_golden():
     assert b32.band_list().tolist() == want["band_u"]
     b32.build(f32, gamma, dilate=False)
     assert b32.band_list().tolist() == want["band_a"]
-    del oracle
