@@ -104,64 +104,10 @@ struct ItemRecordFn {
     }
 };
 
-// Emits the whole record of a work item at its compacted position (the map
-// is complete when the scatter pass runs).
-struct EmitRecord {
-    ItemRecordFn f;
-    __device__ void operator()(int pos, int64_t t) const {
-        f.rec[static_cast<int64_t>(pos) * kItemWords + 7] = static_cast<int32_t>(t);
-        f(pos);
-    }
-};
-
-// The update map of a tile from the flags A: A itself, or A grown by one tile
-// in all 26 directions (clipped to the grid).
-__device__ inline bool dilated(const uint8_t *a, int64_t t, int ntx, int nty, int ntz,
-                               int dilate) {
-    if (!dilate) return a[t] != 0;
-    const int ti = static_cast<int>(t % ntx);
-    const int64_t r = t / ntx;
-    const int tj = static_cast<int>(r % nty), tk = static_cast<int>(r / nty);
-    uint8_t hit = 0;
-    for (int dk = -1; dk <= 1; ++dk) {
-        const int k = tk + dk;
-        if (k < 0 || k >= ntz) continue;
-        for (int dj = -1; dj <= 1; ++dj) {
-            const int j = tj + dj;
-            if (j < 0 || j >= nty) continue;
-            const uint8_t *row = a + (static_cast<int64_t>(k) * nty + j) * ntx;
-            hit |= row[ti];
-            if (ti > 0) hit |= row[ti - 1];
-            if (ti + 1 < ntx) hit |= row[ti + 1];
-        }
-    }
-    return hit != 0;
+__global__ __launch_bounds__(kBlock) void item_record_kernel(ItemRecordFn f, const int32_t *nitems) {
+    const int n = *nitems;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) f(i);
 }
-
-// Counting-pass predicates of the band build: the band (computing and
-// writing the update map on the way) and the heads of its work items
-// (recomputing the map of the x-predecessor, which another block may be
-// writing at the same time).
-struct DilateWritePred {
-    const uint8_t *a;
-    uint8_t *u;
-    int ntx, nty, ntz, dilate;
-    __device__ bool operator()(int64_t t) const {
-        const bool in = dilated(a, t, ntx, nty, ntz, dilate);
-        u[t] = in ? 1 : 0;
-        return in;
-    }
-};
-struct DilateHeadPred {
-    const uint8_t *a;
-    int ntx, nty, ntz, dilate, R;
-    __device__ bool operator()(int64_t t) const {
-        if (!dilated(a, t, ntx, nty, ntz, dilate)) return false;
-        const int ti = static_cast<int>(t % ntx);
-        return ti % R == 0 || !dilated(a, t - 1, ntx, nty, ntz, dilate);
-    }
-};
-
 
 int build_plan(const Geom &g, uint8_t *ws, int32_t *list, int32_t *list_count,
                hipStream_t stream) {
@@ -173,31 +119,19 @@ int build_plan(const Geom &g, uint8_t *ws, int32_t *list, int32_t *list_count,
     int32_t *nitems = reinterpret_cast<int32_t *>(ws + w.counters);
     const int R = plan_run_tiles(g);
     const HeadMapPred heads{umap, g.ntx, R};
-    const EmitRecord records{ItemRecordFn{rec, umap, g.ntx, g.nty, g.ntz, R}};
+    int rc;
     if (list)
-        return compact2(MapPred{umap}, EmitIndex{list}, list_count, blk, heads, records, nitems,
-                        blk2, nullptr, g.ntiles, stream);
-    return compact(heads, records, nullptr, g.ntiles, nitems, blk, stream);
-}
-
-// The band of the flags A (dilated or not), its list and its step plan in
-// three launches: the counting pass computes and writes the update map, the
-// scatter pass writes the list and the work-item records.
-static int build_plan_from_flags(const Geom &g, uint8_t *ws, int dilate, int32_t *list,
-                                 int32_t *list_count, hipStream_t stream) {
-    const Workspace w = workspace_layout(g);
-    const uint8_t *a = ws + w.a_flags;
-    uint8_t *umap = ws + w.u_map;
-    int32_t *blk = reinterpret_cast<int32_t *>(ws + w.blk_counts);
-    int32_t *blk2 = reinterpret_cast<int32_t *>(ws + w.blk_counts2);
-    int32_t *rec = reinterpret_cast<int32_t *>(ws + w.items);
-    int32_t *nitems = reinterpret_cast<int32_t *>(ws + w.counters);
-    const int R = plan_run_tiles(g);
-    const DilateWritePred count_band{a, umap, g.ntx, g.nty, g.ntz, dilate};
-    const DilateHeadPred count_heads{a, g.ntx, g.nty, g.ntz, dilate, R};
-    const EmitRecord records{ItemRecordFn{rec, umap, g.ntx, g.nty, g.ntz, R}};
-    return compact2_split(count_band, count_heads, MapPred{umap}, EmitIndex{list}, list_count, blk,
-                          HeadMapPred{umap, g.ntx, R}, records, nitems, blk2, g.ntiles, stream);
+        rc = compact2(MapPred{umap}, EmitIndex{list}, list_count, blk, heads, EmitHeadTile{rec},
+                      nitems, blk2, nullptr, g.ntiles, stream);
+    else
+        rc = compact(heads, EmitHeadTile{rec}, nullptr, g.ntiles, nitems, blk, stream);
+    if (rc != LS_OK) return rc;
+    const unsigned rb = static_cast<unsigned>(std::min<int64_t>(cdiv64(g.ntiles, kBlock), 2048));
+    hipLaunchKernelGGL(item_record_kernel, dim3(rb), dim3(kBlock), 0, stream,
+                       ItemRecordFn{rec, umap, g.ntx, g.nty, g.ntz, R},
+                       static_cast<const int32_t *>(nitems));
+    LS_LAUNCH_CHECK("item_record_kernel");
+    return LS_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -279,6 +213,36 @@ __global__ __launch_bounds__(kBlock) void band_flag_kernel(const S *__restrict__
     __syncthreads();
     uint8_t *dst = a_flags + (static_cast<int64_t>(tk) * nty + tj) * ntx;
     for (int t = threadIdx.x; t < ntx; t += kBlock) dst[t] = sflag[t];
+}
+
+// U = A grown by one tile in all 26 directions (clipped to the tile grid),
+// or U = A when dilate is 0.
+__global__ __launch_bounds__(kBlock) void band_dilate_kernel(const uint8_t *__restrict__ a,
+                                                             uint8_t *__restrict__ u, int ntx,
+                                                             int nty, int ntz, int dilate) {
+    const int ti = blockIdx.x * 64 + threadIdx.x;
+    const int tj = blockIdx.y * 4 + threadIdx.y;
+    const int tk = blockIdx.z;
+    if (ti >= ntx || tj >= nty) return;
+    const int64_t t = (static_cast<int64_t>(tk) * nty + tj) * ntx + ti;
+    if (!dilate) {
+        u[t] = a[t];
+        return;
+    }
+    uint8_t hit = 0;
+    for (int dk = -1; dk <= 1; ++dk) {
+        const int k = tk + dk;
+        if (k < 0 || k >= ntz) continue;
+        for (int dj = -1; dj <= 1; ++dj) {
+            const int j = tj + dj;
+            if (j < 0 || j >= nty) continue;
+            const uint8_t *row = a + (static_cast<int64_t>(k) * nty + j) * ntx;
+            hit |= row[ti];
+            if (ti > 0) hit |= row[ti - 1];
+            if (ti + 1 < ntx) hit |= row[ti + 1];
+        }
+    }
+    u[t] = hit ? 1 : 0;
 }
 
 // Tile flags of the listed tiles only (the incremental rebuild): one wave per
@@ -374,7 +338,14 @@ static int band_args(const S *phi, const ls_grid *grid, typename Codec<S>::C gam
 // list and the step plan of that list.
 static int band_finish(const Geom &g, uint8_t *ws, int dilate, int32_t *tiles,
                        int32_t *ntiles_dev, hipStream_t stream) {
-    return build_plan_from_flags(g, ws, dilate, tiles, ntiles_dev, stream);
+    const Workspace w = workspace_layout(g);
+    const dim3 dgrid(static_cast<unsigned>(cdiv64(g.ntx, 64)), static_cast<unsigned>(cdiv64(g.nty, 4)),
+                     g.ntz);
+    hipLaunchKernelGGL(band_dilate_kernel, dgrid, dim3(64, 4), 0, stream,
+                       static_cast<const uint8_t *>(ws + w.a_flags), ws + w.u_map, g.ntx, g.nty,
+                       g.ntz, dilate);
+    LS_LAUNCH_CHECK("band_dilate_kernel");
+    return build_plan(g, ws, tiles, ntiles_dev, stream);
 }
 
 template <class S>

@@ -545,6 +545,10 @@ static int batch_steps(const BatchLayout &L, float *phi, const float *F, float *
     // software pipelining is on only when asked for: measured slower on the
     // 256-grid batch (its predicated kernels need the registers)
     const bool pipe = pipeline_forced();
+    int64_t slot;
+    if ((rc = stats_before(LS_KERNEL_UPWIND, stream, &slot,
+                           int64_t(nsteps) * int64_t(L.groups.size()))) != LS_OK)
+        return rc;
     for (int s = 0; s < nsteps; ++s) {
         args.cur = (s & 1) ? scratch : phi;
         args.nxt = (s & 1) ? phi : scratch;
@@ -553,14 +557,12 @@ static int batch_steps(const BatchLayout &L, float *phi, const float *F, float *
             int threads = kBlock;
             BatchFn k = batch_kernel(L.groups[gi].shape, pipe, &lds, &threads);
             args.range = ranges + gi;
-            int64_t slot;
-            if ((rc = stats_before(LS_KERNEL_UPWIND, stream, &slot)) != LS_OK) return rc;
             hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(G)), dim3(threads), lds, stream, sg,
                                args);
             LS_LAUNCH_CHECK("upwind_fast_kernel (batch)");
-            if ((rc = stats_after(LS_KERNEL_UPWIND, stream, slot)) != LS_OK) return rc;
         }
     }
+    if ((rc = stats_after(LS_KERNEL_UPWIND, stream, slot)) != LS_OK) return rc;
     if (nsteps & 1) {
         hipLaunchKernelGGL(batch_copy_kernel, dim3(static_cast<unsigned>(di.cus * 8)),
                            dim3(kBlock), 0, stream, static_cast<const float *>(scratch), phi, rec,

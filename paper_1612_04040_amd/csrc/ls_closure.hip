@@ -286,7 +286,8 @@ constexpr int kF0 = kT + 6, kF1 = kT + 4, kF2 = kT + 2;  // 14, 12, 10
 constexpr size_t kFusedIn = size_t(kF0) * kF0 * kF0 * 4;  // bf16 elements
 constexpr size_t kFusedA0 = size_t(kF1) * kF1 * kF1 * 16;
 constexpr size_t kFusedA1 = size_t(kF2) * kF2 * kF2 * 16;
-constexpr size_t kFusedLds = 2 * (kFusedIn + kFusedA0 + kFusedA1);
+constexpr size_t kFusedW = size_t(4 + 14 + 14) * 64 * 8;  // packed weights of the 3 layers
+constexpr size_t kFusedLds = 2 * (kFusedIn + kFusedA0 + kFusedA1 + kFusedW);
 // activations are stored as two planes of 8 channels (channels 0-7, then
 // 8-15), 16 bytes per point: the 16 points of an MFMA column block read 256
 // contiguous bytes, free of LDS bank conflicts
@@ -303,30 +304,60 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
     __bf16 *in = reinterpret_cast<__bf16 *>(fsm);
     __bf16 *a0 = in + kFusedIn;
     __bf16 *a1 = a0 + kFusedA0;
+    __bf16 *wts = a1 + kFusedA1;  // chunks 0-3 layer 1, 4-17 layer 2, 18-31 layer 3
     __shared__ int bad_s;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int j = lane & 15, kq = lane >> 4;
     const int n = min(*ntiles_dev, ntiles_cap);
+
+    // the packed weights of all layers, once per block
+    for (int i = threadIdx.x; i < static_cast<int>(kFusedW / 8); i += kFusedBlock) {
+        const int c = i / 64, l = i % 64;
+        const __bf16 *src = c < 4 ? wp0 + (c * 64 + l) * 8
+                                  : (c < 18 ? wp1 + ((c - 4) * 64 + l) * 8
+                                            : wp2 + ((c - 18) * 64 + l) * 8);
+        *reinterpret_cast<uint4 *>(wts + i * 8) = *reinterpret_cast<const uint4 *>(src);
+    }
 
     for (int p = blockIdx.x; p < n; p += gridDim.x) {
         const int t = tiles[p];
         if (t < 0 || t >= g.ntx * g.nty * g.ntz) continue;  // uniform
         const int ti = t % g.ntx, rr = t / g.ntx;
         const int x0 = ti * kT, y0 = (rr % g.nty) * kT, z0 = (rr / g.nty) * kT;
-        // features of the 14^3 points (zero outside the grid)
-        for (int q = threadIdx.x; q < kF0 * kF0 * kF0; q += kFusedBlock) {
+        // features of the 14^3 points (zero outside the grid): every load of
+        // the thread issued first, then the conversions and LDS stores
+        constexpr int NP0 = kF0 * kF0 * kF0;
+        constexpr int NQ = (NP0 + kFusedBlock - 1) / kFusedBlock;
+        float vph[NQ], vf[NQ], vpl[NQ];
+        bool vok[NQ];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            const int q = threadIdx.x + k * kFusedBlock;
             const int px = q % kF0, py = (q / kF0) % kF0, pz = q / (kF0 * kF0);
             const int gx = x0 + px - 3, gy = y0 + py - 3, gz = z0 + pz - 3;
-            float v0 = 0.f, v1 = 0.f, v2 = 0.f;
-            if (gx >= 0 && gy >= 0 && gz >= 0 && gx < g.nx && gy < g.ny && gz < g.nz) {
+            vok[k] = q < NP0 && gx >= 0 && gy >= 0 && gz >= 0 && gx < g.nx && gy < g.ny &&
+                     gz < g.nz;
+            vph[k] = vf[k] = vpl[k] = 0.f;
+            if (vok[k]) {
                 const int64_t gi = (static_cast<int64_t>(gz) * g.ny + gy) * g.nx + gx;
-                const float ph = feat.phi[gi];
-                v0 = fminf(fmaxf(ph * feat.inv_gamma, -2.f), 2.f);
-                v1 = feat.F[gi] * feat.inv_fmax;
-                v2 = (feat.plain[gi] - ph) * feat.inv_dx;
+                vph[k] = feat.phi[gi];
+                vf[k] = feat.F[gi];
+                vpl[k] = feat.plain[gi];
             }
-            __bf16 d[4] = {to_bf16(v0), to_bf16(v1), to_bf16(v2), to_bf16(0.f)};
-            *reinterpret_cast<uint2 *>(in + q * 4) = *reinterpret_cast<const uint2 *>(d);
+        }
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            const int q = threadIdx.x + k * kFusedBlock;
+            if (q < NP0) {
+                float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+                if (vok[k]) {
+                    v0 = fminf(fmaxf(vph[k] * feat.inv_gamma, -2.f), 2.f);
+                    v1 = vf[k] * feat.inv_fmax;
+                    v2 = (vpl[k] - vph[k]) * feat.inv_dx;
+                }
+                __bf16 d[4] = {to_bf16(v0), to_bf16(v1), to_bf16(v2), to_bf16(0.f)};
+                *reinterpret_cast<uint2 *>(in + q * 4) = *reinterpret_cast<const uint2 *>(d);
+            }
         }
         if (threadIdx.x == 0) bad_s = 0;
         __syncthreads();
@@ -338,7 +369,7 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
             int off[4][2];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                wa[c] = *reinterpret_cast<const bf16x8 *>(wp0 + (c * 64 + lane) * 8);
+                wa[c] = *reinterpret_cast<const bf16x8 *>(wts + (c * 64 + lane) * 8);
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int tap = 8 * c + 2 * kq + h;
@@ -387,7 +418,7 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
             int off[14];
 #pragma unroll
             for (int c = 0; c < 14; ++c) {
-                wa[c] = *reinterpret_cast<const bf16x8 *>(wp1 + (c * 64 + lane) * 8);
+                wa[c] = *reinterpret_cast<const bf16x8 *>(wts + ((4 + c) * 64 + lane) * 8);
                 const int tap = 2 * c + (kq >> 1);
                 off[c] = tap < kTaps
                              ? (((tap / 9) * kF1 + (tap / 3) % 3) * kF1 + tap % 3) * 8 +
@@ -431,7 +462,7 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
             int off[14];
 #pragma unroll
             for (int c = 0; c < 14; ++c) {
-                wa[c] = *reinterpret_cast<const bf16x8 *>(wp2 + (c * 64 + lane) * 8);
+                wa[c] = *reinterpret_cast<const bf16x8 *>(wts + ((18 + c) * 64 + lane) * 8);
                 const int tap = 2 * c + (kq >> 1);
                 off[c] = tap < kTaps
                              ? (((tap / 9) * kF2 + (tap / 3) % 3) * kF2 + tap % 3) * 8 +
@@ -439,6 +470,19 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
                              : -1;
             }
             const float b2 = params[kB2];
+            // phi and the plain step on the lane's points, for the gate and the limiter
+            float gph[NG3], gpl[NG3];
+#pragma unroll
+            for (int gi8 = 0; gi8 < NG3; ++gi8) {
+                const int pt = (wave + kFusedWaves * gi8) * 16 + j;
+                const int64_t gpt = (static_cast<int64_t>(z0 + (pt >> 6)) * g.ny +
+                                     (y0 + ((pt >> 3) & 7))) * g.nx + (x0 + (pt & 7));
+                gph[gi8] = gpl[gi8] = 0.f;
+                if (kq == 0) {
+                    gph[gi8] = feat.phi[gpt];
+                    gpl[gi8] = feat.plain[gpt];
+                }
+            }
 #pragma unroll
             for (int gi8 = 0; gi8 < NG3; ++gi8) {
                 const int pt = (wave + kFusedWaves * gi8) * 16 + j;
@@ -456,12 +500,12 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
                     const int64_t gpt =
                         (static_cast<int64_t>(z0 + lz) * g.ny + (y0 + ly)) * g.nx + (x0 + lx);
                     if (rout) rout[gpt] = rv[gi8];
-                    const float ph = feat.phi[gpt];
+                    const float ph = gph[gi8];
                     rv[gi8] *= cutoff_f(ph, feat.inv_gamma);
                     if (!(fabsf(rv[gi8]) <= 0.5f)) atomicOr(&bad_s, 1);  // NaN fails too
                     // limiter: the correction changes the plain increment by at
                     // most half of it, so it never reverses or stalls the plain step
-                    const float lim = kCorrLimit * fabsf(feat.plain[gpt] - ph);
+                    const float lim = kCorrLimit * fabsf(gpl[gi8] - ph);
                     rv[gi8] = fminf(fmaxf(dx * rv[gi8], -lim), lim);
                 }
             }

@@ -114,32 +114,6 @@ struct EmitIndex {
     __device__ void operator()(int pos, int64_t idx) const { out[pos] = static_cast<int32_t>(idx); }
 };
 
-// As compact2, with separate predicates for the counting pass (ca, cb) and
-// the scatter pass (pa, pb): they must select the same indices; the counting
-// predicates may compute what the scatter predicates read (e.g. write a map
-// that the scatter pass tests).
-template <class CA, class CB, class PA, class EA, class PB, class EB>
-int compact2_split(CA ca, CB cb, PA pa, EA ea, int32_t *count_a, int32_t *blk_a, PB pb, EB eb,
-                   int32_t *count_b, int32_t *blk_b, int64_t n_cap, hipStream_t stream) {
-    const int64_t nblk = cdiv64(n_cap, kCompactChunk);
-    if (nblk > 0) {
-        hipLaunchKernelGGL((compact_count_kernel<CA, CB>), dim3(static_cast<unsigned>(nblk)),
-                           dim3(kBlock), 0, stream, ca, cb, nullptr, n_cap, blk_a, blk_b);
-        LS_LAUNCH_CHECK("compact_count_kernel");
-    }
-    hipLaunchKernelGGL(compact_scan_kernel, dim3(blk_b ? 2 : 1), dim3(1024), 0, stream, blk_a,
-                       count_a, blk_b, count_b, nblk);
-    LS_LAUNCH_CHECK("compact_scan_kernel");
-    if (nblk > 0) {
-        hipLaunchKernelGGL((compact_scatter_kernel<PA, EA, PB, EB>),
-                           dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, stream, pa, ea, pb,
-                           eb, nullptr, n_cap, static_cast<const int32_t *>(blk_a),
-                           static_cast<const int32_t *>(blk_b));
-        LS_LAUNCH_CHECK("compact_scatter_kernel");
-    }
-    return LS_OK;
-}
-
 // Compacts pa (into ea, count_a) and, unless blk_b is null, pb (into eb,
 // count_b) over [0, n): n = *n_dev (clamped to n_cap) or n_cap.
 template <class PA, class EA, class PB = NullPred, class EB = NullEmit>

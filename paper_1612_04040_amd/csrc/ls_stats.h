@@ -6,9 +6,9 @@
 namespace ls {
 
 bool stats_on();
-// Records the start event of a timed launch of `kind` on `stream`; *slot < 0
-// when the launch is not timed.
-int stats_before(int kind, hipStream_t stream, int64_t *slot);
+// Records the start event of `count` back-to-back timed launches of `kind` on
+// `stream`; *slot < 0 when they are not timed.
+int stats_before(int kind, hipStream_t stream, int64_t *slot, int64_t count = 1);
 int stats_after(int kind, hipStream_t stream, int64_t slot);
 
 }  // namespace ls

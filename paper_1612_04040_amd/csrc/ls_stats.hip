@@ -13,6 +13,7 @@ constexpr int64_t kMaxPairs = 65536;
 
 struct Record {
     std::vector<hipEvent_t> start, stop;
+    std::vector<int64_t> count;  // launches between the events of a pair
     int64_t launches = 0;
     int64_t used = 0;
 };
@@ -24,12 +25,12 @@ Record g_rec[kKinds];
 
 bool stats_on() { return g_on; }
 
-int stats_before(int kind, hipStream_t stream, int64_t *slot) {
+int stats_before(int kind, hipStream_t stream, int64_t *slot, int64_t count) {
     *slot = -1;
     if (!g_on) return LS_OK;
     std::lock_guard<std::mutex> lock(g_mu);
     Record &r = g_rec[kind];
-    ++r.launches;
+    r.launches += count;
     if (r.used >= kMaxPairs) return LS_OK;
     if (r.used == static_cast<int64_t>(r.start.size())) {
         hipEvent_t a, b;
@@ -37,7 +38,9 @@ int stats_before(int kind, hipStream_t stream, int64_t *slot) {
         LS_HIP_CHECK(hipEventCreate(&b));
         r.start.push_back(a);
         r.stop.push_back(b);
+        r.count.push_back(0);
     }
+    r.count[r.used] = count;
     *slot = r.used++;
     LS_HIP_CHECK(hipEventRecord(r.start[*slot], stream));
     return LS_OK;
@@ -144,14 +147,16 @@ int ls_stats_read(int which, int64_t *launches, int64_t *timed, double *total_ms
     std::lock_guard<std::mutex> lock(ls::g_mu);
     const ls::Record &r = ls::g_rec[which];
     double sum = 0.0;
+    int64_t covered = 0;
     for (int64_t i = 0; i < r.used; ++i) {
         LS_HIP_CHECK(hipEventSynchronize(r.stop[i]));
         float ms = 0.f;
         LS_HIP_CHECK(hipEventElapsedTime(&ms, r.start[i], r.stop[i]));
         sum += ms;
+        covered += r.count[i];
     }
     *launches = r.launches;
-    *timed = r.used;
+    *timed = covered;
     *total_ms = sum;
     return LS_OK;
 }

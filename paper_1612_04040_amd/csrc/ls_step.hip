@@ -469,15 +469,16 @@ static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const 
     args.dt = dt;
     args.dtdx = static_cast<C>(static_cast<double>(dt) / static_cast<double>(dx));
     args.scale = scale;
+    // one pair of timing events around the nsteps back-to-back launches
+    int64_t slot;
+    if ((rc = stats_before(LS_KERNEL_UPWIND, stream, &slot, nsteps)) != LS_OK) return rc;
     for (int s = 0; s < nsteps; ++s) {
         args.cur = (s & 1) ? scratch : phi;
         args.nxt = (s & 1) ? phi : scratch;
-        int64_t slot;
-        if ((rc = stats_before(LS_KERNEL_UPWIND, stream, &slot)) != LS_OK) return rc;
         hipLaunchKernelGGL(kernel, dim3(nblocks), dim3(threads), lds, stream, sg, args);
         LS_LAUNCH_CHECK("upwind_kernel");
-        if ((rc = stats_after(LS_KERNEL_UPWIND, stream, slot)) != LS_OK) return rc;
     }
+    if ((rc = stats_after(LS_KERNEL_UPWIND, stream, slot)) != LS_OK) return rc;
     if ((nsteps & 1) && !land_in_scratch) {
         hipLaunchKernelGGL(band_copy_kernel<S>, dim3(nblocks), dim3(kBlock), 0, stream, sg,
                            static_cast<const S *>(scratch), phi,

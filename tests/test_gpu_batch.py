@@ -109,3 +109,18 @@ def test_batch_point_steps_count_in_domain_points():
             ti, tj, tk = t % ntx, (t // ntx) % nty, t // (ntx * nty)
             want += (min(tx, nx - ti * tx) * min(ty, ny - tj * ty) * min(tz, nz - tk * tz))
     assert int(ps.item()) == 10 * want
+
+
+def test_native_autotuner_and_cache(tmp_path):
+    """ls_autotune picks one of the compiled shapes per size bucket, writes its
+    cache, and a second call answers from the cache."""
+    from paper_1612_04040_amd import autotune
+
+    path = str(tmp_path / "tune.txt")
+    table = autotune.tune([40, 50, 72], path=path)
+    assert set(table) == {1, 2}  # buckets of 32 points
+    assert all(tuple(t) in CANDIDATES for t in table.values())
+    with open(path) as fh:
+        lines = [ln for ln in fh.read().splitlines() if ln.strip()]
+    assert len(lines) == 2
+    assert autotune.tune([40, 72], path=path) == table
