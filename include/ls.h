@@ -283,14 +283,17 @@ int ls_upwind_launch_info(const ls_grid *g, int precision, int32_t *blocks, int3
 /* ---------------------------------------------------------------------------
  * Kernel timing (measurement support, not part of the method).
  *
- * While enabled, every launch of the kernel `which` (LS_KERNEL_UPWIND: the
- * band step kernel, LS_KERNEL_BAND_FLAG: the band build's full scan of phi)
- * is bracketed by a pair of HIP events recorded on the launch stream.
+ * While enabled, the launches of the kernel `which` (LS_KERNEL_UPWIND: the
+ * band step kernel, LS_KERNEL_BAND_FLAG: the band build's scan of phi) are
+ * bracketed by pairs of HIP events recorded on the launch stream: one pair
+ * around each scan, and one pair around the back-to-back step launches of a
+ * call (the nsteps launches of a window), so the time per launch includes the
+ * short gaps between consecutive launches but not the setup of the call.
  * ls_stats_enable(1) clears the record; ls_stats_read waits for the recorded
- * events and returns the number of launches and their summed duration in ms.
- * At most 65536 launches per kernel are recorded; later ones are counted in
- * *launches but not timed (*timed tells how many were).  Do not enable it
- * while a stream is being captured into a HIP graph.
+ * events and returns the number of launches, how many of them were timed,
+ * and the summed duration of the timed ones in ms.  At most 65536 event pairs
+ * per kernel are recorded.  Do not enable it while a stream is being captured
+ * into a HIP graph.
  * ------------------------------------------------------------------------- */
 enum { LS_KERNEL_UPWIND = 0, LS_KERNEL_BAND_FLAG = 1 };
 int ls_stats_enable(int on);
