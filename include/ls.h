@@ -256,6 +256,8 @@ typedef struct ls_tuning {
     int32_t pipeline; /* 0 auto (single grids: on when phi exceeds 1 GiB and a
                          work item spans at most 4 tiles; batches: off),
                          1 off, 2 on */
+    int32_t vector;   /* 0 auto (FP32 8x8x8 tiles on 16-byte aligned rows: the
+                         vectorised kernel), 1 off */
 } ls_tuning;
 int ls_set_tuning(const ls_tuning *t);
 int ls_get_tuning(ls_tuning *t);

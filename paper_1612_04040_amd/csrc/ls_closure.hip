@@ -373,9 +373,10 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int tap = 8 * c + 2 * kq + h;
+                    // taps past the 27th have zero weights: any point reads as well
                     off[c][h] = tap < kTaps
                                     ? ((tap / 9) * kF0 + (tap / 3) % 3) * kF0 + tap % 3
-                                    : -1;
+                                    : 0;
                 }
             }
             float bb[4];
@@ -390,11 +391,8 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
                 for (int c = 0; c < 4; ++c) {
                     uint2 v[2];
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        v[h] = make_uint2(0, 0);
-                        if (off[c][h] >= 0)
-                            v[h] = *reinterpret_cast<const uint2 *>(in + (q0 + off[c][h]) * 4);
-                    }
+                    for (int h = 0; h < 2; ++h)
+                        v[h] = *reinterpret_cast<const uint2 *>(in + (q0 + off[c][h]) * 4);
                     const bf16x8 b =
                         __builtin_bit_cast(bf16x8, make_uint4(v[0].x, v[0].y, v[1].x, v[1].y));
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[c], b, acc, 0, 0, 0);
@@ -420,10 +418,9 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
             for (int c = 0; c < 14; ++c) {
                 wa[c] = *reinterpret_cast<const bf16x8 *>(wts + ((4 + c) * 64 + lane) * 8);
                 const int tap = 2 * c + (kq >> 1);
-                off[c] = tap < kTaps
-                             ? (((tap / 9) * kF1 + (tap / 3) % 3) * kF1 + tap % 3) * 8 +
-                                   (kq & 1) * kHalf0
-                             : -1;
+                off[c] = (tap < kTaps ? (((tap / 9) * kF1 + (tap / 3) % 3) * kF1 + tap % 3) * 8
+                                      : 0) +
+                         (kq & 1) * kHalf0;  // taps past the 27th: zero weights
             }
             float bb[4];
 #pragma unroll
@@ -437,8 +434,7 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
                 f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int c = 0; c < 14; ++c) {
-                    bf16x8 b = bf16x8{};
-                    if (off[c] >= 0) b = *reinterpret_cast<const bf16x8 *>(a0 + q0 + off[c]);
+                    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(a0 + q0 + off[c]);
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[c], b, acc, 0, 0, 0);
                 }
                 const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z0 + lz - 1;
@@ -464,10 +460,9 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
             for (int c = 0; c < 14; ++c) {
                 wa[c] = *reinterpret_cast<const bf16x8 *>(wts + ((18 + c) * 64 + lane) * 8);
                 const int tap = 2 * c + (kq >> 1);
-                off[c] = tap < kTaps
-                             ? (((tap / 9) * kF2 + (tap / 3) % 3) * kF2 + tap % 3) * 8 +
-                                   (kq & 1) * kHalf1
-                             : -1;
+                off[c] = (tap < kTaps ? (((tap / 9) * kF2 + (tap / 3) % 3) * kF2 + tap % 3) * 8
+                                      : 0) +
+                         (kq & 1) * kHalf1;  // taps past the 27th: zero weights
             }
             const float b2 = params[kB2];
             // phi and the plain step on the lane's points, for the gate and the limiter
@@ -491,8 +486,7 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
                 f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int c = 0; c < 14; ++c) {
-                    bf16x8 b = bf16x8{};
-                    if (off[c] >= 0) b = *reinterpret_cast<const bf16x8 *>(a1 + q0 + off[c]);
+                    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(a1 + q0 + off[c]);
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[c], b, acc, 0, 0, 0);
                 }
                 rv[gi8] = acc[0] + b2;

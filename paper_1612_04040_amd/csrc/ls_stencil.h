@@ -362,4 +362,165 @@ __global__ __launch_bounds__((FastCfg<S, FT, TX, TY, TZ, R>::NT)) void upwind_fa
     }
 }
 
+// Vectorised FP32 band step for 8-point-wide tiles on grids with nx a
+// multiple of 4 (16-byte aligned rows): every lane owns 4 consecutive
+// x-points of a row and moves them with 16-byte loads and stores, a quarter of
+// the memory instructions of upwind_fast_kernel, with the same arithmetic
+// (bit-identical results).  Box rows are padded by 4 on the left so the
+// stores of the own points into LDS are aligned 16-byte stores too.
+template <int TY, int TZ, int R>
+struct VecCfg {
+    static constexpr int TX = 8, V = 4;
+    static constexpr int XP = R * TX;   // points per item row
+    static constexpr int XV = XP / V;   // lanes per item row
+    static constexpr int NT = XP >= 64 ? 2 * kBlock : kBlock;
+    static constexpr int RP = NT / XV;  // item rows per pass
+    static constexpr int ROWS = TY * TZ;
+    static constexpr int NOWN = ROWS / RP;
+    static constexpr int NHR = 2 * (TY + TZ);
+    static constexpr int NHALO = (NHR + RP - 1) / RP;
+    static constexpr int PAD = 4;
+    static constexpr int SX = XP + 2 * PAD, SXY = SX * (TY + 2);
+    static constexpr size_t lds = sizeof(float) * SXY * (TZ + 2);
+    static_assert(ROWS % RP == 0 && RP % TY == 0, "rows do not tile the block");
+    static_assert(2 * ROWS <= NT, "x-face points exceed one per thread");
+};
+
+template <int TY, int TZ, int R, bool PARTIAL>
+__global__ __launch_bounds__((VecCfg<TY, TZ, R>::NT)) void upwind_vec_kernel(
+    StepGeom g, StepArgs<float, float> a) {
+    using K = VecCfg<TY, TZ, R>;
+    constexpr int TX = K::TX, RP = K::RP, ROWS = K::ROWS, NOWN = K::NOWN, NHALO = K::NHALO;
+    constexpr int SX = K::SX, SXY = K::SXY, PAD = K::PAD, XV = K::XV;
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *box = reinterpret_cast<float *>(smem);
+
+    int w0, w1;
+    block_slice(0, *a.nitems, &w0, &w1);
+    const int lane = threadIdx.x & 63;
+    const int lx = (threadIdx.x % XV) * 4;
+    const int lr = threadIdx.x / XV;
+    const int lt = lx / TX;
+    const int ly0 = lr % TY, lz0 = lr / TY;
+    const int lbase = (lz0 + 1) * SXY + (ly0 + 1) * SX + PAD + lx;
+    constexpr int DZ = RP / TY;  // z rows between a thread's own rows
+    const bool xok = threadIdx.x < 2 * ROWS;
+    const int xside = threadIdx.x & 1;
+    const int xly = (threadIdx.x >> 1) % TY, xlz = (threadIdx.x >> 1) / TY;
+    const int nx = g.nx, ny = g.ny, nz = g.nz, plane = ny * nx;
+
+    for (int w = w0; w < w1; ++w) {
+        int rv = 0;
+        if (lane < kItemWords) rv = a.rec[static_cast<int64_t>(w) * kItemWords + lane];
+        const int t0 = __builtin_amdgcn_readlane(rv, 0);
+        const int len = __builtin_amdgcn_readlane(rv, 1);
+        const uint32_t m0 = __builtin_amdgcn_readlane(rv, 2), m1 = __builtin_amdgcn_readlane(rv, 3);
+        const uint32_t m2 = __builtin_amdgcn_readlane(rv, 4), m3 = __builtin_amdgcn_readlane(rv, 5);
+        const uint32_t mx = __builtin_amdgcn_readlane(rv, 6);
+        if (t0 < 0 || t0 >= g.ntiles) continue;  // uniform
+        const int ti0 = t0 % g.ntx, rr = t0 / g.ntx;
+        const int tj = rr % g.nty, tk = rr / g.nty;
+        const int x0 = ti0 * TX, y0 = tj * TY, z0 = tk * TZ;
+        const int W = min(len * TX, nx - x0);  // a multiple of 4
+        const int H = PARTIAL ? min(TY, ny - y0) : TY;
+        const int D = PARTIAL ? min(TZ, nz - z0) : TZ;
+        const int64_t base = (static_cast<int64_t>(z0) * ny + y0) * nx + x0;
+        const float *cur = a.cur + base;
+        const float *orig = a.orig + base;
+        const float *Fb = a.F + base;
+        float *nxt = a.nxt + base;
+        const int ebits = (y0 == 0 ? 1 : 0) | (y0 + H == ny ? 2 : 0) | (z0 == 0 ? 4 : 0) |
+                          (z0 + D == nz ? 8 : 0);
+        const bool col_ok = lx < W;
+        const int toff = lz0 * plane + ly0 * nx + lx;
+
+        float4 raw[NOWN], fv[NOWN];
+#pragma unroll
+        for (int q = 0; q < NOWN; ++q) {
+            if (col_ok && (!PARTIAL || (ly0 < H && lz0 + q * DZ < D))) {
+                const int u = q * DZ * plane;
+                raw[q] = *reinterpret_cast<const float4 *>(cur + u + toff);
+                fv[q] = *reinterpret_cast<const float4 *>(Fb + u + toff);
+            }
+        }
+        float4 hv[NHALO];
+        int hlds[NHALO];
+        bool hok[NHALO];
+#pragma unroll
+        for (int q = 0; q < NHALO; ++q) {
+            const int h = lr + q * RP;  // y-face rows (2 per z) first, then z-face rows
+            int ly, lz, lyc, lzc, face;
+            bool ok;
+            if (h < 2 * TZ) {
+                lz = h >> 1;
+                face = h & 1;
+                ly = face ? H : -1;
+                lyc = face ? H - 1 : 0;
+                lzc = lz;
+                ok = lz < D;
+            } else {
+                const int hh = h - 2 * TZ;
+                ly = hh >> 1;
+                face = 2 + (hh & 1);
+                lz = (hh & 1) ? D : -1;
+                lzc = (hh & 1) ? D - 1 : 0;
+                lyc = ly;
+                ok = hh < 2 * TY && ly < H;
+            }
+            ok = ok && col_ok;
+            hok[q] = ok;
+            hlds[q] = (lz + 1) * SXY + (ly + 1) * SX + PAD + lx;
+            const bool hi = face & 1, zf = face & 2;
+            const bool clamp = (ebits >> (face & 3)) & 1;
+            const uint32_t mk = zf ? (hi ? m3 : m2) : (hi ? m1 : m0);
+            const bool in = clamp || ((mk >> lt) & 1u);
+            const int o = clamp ? (lzc * plane + lyc * nx + lx) : (lz * plane + ly * nx + lx);
+            if (ok) hv[q] = *reinterpret_cast<const float4 *>((in ? cur : orig) + o);
+        }
+        float xv = 0.f;
+        const bool xrow_ok = xok && (!PARTIAL || (xly < H && xlz < D));
+        const int cx = xside ? (x0 + W < nx ? W : W - 1) : (x0 > 0 ? -1 : 0);
+        {
+            const bool in = (cx >= 0 && cx < W) || ((mx >> xside) & 1u);
+            const int o = xlz * plane + xly * nx + cx;
+            if (xrow_ok) xv = (in ? cur : orig)[o];
+        }
+
+        if (col_ok) {
+#pragma unroll
+            for (int q = 0; q < NOWN; ++q)
+                if (!PARTIAL || (ly0 < H && lz0 + q * DZ < D))
+                    *reinterpret_cast<float4 *>(box + lbase + q * DZ * SXY) = raw[q];
+        }
+#pragma unroll
+        for (int q = 0; q < NHALO; ++q)
+            if (hok[q]) *reinterpret_cast<float4 *>(box + hlds[q]) = hv[q];
+        if (xrow_ok)
+            box[(xlz + 1) * SXY + (xly + 1) * SX + (xside ? PAD + W : PAD - 1)] = xv;
+        __syncthreads();  // box complete
+
+        if (col_ok) {
+#pragma unroll
+            for (int q = 0; q < NOWN; ++q) {
+                if (PARTIAL && !(ly0 < H && lz0 + q * DZ < D)) continue;
+                const int o0 = lbase + q * DZ * SXY;
+                const float r4[4] = {raw[q].x, raw[q].y, raw[q].z, raw[q].w};
+                const float f4[4] = {fv[q].x, fv[q].y, fv[q].z, fv[q].w};
+                float out[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int o = o0 + e;
+                    const float v = upwind_point<float, false>(
+                        box[o], box[o - 1], box[o + 1], box[o - SX], box[o + SX], box[o - SXY],
+                        box[o + SXY], f4[e], a.dx, a.dt, a.dtdx);
+                    out[e] = (f4[e] == 0.f) ? r4[e] : v;
+                }
+                *reinterpret_cast<float4 *>(nxt + q * DZ * plane + toff) =
+                    make_float4(out[0], out[1], out[2], out[3]);
+            }
+        }
+        __syncthreads();  // box free for the next item
+    }
+}
+
 }  // namespace ls

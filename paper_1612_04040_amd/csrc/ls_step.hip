@@ -14,6 +14,7 @@
 // tile outside the band is read from phi, which holds its (frozen) value for
 // the whole call; a neighbour inside the band is read from P[s%2].
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 
 #include "ls_compact.h"
@@ -246,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void map_set_kernel(uint8_t *map, const int
 // host side
 
 // Process-wide launch tuning (ls_set_tuning); 0 fields mean the defaults.
-static ls_tuning g_tuning = {0, 0, 0};
+static ls_tuning g_tuning = {0, 0, 0, 0};
 constexpr int kDefaultRunWidth = 32;
 constexpr int kDefaultBlocksPerCu = 32;
 // Grids whose phi exceeds this stream from HBM (beyond the Infinity Cache)
@@ -344,9 +345,24 @@ static UpwindFn<S, FT, EXACT> select_halo(int nhalo) {
 // shapes and run lengths, else the run-time-shape kernel.
 template <class S, class FT, bool EXACT>
 static UpwindFn<S, FT, EXACT> select_upwind_kernel(const StepGeom &sg, int nown, int nhalo,
-                                                   size_t *lds, int *threads) {
+                                                   size_t *lds, int *threads,
+                                                   bool aligned = false) {
     *threads = kBlock;
     const bool whole_yz = sg.ny % sg.ty == 0 && sg.nz % sg.tz == 0;
+    if constexpr (std::is_same<S, float>::value && std::is_same<FT, float>::value && !EXACT) {
+        // 16-byte rows: the vectorised form (same arithmetic, fewer memory instructions)
+        if (g_tuning.vector != 1 && aligned && sg.nx % 4 == 0 && sg.tx == 8 && sg.ty == 8 &&
+            sg.tz == 8 && (sg.R == 4 || sg.R == 8)) {
+            if (sg.R == 4) {
+                *lds = VecCfg<8, 8, 4>::lds;
+                *threads = VecCfg<8, 8, 4>::NT;
+                return whole_yz ? upwind_vec_kernel<8, 8, 4, false> : upwind_vec_kernel<8, 8, 4, true>;
+            }
+            *lds = VecCfg<8, 8, 8>::lds;
+            *threads = VecCfg<8, 8, 8>::NT;
+            return whole_yz ? upwind_vec_kernel<8, 8, 8, false> : upwind_vec_kernel<8, 8, 8, true>;
+        }
+    }
     const bool pipe = use_pipeline(int64_t(sg.nx) * sg.ny * sg.nz * int64_t(sizeof(S)), sg.R);
 #define LS_FAST(TX_, TY_, TZ_, R_)                                                          \
     if (sg.tx == TX_ && sg.ty == TY_ && sg.tz == TZ_ && sg.R == R_) {                       \
@@ -452,7 +468,10 @@ static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const 
     const int nhalo = pow2_at_least((2 * (G.ty + G.tz) + rp - 1) / rp);
     size_t lds = static_cast<size_t>(sg.sx) * sg.sy * (G.tz + 2) * sizeof(C);
     int threads = kBlock;
-    auto kernel = select_upwind_kernel<S, FT, EXACT>(sg, nown, nhalo, &lds, &threads);
+    const bool aligned = reinterpret_cast<uintptr_t>(phi) % 16 == 0 &&
+                         reinterpret_cast<uintptr_t>(scratch) % 16 == 0 &&
+                         reinterpret_cast<uintptr_t>(F) % 16 == 0;
+    auto kernel = select_upwind_kernel<S, FT, EXACT>(sg, nown, nhalo, &lds, &threads, aligned);
     int nblocks = 0;
     int rc;
     if ((rc = persistent_grid(kernel, threads, lds, &nblocks, nullptr, G.ntiles)) != LS_OK)
@@ -643,7 +662,7 @@ extern "C" {
 int ls_set_tuning(const ls_tuning *t) {
     ls::clear_error();
     if (!t || t->run_width < 0 || t->blocks_per_cu < 0 || t->blocks_per_cu > 64 ||
-        t->pipeline < 0 || t->pipeline > 2) {
+        t->pipeline < 0 || t->pipeline > 2 || t->vector < 0 || t->vector > 1) {
         ls::set_error("tuning: NULL or out-of-range field");
         return LS_ERR_ARG;
     }
@@ -660,6 +679,7 @@ int ls_get_tuning(ls_tuning *t) {
     t->run_width = ls::run_width();
     t->blocks_per_cu = ls::g_tuning.blocks_per_cu;
     t->pipeline = ls::g_tuning.pipeline;
+    t->vector = ls::g_tuning.vector;
     return LS_OK;
 }
 
