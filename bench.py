@@ -208,7 +208,7 @@ def _single_grid(args, torch, ls, W, BandGrid, dev):
         },
         "kernel": ("ls::upwind_vec_kernel (f32, 8x8x8 tiles, 32-point rows, 16-byte accesses)"
                    if prec == "f32" else
-                   "ls::upwind_fast_kernel (f16s, 8x8x8 tiles, 64-point rows)"),
+                   "ls::upwind_vec_kernel (f16s, 8x8x8 tiles, 64-point rows, 8-byte accesses)"),
         "data": ("synthetic (seeded three-sphere signed distance, sinusoidal speed)"
                  if prec == "f32" else
                  "synthetic (torus signed distance stored as scaled FP16, speed 1 + 0.3 GRF)"),

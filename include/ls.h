@@ -256,16 +256,17 @@ typedef struct ls_tuning {
     int32_t pipeline; /* 0 auto (single grids: on when phi exceeds 1 GiB and a
                          work item spans at most 4 tiles; batches: off),
                          1 off, 2 on */
-    int32_t vector;   /* 0 auto (FP32 8x8x8 tiles on 16-byte aligned rows: the
-                         vectorised kernel), 1 off */
+    int32_t vector;   /* 0 auto (FP32 and FP16s, 8x8x8 tiles, nx a multiple of
+                         4, aligned buffers: the vectorised kernel), 1 off */
 } ls_tuning;
 int ls_set_tuning(const ls_tuning *t);
 int ls_get_tuning(ls_tuning *t);
 
 /* Tile-shape autotuner (native): for each size in sizes[0..n) (cubic grids
  * of that many points per axis), the tile shape with the shortest time per
- * window of the FP32 band driver, measured once per size bucket of 32 points
- * on a synthetic n^3 ellipsoid (sizes bucket*32 + 16) over the shapes the
+ * window of the FP32 batched band driver, measured once per size bucket of 32
+ * points on a batch of copies of a synthetic n^3 ellipsoid (n = bucket*32 +
+ * 16; about 2^25 points in all, at most 512 copies) over the shapes the
  * batched step is compiled for: 8x8x8, 16x4x4, 32x4x4, 16x8x8, 4x4x4.  out[i]
  * receives the grid (sizes[i]^3) with the chosen tile.  Results are cached in
  * the text file cache_path (NULL: no cache), keyed by device name and bucket;
@@ -278,7 +279,8 @@ int ls_autotune(const int32_t *sizes, int n, int precision, const char *cache_pa
 /* Launch configuration the band step would use for grid g on the current
  * device: precision 0 = f32, 1 = f64, 2 = f16s.  Outputs (any may be NULL):
  * workgroups, LDS bytes per workgroup, tiles per work item, and the
- * occupancy limit in workgroups per compute unit. */
+ * occupancy limit in workgroups per compute unit, for 16-byte aligned phi, F
+ * and scratch buffers (what every allocator here returns). */
 int ls_upwind_launch_info(const ls_grid *g, int precision, int32_t *blocks, int32_t *lds_bytes,
                           int32_t *run_tiles, int32_t *blocks_per_cu_limit);
 

@@ -234,7 +234,10 @@ __global__ __launch_bounds__(kBlock) void batch_flag_kernel(const float *__restr
     for (int t = threadIdx.x; t < d.ntx; t += kBlock) dst[t] = sflag[t];
 }
 
-// Tile flags of the listed (global) tiles only: one wave per tile.
+// Tile flags of the listed (global) tiles only: one wave per tile.  Tiles
+// with power-of-two x and y extents (every shape the batched step is compiled
+// for) are read 512 points at a time, all eight loads of a lane issued before
+// any is tested; other shapes take a plain loop.
 __global__ __launch_bounds__(kBlock) void batch_flag_list_kernel(
     const float *__restrict__ phi, const BatchInst *__restrict__ inst, int n, int total_tiles,
     const int32_t *__restrict__ list, const int32_t *__restrict__ list_count,
@@ -251,13 +254,32 @@ __global__ __launch_bounds__(kBlock) void batch_flag_list_kernel(
         const int tj = r % d.nty, tk = r / d.nty;
         const int x0 = ti * d.tx, y0 = tj * d.ty, z0 = tk * d.tz;
         const int W = min(d.tx, d.nx - x0), H = min(d.ty, d.ny - y0), D = min(d.tz, d.nz - z0);
-        const float *ph = phi + d.offset;
+        const float *ph = phi + d.offset + (static_cast<int64_t>(z0) * d.ny + y0) * d.nx + x0;
+        const int64_t plane = static_cast<int64_t>(d.ny) * d.nx;
         bool hit = false;
-        for (int q = lane; q < W * H * D; q += 64) {
-            const int lx = q % W, rr = q / W;
-            const int ly = rr % H, lz = rr / H;
-            hit |= fabsf(ph[(static_cast<int64_t>(z0 + lz) * d.ny + (y0 + ly)) * d.nx + x0 + lx]) <
-                   d.gamma;
+        if (((d.tx & (d.tx - 1)) | (d.ty & (d.ty - 1))) == 0) {
+            const int sx = __ffs(d.tx) - 1, sy = __ffs(d.ty) - 1;
+            const int box = d.tx * d.ty * d.tz;
+            for (int q0 = 0; q0 < box; q0 += 512) {
+                float v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int q = q0 + u * 64 + lane;
+                    const int lx = q & (d.tx - 1), rr = q >> sx;
+                    const int ly = rr & (d.ty - 1), lz = rr >> sy;
+                    v[u] = INFINITY;
+                    if (q < box && lx < W && ly < H && lz < D)
+                        v[u] = ph[lz * plane + static_cast<int64_t>(ly) * d.nx + lx];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) hit |= fabsf(v[u]) < d.gamma;
+            }
+        } else {
+            for (int q = lane; q < W * H * D; q += 64) {
+                const int lx = q % W, rr = q / W;
+                const int ly = rr % H, lz = rr / H;
+                hit |= fabsf(ph[lz * plane + static_cast<int64_t>(ly) * d.nx + lx]) < d.gamma;
+            }
         }
         const bool any = __ballot(hit) != 0;
         if (lane == 0) a_flags[gt] = any ? 1 : 0;
@@ -400,14 +422,15 @@ __global__ void batch_accumulate_kernel(int64_t *acc, const int32_t *count, int 
     if (threadIdx.x == 0 && blockIdx.x == 0) *acc += static_cast<int64_t>(*count) * nsteps;
 }
 
-// acc += nsteps * (in-domain points of the listed tiles); one block.
+// acc += nsteps * (in-domain points of the listed tiles): a grid-stride sum,
+// one atomic add per block (integer, so the order does not matter).
 __global__ __launch_bounds__(kBlock) void batch_point_count_kernel(
     int64_t *acc, const int32_t *__restrict__ list, const int32_t *count,
     const BatchInst *__restrict__ inst, int n, int total_tiles, int nsteps) {
     __shared__ int64_t red[kBlock];
     const int m = min(*count, total_tiles);
     int64_t s = 0;
-    for (int p = threadIdx.x; p < m; p += kBlock) {
+    for (int p = blockIdx.x * kBlock + threadIdx.x; p < m; p += gridDim.x * kBlock) {
         const int gt = list[p];
         if (gt < 0 || gt >= total_tiles) continue;
         const BatchInst &d = inst[find_inst(inst, n, gt, false)];
@@ -423,7 +446,9 @@ __global__ __launch_bounds__(kBlock) void batch_point_count_kernel(
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *acc += red[0] * nsteps;
+    if (threadIdx.x == 0 && red[0] != 0)
+        atomicAdd(reinterpret_cast<unsigned long long *>(acc),
+                  static_cast<unsigned long long>(red[0] * nsteps));
 }
 
 // ---------------------------------------------------------------------------
@@ -656,7 +681,9 @@ int ls_batch_run_f32(const ls_instance *inst, int n, float *phi, const float *F,
             LS_LAUNCH_CHECK("batch_accumulate_kernel");
         }
         if (point_steps_dev) {
-            hipLaunchKernelGGL(ls::batch_point_count_kernel, dim3(1), dim3(ls::kBlock), 0, stream,
+            const unsigned pb = static_cast<unsigned>(
+                std::min<int64_t>(ls::cdiv64(L.total_tiles, ls::kBlock), 1024));
+            hipLaunchKernelGGL(ls::batch_point_count_kernel, dim3(pb), dim3(ls::kBlock), 0, stream,
                                point_steps_dev, static_cast<const int32_t *>(lists[cur]),
                                static_cast<const int32_t *>(counts[cur]),
                                reinterpret_cast<const ls::BatchInst *>(ws + w.inst), n,

@@ -362,12 +362,38 @@ __global__ __launch_bounds__((FastCfg<S, FT, TX, TY, TZ, R>::NT)) void upwind_fa
     }
 }
 
-// Vectorised FP32 band step for 8-point-wide tiles on grids with nx a
-// multiple of 4 (16-byte aligned rows): every lane owns 4 consecutive
-// x-points of a row and moves them with 16-byte loads and stores, a quarter of
-// the memory instructions of upwind_fast_kernel, with the same arithmetic
-// (bit-identical results).  Box rows are padded by 4 on the left so the
-// stores of the own points into LDS are aligned 16-byte stores too.
+// Four consecutive stored values of a row as one vector access: 16 bytes of
+// FP32, 8 bytes of scaled FP16.
+template <class S>
+struct Vec4;
+template <>
+struct Vec4<float> {
+    using T = float4;
+    __device__ static inline float get(const T &v, int e) {
+        return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
+    }
+    __device__ static inline T make(const float o[4]) { return make_float4(o[0], o[1], o[2], o[3]); }
+};
+template <>
+struct Vec4<uint16_t> {
+    using T = uint2;
+    __device__ static inline uint16_t get(const T &v, int e) {
+        const uint32_t w = e < 2 ? v.x : v.y;
+        return static_cast<uint16_t>((e & 1) ? (w >> 16) : (w & 0xffffu));
+    }
+    __device__ static inline T make(const uint16_t o[4]) {
+        return make_uint2(uint32_t(o[0]) | (uint32_t(o[1]) << 16),
+                          uint32_t(o[2]) | (uint32_t(o[3]) << 16));
+    }
+};
+
+// Vectorised band step (FP32 or scaled-FP16 storage, FP32 arithmetic) for
+// 8-point-wide tiles on grids with nx a multiple of 4 (aligned rows): every
+// lane owns 4 consecutive x-points of a row and moves them with one vector
+// access, a quarter of the memory instructions of upwind_fast_kernel, with
+// the same arithmetic (bit-identical results).  Box rows are padded by 4 on
+// the left so the stores of the own points into LDS are aligned 16-byte
+// stores too.
 template <int TY, int TZ, int R>
 struct VecCfg {
     static constexpr int TX = 8, V = 4;
@@ -386,10 +412,12 @@ struct VecCfg {
     static_assert(2 * ROWS <= NT, "x-face points exceed one per thread");
 };
 
-template <int TY, int TZ, int R, bool PARTIAL>
+template <class S, int TY, int TZ, int R, bool PARTIAL>
 __global__ __launch_bounds__((VecCfg<TY, TZ, R>::NT)) void upwind_vec_kernel(
-    StepGeom g, StepArgs<float, float> a) {
+    StepGeom g, StepArgs<S, float> a) {
     using K = VecCfg<TY, TZ, R>;
+    using VS = Vec4<S>;
+    using VT = typename VS::T;
     constexpr int TX = K::TX, RP = K::RP, ROWS = K::ROWS, NOWN = K::NOWN, NHALO = K::NHALO;
     constexpr int SX = K::SX, SXY = K::SXY, PAD = K::PAD, XV = K::XV;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -408,6 +436,11 @@ __global__ __launch_bounds__((VecCfg<TY, TZ, R>::NT)) void upwind_vec_kernel(
     const int xside = threadIdx.x & 1;
     const int xly = (threadIdx.x >> 1) % TY, xlz = (threadIdx.x >> 1) / TY;
     const int nx = g.nx, ny = g.ny, nz = g.nz, plane = ny * nx;
+    const float sc = a.scale;
+    auto decode = [&](const VT &v) {
+        return make_float4(Codec<S>::load(VS::get(v, 0), sc), Codec<S>::load(VS::get(v, 1), sc),
+                           Codec<S>::load(VS::get(v, 2), sc), Codec<S>::load(VS::get(v, 3), sc));
+    };
 
     for (int w = w0; w < w1; ++w) {
         int rv = 0;
@@ -425,25 +458,26 @@ __global__ __launch_bounds__((VecCfg<TY, TZ, R>::NT)) void upwind_vec_kernel(
         const int H = PARTIAL ? min(TY, ny - y0) : TY;
         const int D = PARTIAL ? min(TZ, nz - z0) : TZ;
         const int64_t base = (static_cast<int64_t>(z0) * ny + y0) * nx + x0;
-        const float *cur = a.cur + base;
-        const float *orig = a.orig + base;
+        const S *cur = a.cur + base;
+        const S *orig = a.orig + base;
         const float *Fb = a.F + base;
-        float *nxt = a.nxt + base;
+        S *nxt = a.nxt + base;
         const int ebits = (y0 == 0 ? 1 : 0) | (y0 + H == ny ? 2 : 0) | (z0 == 0 ? 4 : 0) |
                           (z0 + D == nz ? 8 : 0);
         const bool col_ok = lx < W;
         const int toff = lz0 * plane + ly0 * nx + lx;
 
-        float4 raw[NOWN], fv[NOWN];
+        VT raw[NOWN];
+        float4 fv[NOWN];
 #pragma unroll
         for (int q = 0; q < NOWN; ++q) {
             if (col_ok && (!PARTIAL || (ly0 < H && lz0 + q * DZ < D))) {
                 const int u = q * DZ * plane;
-                raw[q] = *reinterpret_cast<const float4 *>(cur + u + toff);
+                raw[q] = *reinterpret_cast<const VT *>(cur + u + toff);
                 fv[q] = *reinterpret_cast<const float4 *>(Fb + u + toff);
             }
         }
-        float4 hv[NHALO];
+        VT hv[NHALO];
         int hlds[NHALO];
         bool hok[NHALO];
 #pragma unroll
@@ -475,9 +509,9 @@ __global__ __launch_bounds__((VecCfg<TY, TZ, R>::NT)) void upwind_vec_kernel(
             const uint32_t mk = zf ? (hi ? m3 : m2) : (hi ? m1 : m0);
             const bool in = clamp || ((mk >> lt) & 1u);
             const int o = clamp ? (lzc * plane + lyc * nx + lx) : (lz * plane + ly * nx + lx);
-            if (ok) hv[q] = *reinterpret_cast<const float4 *>((in ? cur : orig) + o);
+            if (ok) hv[q] = *reinterpret_cast<const VT *>((in ? cur : orig) + o);
         }
-        float xv = 0.f;
+        S xv = S(0);
         const bool xrow_ok = xok && (!PARTIAL || (xly < H && xlz < D));
         const int cx = xside ? (x0 + W < nx ? W : W - 1) : (x0 > 0 ? -1 : 0);
         {
@@ -490,13 +524,14 @@ __global__ __launch_bounds__((VecCfg<TY, TZ, R>::NT)) void upwind_vec_kernel(
 #pragma unroll
             for (int q = 0; q < NOWN; ++q)
                 if (!PARTIAL || (ly0 < H && lz0 + q * DZ < D))
-                    *reinterpret_cast<float4 *>(box + lbase + q * DZ * SXY) = raw[q];
+                    *reinterpret_cast<float4 *>(box + lbase + q * DZ * SXY) = decode(raw[q]);
         }
 #pragma unroll
         for (int q = 0; q < NHALO; ++q)
-            if (hok[q]) *reinterpret_cast<float4 *>(box + hlds[q]) = hv[q];
+            if (hok[q]) *reinterpret_cast<float4 *>(box + hlds[q]) = decode(hv[q]);
         if (xrow_ok)
-            box[(xlz + 1) * SXY + (xly + 1) * SX + (xside ? PAD + W : PAD - 1)] = xv;
+            box[(xlz + 1) * SXY + (xly + 1) * SX + (xside ? PAD + W : PAD - 1)] =
+                Codec<S>::load(xv, sc);
         __syncthreads();  // box complete
 
         if (col_ok) {
@@ -504,19 +539,17 @@ __global__ __launch_bounds__((VecCfg<TY, TZ, R>::NT)) void upwind_vec_kernel(
             for (int q = 0; q < NOWN; ++q) {
                 if (PARTIAL && !(ly0 < H && lz0 + q * DZ < D)) continue;
                 const int o0 = lbase + q * DZ * SXY;
-                const float r4[4] = {raw[q].x, raw[q].y, raw[q].z, raw[q].w};
                 const float f4[4] = {fv[q].x, fv[q].y, fv[q].z, fv[q].w};
-                float out[4];
+                S out[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int o = o0 + e;
                     const float v = upwind_point<float, false>(
                         box[o], box[o - 1], box[o + 1], box[o - SX], box[o + SX], box[o - SXY],
                         box[o + SXY], f4[e], a.dx, a.dt, a.dtdx);
-                    out[e] = (f4[e] == 0.f) ? r4[e] : v;
+                    out[e] = (f4[e] == 0.f) ? VS::get(raw[q], e) : Codec<S>::store(v, sc);
                 }
-                *reinterpret_cast<float4 *>(nxt + q * DZ * plane + toff) =
-                    make_float4(out[0], out[1], out[2], out[3]);
+                *reinterpret_cast<VT *>(nxt + q * DZ * plane + toff) = VS::make(out);
             }
         }
         __syncthreads();  // box free for the next item

@@ -349,18 +349,20 @@ static UpwindFn<S, FT, EXACT> select_upwind_kernel(const StepGeom &sg, int nown,
                                                    bool aligned = false) {
     *threads = kBlock;
     const bool whole_yz = sg.ny % sg.ty == 0 && sg.nz % sg.tz == 0;
-    if constexpr (std::is_same<S, float>::value && std::is_same<FT, float>::value && !EXACT) {
-        // 16-byte rows: the vectorised form (same arithmetic, fewer memory instructions)
+    if constexpr (std::is_same<FT, float>::value && !EXACT) {
+        // aligned rows: the vectorised form (same arithmetic, fewer memory instructions)
         if (g_tuning.vector != 1 && aligned && sg.nx % 4 == 0 && sg.tx == 8 && sg.ty == 8 &&
             sg.tz == 8 && (sg.R == 4 || sg.R == 8)) {
             if (sg.R == 4) {
                 *lds = VecCfg<8, 8, 4>::lds;
                 *threads = VecCfg<8, 8, 4>::NT;
-                return whole_yz ? upwind_vec_kernel<8, 8, 4, false> : upwind_vec_kernel<8, 8, 4, true>;
+                return whole_yz ? upwind_vec_kernel<S, 8, 8, 4, false>
+                                : upwind_vec_kernel<S, 8, 8, 4, true>;
             }
             *lds = VecCfg<8, 8, 8>::lds;
             *threads = VecCfg<8, 8, 8>::NT;
-            return whole_yz ? upwind_vec_kernel<8, 8, 8, false> : upwind_vec_kernel<8, 8, 8, true>;
+            return whole_yz ? upwind_vec_kernel<S, 8, 8, 8, false>
+                            : upwind_vec_kernel<S, 8, 8, 8, true>;
         }
     }
     const bool pipe = use_pipeline(int64_t(sg.nx) * sg.ny * sg.nz * int64_t(sizeof(S)), sg.R);
@@ -567,7 +569,7 @@ static int launch_info(const ls_grid *grid, int32_t *blocks, int32_t *lds_bytes,
     const int nown = pow2_at_least((G.ty * G.tz + rp - 1) / rp);
     const int nhalo = pow2_at_least((2 * (G.ty + G.tz) + rp - 1) / rp);
     int threads = kBlock;
-    auto kernel = select_upwind_kernel<S, FT, EXACT>(sg, nown, nhalo, &lds, &threads);
+    auto kernel = select_upwind_kernel<S, FT, EXACT>(sg, nown, nhalo, &lds, &threads, true);
     int nb = 0, lim = 0;
     if ((rc = persistent_grid(kernel, threads, lds, &nb, &lim, G.ntiles)) != LS_OK) return rc;
     if (blocks) *blocks = nb;

@@ -192,3 +192,50 @@ def test_vector_and_scalar_kernels_agree_bitwise(dims, run_width):
     assert out[0].tobytes() == out[1].tobytes()
     want = oracle.upwind_steps(phi.astype(np.float64), F, dx, dt, tiles, 3, tile)
     assert np.max(np.abs(out[0] - want)) <= fp32_step_bound(phi, F, dx, dt, 3)
+
+
+@pytest.mark.parametrize("dims", [(96, 100, 92), (128, 72, 80)])
+@pytest.mark.parametrize("run_width", [32, 64])
+def test_vector_and_scalar_kernels_agree_bitwise_f16s(dims, run_width):
+    """Scaled-FP16 storage: the vectorised step (8-byte rows of four halves)
+    and the scalar fast step give the same bits, F = 0 points keep theirs, and
+    both stay within the FP16 storage bound of the FP64 oracle run on the
+    dequantised input."""
+    from paper_1612_04040_amd import ls
+
+    rng = np.random.default_rng(sum(dims) + 7 * run_width)
+    nx, ny, nz = dims
+    s = np.float32(0.05)
+    h = (rng.uniform(-1, 1, (nz, ny, nx)) / float(s)).astype(np.float16)
+    h.flat[::11] = np.float16(-0.0)
+    F = rng.uniform(-1, 1, (nz, ny, nx)).astype(np.float32)
+    zero = rng.random(F.shape) < 0.05
+    F[zero] = 0.0
+    phi = oracle.dequant_f16s(h, s)
+    dx = 1.0 / nx
+    dt = float(np.float32(W.stable_dt(F, dx)))
+    tile = (8, 8, 8)
+    ntiles = -(-nx // 8) * -(-ny // 8) * -(-nz // 8)
+    tiles = random_tiles(rng, ntiles, 0.4)
+    steps = 3
+    out = {}
+    try:
+        for vec in (0, 1):
+            ls.ls_set_tuning(run_width, 0, 0, vec)
+            bg = BandGrid(dims, tile, "f16s")
+            hd = torch.from_numpy(h.copy()).to(dev())
+            bg.step(hd, to_dev(F), dx, dt, steps, scale=float(s), tiles=to_dev(tiles),
+                    ntiles=to_dev(np.array([tiles.size], np.int32)))
+            out[vec] = host(hd)
+    finally:
+        ls.ls_set_tuning(0, 0, 0, 0)
+    assert out[0].tobytes() == out[1].tobytes()
+    assert out[0][zero].tobytes() == h[zero].tobytes()
+    want = oracle.upwind_steps(phi.astype(np.float64), F, dx, dt, tiles, steps, tile)
+    got = oracle.dequant_f16s(out[0], s).astype(np.float64)
+    # one FP16 store rounding per step (half an ulp of the largest |phi|/s
+    # reached, times s) on top of the FP32 arithmetic bound; non-expansive
+    reach = max(float(np.abs(want).max()), float(np.abs(got).max())) / float(s)
+    half_ulp = 2.0 ** (np.floor(np.log2(reach)) - 11)
+    bound = steps * half_ulp * float(s) + fp32_step_bound(phi, F, dx, dt, steps)
+    assert np.max(np.abs(got - want)) <= bound
