@@ -59,7 +59,7 @@ def parse():
     return args
 
 
-STEP_KERNEL_SOURCES = ("ls_internal.h", "ls_stencil.h", "ls_step.hip")
+STEP_KERNEL_SOURCES = ("ls_internal.h", "ls_stencil.h", "ls_step.hip", "ls_batch.hip")
 
 
 def kernel_source_digest():

@@ -182,7 +182,13 @@ int ls_band_run_f16s(uint16_t *phi_h, float scale, const float *F, const ls_grid
  * launches (the narrow-band driver above, applied to every grid at once).
  *
  * Each grid lives in the caller's phi / F / scratch buffers (FP32) at element
- * `offset`, x fastest as above; the grids must not overlap.  The tile shape of
+ * `offset`, x fastest, with `pitch` elements from one x row to the next
+ * (pitch >= nx; 0 means nx, the dense layout above) and pitch * ny from one z
+ * plane to the next: point (i, j, k) is element offset + (k*ny + j)*pitch + i.
+ * The pitch padding is never read or written.  A pitch that is a multiple of
+ * 32 (128 bytes) with a 128-byte aligned offset starts every row on a cache
+ * line, which the step kernel's row loads are laid out for.  The grids (their
+ * pitch * ny * nz spans) must not overlap.  The tile shape of
  * a grid is its own (typically picked per size by an autotuner); it must be
  * one of the shapes the batched step kernel is compiled for: 8x8x8, 16x4x4,
  * 32x4x4, 16x8x8 or 4x4x4 with the default run width, and the other shapes
@@ -197,7 +203,7 @@ typedef struct ls_instance {
     int64_t offset;   /* first element of this grid in phi, F and scratch */
     float dx, dt;     /* spacing and time step */
     float gamma;      /* band half-width */
-    int32_t reserved; /* 0 */
+    int32_t pitch;    /* elements between consecutive x rows (>= nx); 0 = nx */
 } ls_instance;
 
 /* Workspace bytes of a batch (device memory, caller-owned). */

@@ -5,29 +5,33 @@ import torch
 
 from . import ls
 
-ALIGN = 64  # grid offsets in elements: 256-byte aligned rows for vector loads
+ALIGN = 64  # grid offsets in elements (256 bytes)
+ROW_ALIGN = 32  # default row pitch granule in elements: every x row starts a 128-byte line
 
 
 class Batch:
     """Grids (n_i^3 or any dims) packed into one phi / F / scratch buffer each.
 
     ``specs`` is a list of (dims, tile, dx, dt, gamma); grid i starts at
-    element ``offsets[i]`` of the buffers.
+    element ``offsets[i]`` of the buffers, its x rows ``pitches[i]`` elements
+    apart (nx rounded up to ``row_align``; 1 gives dense rows).
     """
 
-    def __init__(self, specs, device="cuda"):
+    def __init__(self, specs, device="cuda", row_align=ROW_ALIGN):
         self.device = torch.device(device)
         self.specs = [(tuple(int(v) for v in d), tuple(int(v) for v in t), float(dx), float(dt),
                        float(gm)) for d, t, dx, dt, gm in specs]
-        self.offsets = []
+        self.offsets, self.pitches = [], []
         off = 0
-        for dims, *_ in self.specs:
+        for (nx, ny, nz), *_ in self.specs:
+            px = -(-nx // row_align) * row_align
             self.offsets.append(off)
-            off += -(-int(np.prod(dims)) // ALIGN) * ALIGN
+            self.pitches.append(px)
+            off += -(-px * ny * nz // ALIGN) * ALIGN
         self.total = off
         self.n = len(self.specs)
-        self.inst = ls.instances([(d, t, o, dx, dt, g) for (d, t, dx, dt, g), o
-                                  in zip(self.specs, self.offsets)])
+        self.inst = ls.instances([(d, t, o, dx, dt, g, px) for (d, t, dx, dt, g), o, px
+                                  in zip(self.specs, self.offsets, self.pitches)])
         self.tile_base, self.total_tiles = ls.ls_batch_layout(self.inst, self.n)
         self.ws_bytes = ls.ls_batch_workspace_bytes(self.inst, self.n)
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
@@ -39,9 +43,10 @@ class Batch:
         ls.ls_batch_setup(self.inst, self.n, self.ws, self.ws_bytes)
 
     def view(self, buf, i):
+        """(nz, ny, nx) view of grid i in a batch buffer (strided when pitched)."""
         nx, ny, nz = self.specs[i][0]
-        o = self.offsets[i]
-        return buf[o:o + nx * ny * nz].view(nz, ny, nx)
+        o, px = self.offsets[i], self.pitches[i]
+        return buf[o:o + px * ny * nz].view(nz, ny, px)[:, :, :nx]
 
     def load(self, phis, Fs):
         for i, (p, f) in enumerate(zip(phis, Fs)):

@@ -4,8 +4,8 @@
 // copies of a synthetic ellipsoid of that size, enough copies for about
 // kTunePoints grid points, so the measurement sees the work of a full batch
 // rather than launch latency; each candidate tile shape is timed and the one
-// with the shortest time per window kept: the time to advance the same
-// fronts, which is what differs between shapes (a bigger tile updates more
+// with the shortest time per window kept (rows pitched to 128 bytes, as a
+// batch lays them out): the time to advance the same fronts, which is what differs between shapes (a bigger tile updates more
 // points of the same band).
 //
 // Results are cached in a text file, one line per (device, bucket):
@@ -26,24 +26,27 @@ constexpr int kTuneBucket = 32;
 constexpr int kTuneShapes[][3] = {{8, 8, 8}, {16, 4, 4}, {32, 4, 4}, {16, 8, 8}, {4, 4, 4}};
 constexpr int64_t kTunePoints = int64_t(1) << 25;
 constexpr int kTuneMaxCopies = 512;
-constexpr int64_t kTuneAlign = 64;  // copy offsets in elements (256-byte aligned rows)
+constexpr int64_t kTuneAlign = 64;     // copy offsets in elements (256 bytes)
+constexpr int kTuneRowAlign = 32;      // row pitch granule in elements (128 bytes)
 
-// copies x (phi, F) of one n^3 grid, copy c at element c * stride:
+// copies x (phi, F) of one n^3 grid, copy c at element c * stride, x rows px
+// elements apart:
 // phi = (|A^-1 (x - c)| - 1) * min(a) for the axis-aligned ellipsoid with
 // semi-axes a about c (sign-correct, |grad phi| in [a_min/a_max, 1] on the
 // surface); F = speed.
-__global__ void tune_field_kernel(float *__restrict__ phi, float *__restrict__ F, int n,
+__global__ void tune_field_kernel(float *__restrict__ phi, float *__restrict__ F, int n, int px,
                                   int copies, int64_t stride, float dx, float cx, float cy,
                                   float cz, float ax, float ay, float az, float speed) {
-    const int64_t pts = static_cast<int64_t>(n) * n * n;
+    const int64_t span = static_cast<int64_t>(px) * n * n;
     const int64_t total = stride * copies;
     const float amin = fminf(ax, fminf(ay, az));
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int64_t l = i % stride;
-        if (l >= pts) continue;
-        const int x = static_cast<int>(l % n), y = static_cast<int>((l / n) % n);
-        const int z = static_cast<int>(l / (static_cast<int64_t>(n) * n));
+        if (l >= span) continue;
+        const int x = static_cast<int>(l % px), y = static_cast<int>((l / px) % n);
+        const int z = static_cast<int>(l / (static_cast<int64_t>(px) * n));
+        if (x >= n) continue;
         const float u = ((x + 0.5f) * dx - cx) / ax, v = ((y + 0.5f) * dx - cy) / ay,
                     w = ((z + 0.5f) * dx - cz) / az;
         phi[i] = (sqrtf(u * u + v * v + w * w) - 1.0f) * amin;
@@ -77,12 +80,13 @@ static int time_shape(int n, const int t[3], float *ms) {
     const float dt = static_cast<float>(0.5 * static_cast<double>(dx) / speed);
     const float gamma = static_cast<float>(6.0 * static_cast<double>(dx));
     const int64_t pts = static_cast<int64_t>(n) * n * n;
-    const int64_t stride = cdiv64(pts, kTuneAlign) * kTuneAlign;
+    const int px = static_cast<int>(cdiv64(n, kTuneRowAlign) * kTuneRowAlign);
+    const int64_t stride = cdiv64(static_cast<int64_t>(px) * n * n, kTuneAlign) * kTuneAlign;
     const int copies =
         static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(kTuneMaxCopies, kTunePoints / pts)));
     std::vector<ls_instance> inst(copies);
     for (int c = 0; c < copies; ++c)
-        inst[c] = ls_instance{ls_grid{n, n, n, t[0], t[1], t[2]}, c * stride, dx, dt, gamma, 0};
+        inst[c] = ls_instance{ls_grid{n, n, n, t[0], t[1], t[2]}, c * stride, dx, dt, gamma, px};
     const int64_t wsb = ls_batch_workspace_bytes(inst.data(), copies);
     if (wsb < 0) return static_cast<int>(wsb);
     const int64_t total = stride * copies;
@@ -99,7 +103,7 @@ static int time_shape(int n, const int t[3], float *ms) {
     if (rc != LS_OK) return rc;
     float *p = static_cast<float *>(phi.p), *f = static_cast<float *>(F.p);
     auto reset = [&]() -> int {
-        hipLaunchKernelGGL(tune_field_kernel, dim3(2048), dim3(256), 0, sg.s, p, f, n, copies,
+        hipLaunchKernelGGL(tune_field_kernel, dim3(2048), dim3(256), 0, sg.s, p, f, n, px, copies,
                            stride, dx, 0.5f, 0.47f, 0.53f, 0.27f, 0.19f, 0.23f, speed);
         LS_LAUNCH_CHECK("tune_field_kernel");
         return LS_OK;

@@ -84,15 +84,24 @@ static int make_layout(const ls_instance *in, int n, BatchLayout *L) {
                       "of the batched kernel shapes", s.tx, s.ty, s.tz, s.R, i);
             return LS_ERR_UNSUPPORTED;
         }
-        if (static_cast<int64_t>(geo[i].tz + 1) * geo[i].ny * geo[i].nx >= (int64_t(1) << 31)) {
+        if (in[i].pitch != 0 && in[i].pitch < geo[i].nx) {
+            set_error("batch: instance %d has pitch %d < nx = %d", i, in[i].pitch, geo[i].nx);
+            return LS_ERR_ARG;
+        }
+        const int64_t px = in[i].pitch ? in[i].pitch : geo[i].nx;
+        if (static_cast<int64_t>(geo[i].tz + 1) * geo[i].ny * px >= (int64_t(1) << 31)) {
             set_error("batch: instance %d is too large", i);
             return LS_ERR_UNSUPPORTED;
         }
         key[i] = {s, i};
     }
+    auto pitch_of = [&](int i) -> int64_t { return in[i].pitch ? in[i].pitch : geo[i].nx; };
+    auto span_of = [&](int i) -> int64_t {
+        return pitch_of(i) * geo[i].ny * static_cast<int64_t>(geo[i].nz);
+    };
     // check the grids do not overlap in the buffers
     std::vector<std::pair<int64_t, int64_t>> spans(n);
-    for (int i = 0; i < n; ++i) spans[i] = {in[i].offset, in[i].offset + geo[i].npoints};
+    for (int i = 0; i < n; ++i) spans[i] = {in[i].offset, in[i].offset + span_of(i)};
     std::sort(spans.begin(), spans.end());
     for (int i = 1; i < n; ++i)
         if (spans[i].first < spans[i - 1].second) {
@@ -126,7 +135,8 @@ static int make_layout(const ls_instance *in, int n, BatchLayout *L) {
         b.ntiles = static_cast<int32_t>(g.ntiles);
         b.R = key[k].first.R;
         b.slab_base = static_cast<int32_t>(slabs);
-        b.vec_ok = (g.nx % 4 == 0 && in[i].offset % 4 == 0) ? 1 : 0;
+        b.px = static_cast<int32_t>(pitch_of(i));
+        b.vec_ok = (g.nx % 4 == 0 && b.px % 4 == 0 && in[i].offset % 4 == 0) ? 1 : 0;
         b.dx = in[i].dx;
         b.dt = in[i].dt;
         b.dtdx = static_cast<float>(static_cast<double>(in[i].dt) / static_cast<double>(in[i].dx));
@@ -137,7 +147,7 @@ static int make_layout(const ls_instance *in, int n, BatchLayout *L) {
         tiles += g.ntiles;
         slabs += static_cast<int64_t>(g.nty) * g.ntz;
         L->max_ntx = std::max(L->max_ntx, g.ntx);
-        L->max_points = std::max(L->max_points, in[i].offset + g.npoints);
+        L->max_points = std::max(L->max_points, in[i].offset + span_of(i));
         if (tiles > INT32_MAX - kCompactChunk || slabs > INT32_MAX) {
             set_error("batch: too many tiles in total");
             return LS_ERR_UNSUPPORTED;
@@ -215,7 +225,7 @@ __global__ __launch_bounds__(kBlock) void batch_flag_kernel(const float *__restr
             const int r = q / nvec, c = q - r * nvec;
             const int jj = r % rows_y, kk = r / rows_y;
             const float4 v = *reinterpret_cast<const float4 *>(
-                p + (static_cast<int64_t>(k0 + kk) * d.ny + (j0 + jj)) * d.nx + 4 * c);
+                p + (static_cast<int64_t>(k0 + kk) * d.ny + (j0 + jj)) * d.px + 4 * c);
             if (fabsf(v.x) < d.gamma) sflag[(4 * c) / d.tx] = 1;
             if (fabsf(v.y) < d.gamma) sflag[(4 * c + 1) / d.tx] = 1;
             if (fabsf(v.z) < d.gamma) sflag[(4 * c + 2) / d.tx] = 1;
@@ -225,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void batch_flag_kernel(const float *__restr
         for (int q = threadIdx.x; q < nrows * d.nx; q += kBlock) {
             const int r = q / d.nx, c = q - r * d.nx;
             const int jj = r % rows_y, kk = r / rows_y;
-            const float v = p[(static_cast<int64_t>(k0 + kk) * d.ny + (j0 + jj)) * d.nx + c];
+            const float v = p[(static_cast<int64_t>(k0 + kk) * d.ny + (j0 + jj)) * d.px + c];
             if (fabsf(v) < d.gamma) sflag[c / d.tx] = 1;
         }
     }
@@ -254,8 +264,8 @@ __global__ __launch_bounds__(kBlock) void batch_flag_list_kernel(
         const int tj = r % d.nty, tk = r / d.nty;
         const int x0 = ti * d.tx, y0 = tj * d.ty, z0 = tk * d.tz;
         const int W = min(d.tx, d.nx - x0), H = min(d.ty, d.ny - y0), D = min(d.tz, d.nz - z0);
-        const float *ph = phi + d.offset + (static_cast<int64_t>(z0) * d.ny + y0) * d.nx + x0;
-        const int64_t plane = static_cast<int64_t>(d.ny) * d.nx;
+        const float *ph = phi + d.offset + (static_cast<int64_t>(z0) * d.ny + y0) * d.px + x0;
+        const int64_t plane = static_cast<int64_t>(d.ny) * d.px;
         bool hit = false;
         if (((d.tx & (d.tx - 1)) | (d.ty & (d.ty - 1))) == 0) {
             const int sx = __ffs(d.tx) - 1, sy = __ffs(d.ty) - 1;
@@ -269,7 +279,7 @@ __global__ __launch_bounds__(kBlock) void batch_flag_list_kernel(
                     const int ly = rr & (d.ty - 1), lz = rr >> sy;
                     v[u] = INFINITY;
                     if (q < box && lx < W && ly < H && lz < D)
-                        v[u] = ph[lz * plane + static_cast<int64_t>(ly) * d.nx + lx];
+                        v[u] = ph[lz * plane + static_cast<int64_t>(ly) * d.px + lx];
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) hit |= fabsf(v[u]) < d.gamma;
@@ -278,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void batch_flag_list_kernel(
             for (int q = lane; q < W * H * D; q += 64) {
                 const int lx = q % W, rr = q / W;
                 const int ly = rr % H, lz = rr / H;
-                hit |= fabsf(ph[lz * plane + static_cast<int64_t>(ly) * d.nx + lx]) < d.gamma;
+                hit |= fabsf(ph[lz * plane + static_cast<int64_t>(ly) * d.px + lx]) < d.gamma;
             }
         }
         const bool any = __ballot(hit) != 0;
@@ -412,7 +422,7 @@ __global__ __launch_bounds__(kBlock) void batch_copy_kernel(const float *__restr
             const int lx = q % W, rw = q / W;
             const int ly = rw % H, lz = rw / H;
             const int64_t gi =
-                d.offset + (static_cast<int64_t>(z0 + lz) * d.ny + (y0 + ly)) * d.nx + x0 + lx;
+                d.offset + (static_cast<int64_t>(z0 + lz) * d.ny + (y0 + ly)) * d.px + x0 + lx;
             dst[gi] = src[gi];
         }
     }

@@ -34,7 +34,8 @@ struct BatchInst {
     int32_t vec_ok;          // x rows may be read as 16-byte vectors
     float dx, dt, dtdx, gamma;
     int32_t group;           // tile-shape group of the grid
-    int32_t pad[3];
+    int32_t px;              // elements between consecutive x rows (>= nx)
+    int32_t pad[2];
 };
 static_assert(sizeof(BatchInst) == 96, "BatchInst layout");
 
@@ -189,7 +190,7 @@ __global__ __launch_bounds__((FastCfg<S, FT, TX, TY, TZ, R>::NT)) void upwind_fa
     // uniform description of one item, and the registers its loads fill
     struct Item {
         bool ok;
-        int nx, ny, plane, W, H, D;
+        int nx, px, ny, plane, W, H, D;
         int64_t base;
         C dtdx, dx, dt;
     };
@@ -217,18 +218,20 @@ __global__ __launch_bounds__((FastCfg<S, FT, TX, TY, TZ, R>::NT)) void upwind_fa
         it.dtdx = a.dtdx, it.dx = a.dx, it.dt = a.dt;
         if constexpr (BATCH) {
             const BatchInst &d = a.inst[__builtin_amdgcn_readlane(rv, 7)];
-            it.nx = d.nx, it.ny = d.ny, nz = d.nz, ntx = d.ntx, nty = d.nty, ntiles = d.ntiles;
+            it.nx = d.nx, it.px = d.px, it.ny = d.ny, nz = d.nz, ntx = d.ntx, nty = d.nty;
+            ntiles = d.ntiles;
             goff = d.offset;
             it.dtdx = static_cast<C>(d.dtdx);
             it.dx = static_cast<C>(d.dx);
             it.dt = static_cast<C>(d.dt);
         } else {
-            it.nx = g.nx, it.ny = g.ny, nz = g.nz, ntx = g.ntx, nty = g.nty, ntiles = g.ntiles;
+            it.nx = g.nx, it.px = g.nx, it.ny = g.ny, nz = g.nz, ntx = g.ntx, nty = g.nty;
+            ntiles = g.ntiles;
         }
         it.ok = t0 >= 0 && t0 < ntiles;  // an invalid id is skipped (uniform)
         if (!it.ok) return;
-        const int nx = it.nx, ny = it.ny;
-        const int plane = ny * nx;
+        const int nx = it.nx, px = it.px, ny = it.ny;
+        const int plane = ny * px;
         it.plane = plane;
         const int ti0 = t0 % ntx;
         const int rr = t0 / ntx;
@@ -238,7 +241,7 @@ __global__ __launch_bounds__((FastCfg<S, FT, TX, TY, TZ, R>::NT)) void upwind_fa
         const int H = PARTIAL ? min(TY, ny - y0) : TY;
         const int D = PARTIAL ? min(TZ, nz - z0) : TZ;
         it.W = W, it.H = H, it.D = D;
-        it.base = goff + (static_cast<int64_t>(z0) * ny + y0) * nx + x0;
+        it.base = goff + (static_cast<int64_t>(z0) * ny + y0) * px + x0;
         const S *cur = a.cur + it.base;
         const S *orig = a.orig + it.base;
         const FT *Fb = a.F + it.base;
@@ -246,12 +249,12 @@ __global__ __launch_bounds__((FastCfg<S, FT, TX, TY, TZ, R>::NT)) void upwind_fa
         const int ebits = (y0 == 0 ? 1 : 0) | (y0 + H == ny ? 2 : 0) | (z0 == 0 ? 4 : 0) |
                           (z0 + D == nz ? 8 : 0);
         const bool col_ok = lx < W;
-        const int toff = lz0 * plane + ly0 * nx + lx;
+        const int toff = lz0 * plane + ly0 * px + lx;
 #pragma unroll
         for (int q = 0; q < NOWN; ++q) {
             const bool ok = col_ok && (!PARTIAL || (ly0 + dly(q) < H && lz0 + dlz(q) < D));
             if (ok) {
-                const int u = dlz(q) * plane + dly(q) * nx;  // uniform
+                const int u = dlz(q) * plane + dly(q) * px;  // uniform
                 r.raw[q] = (cur + u)[toff];
                 r.fv[q] = (Fb + u)[toff];
             }
@@ -284,14 +287,14 @@ __global__ __launch_bounds__((FastCfg<S, FT, TX, TY, TZ, R>::NT)) void upwind_fa
             const bool clamp = (ebits >> (face & 3)) & 1;
             const uint32_t mk = zf ? (hi ? m3 : m2) : (hi ? m1 : m0);
             const bool in = clamp || ((mk >> lt) & 1u);
-            const int o = clamp ? (lzc * plane + lyc * nx + lx) : (lz * plane + ly * nx + lx);
+            const int o = clamp ? (lzc * plane + lyc * px + lx) : (lz * plane + ly * px + lx);
             if (ok && in) r.hv[q] = cur[o];
             if (ok && !in) r.hv[q] = orig[o];
         }
         r.xrow_ok = xok && (!PARTIAL || (xly < H && xlz < D));
         const int cx = xside ? (x0 + W < nx ? W : W - 1) : (x0 > 0 ? -1 : 0);
         const bool in = (cx >= 0 && cx < W) || ((mx >> xside) & 1u);
-        const int o = xlz * plane + xly * nx + cx;
+        const int o = xlz * plane + xly * px + cx;
         if (r.xrow_ok && in) r.xv = cur[o];
         if (r.xrow_ok && !in) r.xv = orig[o];
     };
@@ -316,7 +319,7 @@ __global__ __launch_bounds__((FastCfg<S, FT, TX, TY, TZ, R>::NT)) void upwind_fa
     auto update = [&](const Item &it, const Regs &r) {
         if (lx >= it.W) return;
         S *nxt = a.nxt + it.base;
-        const int toff = lz0 * it.plane + ly0 * it.nx + lx;
+        const int toff = lz0 * it.plane + ly0 * it.px + lx;
 #pragma unroll
         for (int q = 0; q < NOWN; ++q) {
             if (PARTIAL && !(ly0 + dly(q) < it.H && lz0 + dlz(q) < it.D)) continue;
@@ -326,7 +329,7 @@ __global__ __launch_bounds__((FastCfg<S, FT, TX, TY, TZ, R>::NT)) void upwind_fa
                                                box[o + SX], box[o - SXY], box[o + SXY], f, it.dx,
                                                it.dt, it.dtdx);
             const S out = (f == C(0)) ? r.raw[q] : Codec<S>::store(v, a.scale);
-            (nxt + dlz(q) * it.plane + dly(q) * it.nx)[toff] = out;
+            (nxt + dlz(q) * it.plane + dly(q) * it.px)[toff] = out;
         }
     };
 

@@ -41,14 +41,18 @@ class ls_tuning(ctypes.Structure):
 
 class ls_instance(ctypes.Structure):
     _fields_ = [("grid", ls_grid), ("offset", ctypes.c_int64), ("dx", ctypes.c_float),
-                ("dt", ctypes.c_float), ("gamma", ctypes.c_float), ("reserved", ctypes.c_int32)]
+                ("dt", ctypes.c_float), ("gamma", ctypes.c_float), ("pitch", ctypes.c_int32)]
 
 
 def instances(items):
-    """ctypes array of ls_instance from (dims, tile, offset, dx, dt, gamma) tuples."""
+    """ctypes array of ls_instance from (dims, tile, offset, dx, dt, gamma[, pitch])
+    tuples (pitch 0 or absent: dense rows)."""
     arr = (ls_instance * len(items))()
-    for k, (dims, tile, offset, dx, dt, gamma) in enumerate(items):
-        arr[k] = ls_instance(grid(dims, tile), int(offset), float(dx), float(dt), float(gamma), 0)
+    for k, it in enumerate(items):
+        dims, tile, offset, dx, dt, gamma = it[:6]
+        pitch = int(it[6]) if len(it) > 6 else 0
+        arr[k] = ls_instance(grid(dims, tile), int(offset), float(dx), float(dt), float(gamma),
+                             pitch)
     return arr
 
 

@@ -18,6 +18,7 @@ import sys
 
 CALIB_KERNEL = "ls::copy_f32_kernel"
 CALIB_BYTES = 1 << 30
+CALIB_DISPATCHES = 3  # the calibration pass: the last three copy dispatches of the run
 
 
 def _rows(db, query):
@@ -63,13 +64,26 @@ def _mean_over(counters, prefix, name):
     return tot / n, int(n)
 
 
+def _calibration(db, counter):
+    """Mean counter value (KiB) of the calibration copies: the last
+    CALIB_DISPATCHES dispatches of the copy kernel (a run may use the same
+    kernel earlier for copies of other sizes)."""
+    rows = _rows(db, "select dispatch_id, kernel_name, counter_name, value "
+                     "from counters_collection")
+    vals = [v for d, k, c, v in sorted(rows)
+            if c == counter and short_name(k).startswith(CALIB_KERNEL)]
+    if len(vals) < CALIB_DISPATCHES:
+        raise KeyError(f"fewer than {CALIB_DISPATCHES} {CALIB_KERNEL} samples of {counter}")
+    return sum(vals[-CALIB_DISPATCHES:]) / CALIB_DISPATCHES
+
+
 def traffic(fetch_db, write_db, prefix):
     """HBM bytes per dispatch of the kernels starting with `prefix` (all their
     variants together), calibrated by the copy kernel."""
     f = kernel_counters(fetch_db)
     w = kernel_counters(write_db)
-    f_cal = f[(CALIB_KERNEL, "FETCH_SIZE")][1] * 1024.0
-    w_cal = w[(CALIB_KERNEL, "WRITE_SIZE")][1] * 1024.0
+    f_cal = _calibration(fetch_db, "FETCH_SIZE") * 1024.0
+    w_cal = _calibration(write_db, "WRITE_SIZE") * 1024.0
     rf, wf = CALIB_BYTES / f_cal, CALIB_BYTES / w_cal
     fm, nf = _mean_over(f, prefix, "FETCH_SIZE")
     wm, nw = _mean_over(w, prefix, "WRITE_SIZE")

@@ -204,6 +204,27 @@ def test_batch_layout_host():
     assert ls.lib().ls_graph_begin(None) == ls.LS_ERR_ARG
 
 
+def test_batch_pitch_host():
+    """Row pitch: a grid spans pitch * ny * nz elements (overlap checks use
+    that span); a pitch below nx is rejected; 0 means dense rows."""
+    dense = ls.instances([((20, 20, 20), (8, 8, 8), 0, 0.05, 0.02, 0.3),
+                          ((20, 20, 20), (8, 8, 8), 8000, 0.05, 0.02, 0.3)])
+    assert ls.ls_batch_layout(dense, 2)[1] == 2 * 27
+    # pitch 32: grid 0 spans 32 * 400 = 12800 elements, so grid 1 at 8000 overlaps
+    over = ls.instances([((20, 20, 20), (8, 8, 8), 0, 0.05, 0.02, 0.3, 32),
+                         ((20, 20, 20), (8, 8, 8), 8000, 0.05, 0.02, 0.3, 32)])
+    with pytest.raises(ls.LsError) as e:
+        ls.ls_batch_layout(over, 2)
+    assert e.value.status == ls.LS_ERR_ARG
+    ok = ls.instances([((20, 20, 20), (8, 8, 8), 0, 0.05, 0.02, 0.3, 32),
+                       ((20, 20, 20), (8, 8, 8), 12800, 0.05, 0.02, 0.3, 32)])
+    assert ls.ls_batch_layout(ok, 2)[1] == 2 * 27
+    small = ls.instances([((20, 20, 20), (8, 8, 8), 0, 0.05, 0.02, 0.3, 19)])
+    with pytest.raises(ls.LsError) as e:
+        ls.ls_batch_layout(small, 1)
+    assert e.value.status == ls.LS_ERR_ARG and "pitch" in str(e.value)
+
+
 def test_closure_parameter_layout_and_cases():
     """The flat parameter vector holds the layers in the documented order and
     the library agrees on its length; closure problems are deterministic and

@@ -1,7 +1,8 @@
 """Batched uneven grids on the GPU.
 
-Every grid of a batch equals the same grid run alone through the single-grid
-driver with its tile shape, bit for bit (phi and band list); one grid is
+Every grid of a batch (rows pitched to 128-byte lines, or dense) equals the
+same grid run alone through the single-grid driver with its tile shape, bit
+for bit (phi and band list); one grid is
 checked against the oracle; a HIP-graph capture of the batch, replayed
 several times with eager work between the replays, reproduces the eager run
 every time.
@@ -34,12 +35,25 @@ def _specs(seed=21, count=10, nmin=20, nmax=72):
     return specs, phis, Fs, rng
 
 
-def test_batch_equals_single_grids():
+@pytest.mark.parametrize("row_align", [32, 1])
+def test_batch_equals_single_grids(row_align):
+    """Pitched rows (128-byte lines, the default) and dense rows."""
     specs, phis, Fs, _ = _specs()
-    b = Batch(specs)
+    b = Batch(specs, row_align=row_align)
     b.load(phis, Fs)
+    # row padding: phi holds a sentinel (a read would change the results),
+    # which must survive the run (no write)
+    pads = []
+    for i, (dims, *_r) in enumerate(specs):
+        nx, ny, nz = dims
+        o, px = b.offsets[i], b.pitches[i]
+        pad = b.phi[o:o + px * ny * nz].view(nz, ny, px)[:, :, nx:]
+        pad.fill_(-7.0)
+        pads.append(pad)
     acc = torch.zeros(1, dtype=torch.int64, device=dev())
     b.run(25, 10, tile_steps=acc)
+    for pad in pads:
+        assert bool((pad == -7.0).all())
     lists = b.band_lists()
     expect_ts = 0
     for i, ((dims, tile, dx, dt, gamma), p, f) in enumerate(zip(specs, phis, Fs)):
