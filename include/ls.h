@@ -275,10 +275,11 @@ int ls_get_tuning(ls_tuning *t);
  * 16; about 2^25 points in all, at most 512 copies) over the shapes the
  * batched step is compiled for: 8x8x8, 16x4x4, 32x4x4, 16x8x8, 4x4x4.  out[i]
  * receives the grid (sizes[i]^3) with the chosen tile.  Results are cached in
- * the text file cache_path (NULL: no cache), keyed by device name and bucket;
- * force != 0 re-measures every bucket asked for.  Unlike every other call,
- * the measurement allocates (and frees) its own device buffers and
- * synchronises its own stream; precision must be 0 (FP32). */
+ * the text file cache_path (NULL: no cache), keyed by device architecture,
+ * compute-unit count and bucket; force != 0 re-measures every bucket asked
+ * for.  Unlike every other call, the measurement allocates (and frees) its
+ * own device buffers and synchronises its own stream; precision must be 0
+ * (FP32). */
 int ls_autotune(const int32_t *sizes, int n, int precision, const char *cache_path, ls_grid *out,
                 int force);
 
@@ -391,13 +392,26 @@ int ls_adam_step(float *params, const float *grad, float *m, float *v, int64_t n
 /* The corrected narrow-band driver: per window of `window` steps, A and U are
  * built from the current phi, then every step is the plain step on U plus the
  * correction on A (with the per-tile fallback).  *fallbacks_dev (int32,
- * caller-zeroed) accumulates the fallback count.  On return phi holds the
- * result; the band list of the last window is in tiles / ntiles_dev. */
+ * caller-zeroed) accumulates the fallback count.
+ *
+ * judge != 0 makes the plain scheme the judge of the corrected run's
+ * interface: a shadow copy of the initial phi (in the closure workspace) is
+ * advanced by the plain narrow-band driver (ls_band_run_f32) window by window
+ * beside the corrected run, and after every window each 8^3 tile whose
+ * zero-crossing state (whether it holds points of both signs, phi < 0 and
+ * phi >= 0) differs between the corrected field and the shadow takes the
+ * shadow's values.  A correction may so move the interface but not create,
+ * remove, split or merge a piece of it inside a tile against the plain run.
+ * *resets_dev (int32, caller-zeroed; required when judging) accumulates the
+ * number of tiles reset.  judge == 0: no shadow run (resets_dev may be NULL).
+ *
+ * On return phi holds the result; the band list of the corrected run's last
+ * window is in tiles / ntiles_dev. */
 int ls_closure_run_f32(float *phi, const float *F, const ls_grid *g, float dx, float dt,
                        float gamma, float fmax, const float *params, int nsteps, int window,
-                       int32_t *tiles, int64_t capacity, int32_t *ntiles_dev,
-                       int32_t *fallbacks_dev, void *ws, int64_t ws_bytes, void *cws,
-                       int64_t cws_bytes, void *stream);
+                       int judge, int32_t *tiles, int64_t capacity, int32_t *ntiles_dev,
+                       int32_t *fallbacks_dev, int32_t *resets_dev, void *ws, int64_t ws_bytes,
+                       void *cws, int64_t cws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -26,6 +26,11 @@ Conventions (readings of a spec addition; the paper has no network):
                exceeds 1/2 in magnitude falls back to the plain step.
   loss         mean over active points of (phi_pred - phi_target)^2 / dx_c^2
                = mean (c r - r*)^2 with r* = (phi_target - phi - delta_plain)/dx_c.
+  judge        the plain scheme judges the corrected run: a shadow plain run
+               advances beside it, and after every window each tile whose
+               zero-crossing state (points of both signs, phi < 0 and
+               phi >= 0, present or not) differs from the shadow's takes the
+               shadow's values.
 """
 import numpy as np
 
@@ -189,3 +194,35 @@ def closure_step(params, phi_c, F_c, dx, dt, gamma, fmax, band, active, tile=(8,
         lim = 0.5 * np.abs(delta[sl])
         out[sl] += np.clip(dx * rt, -lim, lim)
     return out, fallbacks
+
+
+def crossing_tiles(phi, tile=(8, 8, 8)):
+    """Boolean per tile (tile id order, x fastest): the tile holds a point with
+    phi < 0 and a point with phi >= 0 (NaN counts as not negative)."""
+    nz, ny, nx = phi.shape
+    tx, ty, tz = tile
+    ntx, nty, ntz = -(-nx // tx), -(-ny // ty), -(-nz // tz)
+    out = np.zeros(ntx * nty * ntz, bool)
+    for t in range(out.size):
+        ti, tj, tk = t % ntx, (t // ntx) % nty, t // (ntx * nty)
+        blk = phi[tk * tz:(tk + 1) * tz, tj * ty:(tj + 1) * ty, ti * tx:(ti + 1) * tx]
+        neg = blk < 0
+        out[t] = bool(neg.any()) and bool((~neg).any())
+    return out
+
+
+def judge(phi, shadow, tile=(8, 8, 8)):
+    """The judge after a window: (phi with every tile whose crossing state
+    differs from the shadow's replaced by the shadow's values, the number of
+    such tiles)."""
+    out = np.array(phi, copy=True)
+    bad = np.flatnonzero(crossing_tiles(phi, tile) != crossing_tiles(shadow, tile))
+    nz, ny, nx = phi.shape
+    tx, ty, tz = tile
+    ntx, nty = -(-nx // tx), -(-ny // ty)
+    for t in bad:
+        ti, tj, tk = t % ntx, (t // ntx) % nty, t // (ntx * nty)
+        sl = (slice(tk * tz, (tk + 1) * tz), slice(tj * ty, (tj + 1) * ty),
+              slice(ti * tx, (ti + 1) * tx))
+        out[sl] = shadow[sl]
+    return out, int(bad.size)

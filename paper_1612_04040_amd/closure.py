@@ -67,6 +67,7 @@ class ClosureGrid:
         self.grad = torch.zeros(NPARAMS, dtype=torch.float32, device=self.device)
         self.loss = torch.zeros(1, dtype=torch.float32, device=self.device)
         self.fallbacks = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.resets = torch.zeros(1, dtype=torch.int32, device=self.device)
 
     def _band(self):
         b = self.bg
@@ -83,11 +84,15 @@ class ClosureGrid:
         ls.ls_closure_backward_f32(phi, target, F, self.g, dx, dt, gamma, fmax, params, self.grad,
                                    self.loss, t, cap, n, ws, wsb, self.cws, self.cws_bytes, stream)
 
-    def run(self, phi, F, dx, dt, gamma, fmax, params, nsteps, window=10, stream=None):
-        """Corrected narrow-band run; self.fallbacks accumulates (zero it first)."""
+    def run(self, phi, F, dx, dt, gamma, fmax, params, nsteps, window=10, judge=True,
+            stream=None):
+        """Corrected narrow-band run, judged by a plain shadow run unless
+        judge=False; self.fallbacks and self.resets accumulate (zero them
+        first)."""
         t, cap, n, ws, wsb = self._band()
-        ls.ls_closure_run_f32(phi, F, self.g, dx, dt, gamma, fmax, params, nsteps, window, t, cap,
-                              n, self.fallbacks, ws, wsb, self.cws, self.cws_bytes, stream)
+        ls.ls_closure_run_f32(phi, F, self.g, dx, dt, gamma, fmax, params, nsteps, window, judge,
+                              t, cap, n, self.fallbacks, self.resets, ws, wsb, self.cws,
+                              self.cws_bytes, stream)
 
     def band_list(self):
         return self.bg.band_list()

@@ -9,7 +9,7 @@
 // points of the same band).
 //
 // Results are cached in a text file, one line per (device, bucket):
-//   <device name>|<bucket> <tx> <ty> <tz> <ms per window>
+//   <architecture> <compute units>cu|<bucket> <tx> <ty> <tz> <ms per window>
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -192,7 +192,10 @@ int ls_autotune(const int32_t *sizes, int n, int precision, const char *cache_pa
     LS_HIP_CHECK(hipGetDevice(&dev));
     hipDeviceProp_t prop;
     LS_HIP_CHECK(hipGetDeviceProperties(&prop, dev));
-    std::string dname(prop.name);
+    // the key names the architecture and the compute-unit count (the
+    // marketing name can be empty, e.g. under a profiler)
+    std::string dname = std::string(prop.gcnArchName) + " " +
+                        std::to_string(prop.multiProcessorCount) + "cu";
     for (char &ch : dname)
         if (ch == '|' || ch == '\n') ch = ' ';
     std::map<std::string, ls::TuneEntry> cache;

@@ -740,6 +740,31 @@ __global__ void adam_kernel(float *__restrict__ w, const float *__restrict__ gra
     }
 }
 
+// The plain scheme as judge of the corrected run's interface: every 8^3 tile
+// whose zero-crossing state (holding points of both signs, phi < 0 and
+// phi >= 0, or not) differs between the corrected field x and the plain
+// shadow field p takes p's values; *resets counts those tiles.  One block of
+// 512 threads per tile (a point per thread), grid-stride over the tiles.
+__global__ __launch_bounds__(512) void closure_judge_kernel(float *__restrict__ x,
+                                                            const float *__restrict__ p, int nx,
+                                                            int ny, int ntx, int nty, int ntiles,
+                                                            int32_t *resets) {
+    const int lx = threadIdx.x & 7, ly = (threadIdx.x >> 3) & 7, lz = threadIdx.x >> 6;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int ti = t % ntx, r = t / ntx;
+        const int tj = r % nty, tk = r / nty;
+        const int64_t i =
+            (static_cast<int64_t>(tk * 8 + lz) * ny + (tj * 8 + ly)) * nx + ti * 8 + lx;
+        const float xv = x[i], pv = p[i];
+        const int xneg = __syncthreads_or(xv < 0.f), xpos = __syncthreads_or(!(xv < 0.f));
+        const int pneg = __syncthreads_or(pv < 0.f), ppos = __syncthreads_or(!(pv < 0.f));
+        if ((xneg && xpos) != (pneg && ppos)) {  // uniform over the block
+            x[i] = pv;
+            if (threadIdx.x == 0) atomicAdd(resets, 1);
+        }
+    }
+}
+
 __global__ void zero_f32_kernel(float *p, int64_t n) {
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x)
@@ -768,7 +793,8 @@ struct ClosureWs {
     int64_t wp0, wp1, wp2, bp1, bp2;
     int64_t a0, z0, a1, z1, ga;
     int64_t r, gr, plain;
-    int64_t active, counters;  // counters: [0] active count, [1] fallbacks (scratch)
+    int64_t shadow, shadow_scratch;  // the judge's plain run
+    int64_t active, counters;  // counters: [0] active count, [1] fallbacks (scratch), [2] resets
     int64_t partial, tile_loss;
     int64_t total;
 };
@@ -791,6 +817,8 @@ static ClosureWs closure_ws(const Geom &g) {
     w.r = o; o = al(o + 4 * N);
     w.gr = o; o = al(o + 4 * N);
     w.plain = o; o = al(o + 4 * N);
+    w.shadow = o; o = al(o + 4 * N);
+    w.shadow_scratch = o; o = al(o + 4 * N);
     w.active = o; o = al(o + 4 * T);
     w.counters = o; o = al(o + 4 * 64);
     w.partial = o; o = al(o + 4 * kPart * T);
@@ -1164,15 +1192,15 @@ int ls_adam_step(float *params, const float *grad, float *m, float *v, int64_t n
 
 int ls_closure_run_f32(float *phi, const float *F, const ls_grid *g, float dx, float dt,
                        float gamma, float fmax, const float *params, int nsteps, int window,
-                       int32_t *tiles, int64_t capacity, int32_t *ntiles_dev,
-                       int32_t *fallbacks_dev, void *ws, int64_t ws_bytes, void *cws,
-                       int64_t cws_bytes, void *stream) {
+                       int judge, int32_t *tiles, int64_t capacity, int32_t *ntiles_dev,
+                       int32_t *fallbacks_dev, int32_t *resets_dev, void *ws, int64_t ws_bytes,
+                       void *cws, int64_t cws_bytes, void *stream) {
     ls::clear_error();
     ls::ClosureCall c;
     int rc = ls::closure_setup(g, dx, dt, gamma, fmax, params, ws, ws_bytes, cws, cws_bytes,
                                stream, &c);
     if (rc != LS_OK) return rc;
-    if (!phi || !F || !tiles || !ntiles_dev || !fallbacks_dev) {
+    if (!phi || !F || !tiles || !ntiles_dev || !fallbacks_dev || (judge && !resets_dev)) {
         ls::set_error("closure run: NULL argument");
         return LS_ERR_ARG;
     }
@@ -1186,21 +1214,42 @@ int ls_closure_run_f32(float *phi, const float *F, const ls_grid *g, float dx, f
         return LS_ERR_CAPACITY;
     }
     if ((rc = ls::pack_all(c, params)) != LS_OK) return rc;
+    float *shadow = ls::at<float>(c, c.w.shadow);
+    float *shadow_scratch = ls::at<float>(c, c.w.shadow_scratch);
+    if (judge && (rc = ls_copy_f32(shadow, phi, c.G.npoints, c.s)) != LS_OK) return rc;
     // ping-pong between phi and a closure buffer; within a window the points
     // outside the band are equal in both (one dense copy per window)
     float *buf[2] = {phi, ls::at<float>(c, c.w.plain)};
     int cur = 0;
-    for (int s = 0; s < nsteps; ++s) {
-        const bool first = s % window == 0;
-        if (first && (rc = ls::closure_bands(c, buf[cur], g, gamma, tiles, capacity, ntiles_dev,
-                                             ws_bytes)) != LS_OK)
-            return rc;
-        float *x = buf[cur], *y = buf[cur ^ 1];
-        if ((rc = ls::closure_plain(c, x, y, F, dx, dt, first)) != LS_OK) return rc;
-        if ((rc = ls::closure_fused(c, x, F, y, dx, gamma, fmax, params, nullptr, y,
-                                    fallbacks_dev)) != LS_OK)
-            return rc;
-        cur ^= 1;
+    for (int s0 = 0; s0 < nsteps; s0 += window) {
+        const int k = std::min(window, nsteps - s0);
+        if (judge) {
+            // the shadow window first: its band build uses tiles and ws, which
+            // the corrected window then rebuilds from its own field
+            if ((rc = ls_band_run_f32(shadow, F, g, dx, dt, gamma, k, k, tiles, capacity,
+                                      ntiles_dev, nullptr, shadow_scratch, ws, ws_bytes, c.s)) !=
+                LS_OK)
+                return rc;
+        }
+        for (int s = 0; s < k; ++s) {
+            const bool first = s == 0;
+            if (first && (rc = ls::closure_bands(c, buf[cur], g, gamma, tiles, capacity,
+                                                 ntiles_dev, ws_bytes)) != LS_OK)
+                return rc;
+            float *x = buf[cur], *y = buf[cur ^ 1];
+            if ((rc = ls::closure_plain(c, x, y, F, dx, dt, first)) != LS_OK) return rc;
+            if ((rc = ls::closure_fused(c, x, F, y, dx, gamma, fmax, params, nullptr, y,
+                                        fallbacks_dev)) != LS_OK)
+                return rc;
+            cur ^= 1;
+        }
+        if (judge) {
+            const unsigned jb = static_cast<unsigned>(std::min<int64_t>(c.G.ntiles, 4096));
+            hipLaunchKernelGGL(ls::closure_judge_kernel, dim3(jb), dim3(512), 0, c.s, buf[cur],
+                               static_cast<const float *>(shadow), c.G.nx, c.G.ny, c.G.ntx,
+                               c.G.nty, static_cast<int>(c.G.ntiles), resets_dev);
+            LS_LAUNCH_CHECK("closure_judge_kernel");
+        }
     }
     if (cur == 1 && (rc = ls_copy_f32(phi, buf[1], c.G.npoints, c.s)) != LS_OK) return rc;
     return LS_OK;

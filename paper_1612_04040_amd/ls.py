@@ -118,8 +118,8 @@ _SIGNATURES = {
     "ls_closure_backward_f32": (_I32, [_VP, _VP, _VP, _G, _F32, _F32, _F32, _F32, _VP, _VP, _VP,
                                        _VP, _I64, _VP, _VP, _I64, _VP, _I64, _VP]),
     "ls_adam_step": (_I32, [_VP, _VP, _VP, _VP, _I64, _F32, _F32, _F32, _F32, _I32, _VP]),
-    "ls_closure_run_f32": (_I32, [_VP, _VP, _G, _F32, _F32, _F32, _F32, _VP, _I32, _I32, _VP,
-                                  _I64, _VP, _VP, _VP, _I64, _VP, _I64, _VP]),
+    "ls_closure_run_f32": (_I32, [_VP, _VP, _G, _F32, _F32, _F32, _F32, _VP, _I32, _I32, _I32,
+                                  _VP, _I64, _VP, _VP, _VP, _VP, _I64, _VP, _I64, _VP]),
 }
 
 LS_KERNEL_UPWIND = 0
@@ -406,12 +406,13 @@ def ls_adam_step(params, grad, m, v, n, lr, beta1, beta2, eps, t, stream=None):
                                      beta1, beta2, eps, int(t), _stream(stream)))
 
 
-def ls_closure_run_f32(phi, F, g, dx, dt, gamma, fmax, params, nsteps, window, tiles, capacity,
-                       ntiles_dev, fallbacks_dev, ws, ws_bytes, cws, cws_bytes, stream=None):
+def ls_closure_run_f32(phi, F, g, dx, dt, gamma, fmax, params, nsteps, window, judge, tiles,
+                       capacity, ntiles_dev, fallbacks_dev, resets_dev, ws, ws_bytes, cws,
+                       cws_bytes, stream=None):
     return _check(lib().ls_closure_run_f32(
         _ptr(phi), _ptr(F), _g(g), dx, dt, gamma, fmax, _ptr(params), int(nsteps), int(window),
-        _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(fallbacks_dev), _ptr(ws), ws_bytes,
-        _ptr(cws), cws_bytes, _stream(stream)))
+        1 if judge else 0, _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(fallbacks_dev),
+        _ptr(resets_dev), _ptr(ws), ws_bytes, _ptr(cws), cws_bytes, _stream(stream)))
 
 
 def ls_autotune(sizes, cache_path=None, force=False, precision=0):

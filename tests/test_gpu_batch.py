@@ -138,3 +138,13 @@ def test_native_autotuner_and_cache(tmp_path):
         lines = [ln for ln in fh.read().splitlines() if ln.strip()]
     assert len(lines) == 2
     assert autotune.tune([40, 72], path=path) == table
+    # an entry planted for this device is returned as it is, unmeasured: the
+    # key read back matches the key written (architecture and CU count)
+    key = lines[0].split("|")[0]
+    prop = torch.cuda.get_device_properties(0)
+    assert key == f"{prop.gcnArchName} {prop.multi_processor_count}cu"
+    with open(path, "w") as fh:
+        fh.write(f"{key}|1 32 4 4 0.0001\n{key}|2 4 4 4 0.0001\n")
+    assert autotune.tune([40, 72], path=path) == {1: (32, 4, 4), 2: (4, 4, 4)}
+    with open(path) as fh:  # nothing re-measured, nothing rewritten
+        assert fh.read() == f"{key}|1 32 4 4 0.0001\n{key}|2 4 4 4 0.0001\n"

@@ -149,13 +149,15 @@ def test_zero_last_layer_is_the_plain_driver():
     cg = C.ClosureGrid(wl.phi.shape[::-1])
     pd, Fd = to_dev(wl.phi), to_dev(wl.F)
     cg.fallbacks.zero_()
-    cg.run(pd, Fd, wl.dx, wl.dt, wl.gamma, fmax, to_dev(params), 25, 10)
+    cg.resets.zero_()
+    cg.run(pd, Fd, wl.dx, wl.dt, wl.gamma, fmax, to_dev(params), 25, 10)  # judged
     bg = BandGrid(wl.phi.shape[::-1], TILE, "f32")
     pp = to_dev(wl.phi)
     bg.run(pp, Fd, wl.dx, wl.dt, wl.gamma, 25, 10)
     a, b = host(pd), host(pp)
     assert np.array_equal(a, b)  # value equality: -0.0 == 0.0
     assert int(host(cg.fallbacks)[0]) == 0
+    assert int(host(cg.resets)[0]) == 0  # the plain judge agrees with itself
     assert cg.band_list().tolist() == bg.band_list().tolist()
 
 
@@ -176,13 +178,13 @@ def test_fallback_and_constant_correction():
     p["b2"][:] = 1e6  # gated correction above 1/2 wherever c > 5e-7: every active tile
     pd = to_dev(wl.phi)
     cg.fallbacks.zero_()
-    cg.run(pd, Fd, wl.dx, wl.dt, wl.gamma, fmax, to_dev(C.flatten(p)), 1, 10)
+    cg.run(pd, Fd, wl.dx, wl.dt, wl.gamma, fmax, to_dev(C.flatten(p)), 1, 10, judge=False)
     assert int(host(cg.fallbacks)[0]) == len(active)
     assert np.array_equal(host(pd), plain)
     p["b2"][:] = 0.25  # accepted everywhere: plain + dx c(phi) / 4 on the active tiles
     pd = to_dev(wl.phi)
     cg.fallbacks.zero_()
-    cg.run(pd, Fd, wl.dx, wl.dt, wl.gamma, fmax, to_dev(C.flatten(p)), 1, 10)
+    cg.run(pd, Fd, wl.dx, wl.dt, wl.gamma, fmax, to_dev(C.flatten(p)), 1, 10, judge=False)
     assert int(host(cg.fallbacks)[0]) == 0
     got = host(pd).astype(np.float64)
     lim = 0.5 * np.abs(plain.astype(np.float64) - wl.phi.astype(np.float64))
@@ -206,7 +208,8 @@ def test_multistep_run_matches_reference():
     pd = to_dev(wl.phi)
     cg.fallbacks.zero_()
     nsteps, window = 12, 5
-    cg.run(pd, to_dev(wl.F), wl.dx, wl.dt, wl.gamma, fmax, to_dev(params), nsteps, window)
+    cg.run(pd, to_dev(wl.F), wl.dx, wl.dt, wl.gamma, fmax, to_dev(params), nsteps, window,
+           judge=False)
     got = host(pd).astype(np.float64)
     phi = wl.phi.astype(np.float64)
     total_fb = 0
@@ -250,3 +253,68 @@ def test_restrict4_matches_reference():
     want = CL.restrict4(fine.astype(np.float64))
     assert got.shape == (8, 6, 10)
     assert np.max(np.abs(got - want)) <= 4 * np.finfo(np.float32).eps * np.max(np.abs(fine))
+
+
+def test_judge_resets_a_bubble_the_plain_run_removes():
+    """A sphere of radius 3.5 dx shrinking at F = -1 (32^3): the plain scheme
+    removes it within 6 steps; a constant correction r = -1/2 (accepted, the
+    limiter halving the plain increment) keeps it alive past step 8.  With
+    the judge (windows of 4 steps) the corrected run's bubble tile takes the
+    plain run's values after the second window, the only reset; every other
+    point keeps the unjudged corrected value.  The whole judged run matches
+    the FP64 reference (oracle corrected steps, oracle plain shadow, oracle
+    judge per window)."""
+    n = 32
+    dx = 1.0 / n
+    dt = float(np.float32(0.5 * dx))
+    phi0 = W.sphere((n, n, n), dx, (12.5 * dx,) * 3, 3.5 * dx, dtype=np.float32)
+    F = np.full((n, n, n), -1.0, np.float32)
+    gamma = float(np.float32(6 * dx))
+    p = C.unflatten(C.init_params(np.random.default_rng(1)))
+    p["b2"][:] = -0.5
+    params = to_dev(C.flatten(p))
+    Fd = to_dev(F)
+    cg = C.ClosureGrid((n, n, n))
+    runs = {}
+    for judge in (False, True):
+        pd = to_dev(phi0)
+        cg.fallbacks.zero_()
+        cg.resets.zero_()
+        cg.run(pd, Fd, dx, dt, gamma, 1.0, params, 8, 4, judge=judge)
+        runs[judge] = host(pd)
+        assert int(host(cg.fallbacks)[0]) == 0
+    resets = int(host(cg.resets)[0])
+    bg = BandGrid((n, n, n), TILE, "f32")
+    pp = to_dev(phi0)
+    bg.run(pp, Fd, dx, dt, gamma, 8, 4)
+    plain = host(pp)
+    tile = (slice(8, 16),) * 3
+    assert plain.min() > 0 and runs[False][tile].min() < 0  # the premise
+    assert resets == 1
+    assert np.array_equal(runs[True][tile], plain[tile])
+    rest = np.ones(phi0.shape, bool)
+    rest[tile] = False
+    assert np.array_equal(runs[True][rest], runs[False][rest])
+
+    # the FP64 reference of the judged run
+    pr = {k: bf16(v.astype(np.float32)) for k, v in C.unflatten(C.flatten(p)).items()}
+    for k in ("b0", "b1", "b2"):
+        pr[k] = C.unflatten(C.flatten(p))[k].astype(np.float32).astype(np.float64)
+    x = phi0.astype(np.float64)
+    shadow = x.copy()
+    total = 0
+    g32 = np.float32(gamma)
+    for w in range(2):
+        shadow = oracle.run_band(shadow, F, dx, dt, g32, 4, window=4)
+        for s in range(4):
+            if s == 0:
+                band = oracle.band_tiles(x.astype(np.float32), TILE, g32, True)
+                active = oracle.band_tiles(x.astype(np.float32), TILE, g32, False)
+            x, fb = CL.closure_step(pr, x, F, dx, dt, g32, np.float32(1.0), band, active)
+            assert fb == 0
+        x, k = CL.judge(x, shadow)
+        total += k
+    assert total == resets
+    err = np.max(np.abs(runs[True].astype(np.float64) - x))
+    report("closure_judge", max_err_dx=float(err / dx), resets=resets)
+    assert err <= 1e-3 * dx, err / dx

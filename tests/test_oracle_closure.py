@@ -149,3 +149,32 @@ def test_adam_first_step_is_signed_lr():
     before = params["w"].copy()
     CL.adam_step(params, grads, {}, lr=1e-3)
     assert np.allclose(params["w"] - before, -1e-3 * np.sign(grads["w"]), rtol=1e-4)
+
+
+def test_judge_resets_tiles_whose_crossing_state_differs():
+    """Hand-built 16^3 fields (8 tiles): a bubble only in phi (reset), a
+    crossing only in the shadow (reset), a crossing in both at other places
+    (kept), a sign-only difference without crossings (kept: all-negative
+    versus all-negative with other values), a NaN tile (NaN is not negative)."""
+    rng = np.random.default_rng(0)
+    phi = rng.uniform(1, 2, (16, 16, 16))
+    shadow = rng.uniform(1, 2, (16, 16, 16))
+    phi[2, 2, 2] = -0.5                      # tile 0: bubble in phi only
+    shadow[3, 3, 12] = -0.1                  # tile 1: crossing in the shadow only
+    phi[4, 12, 1] = -1.0                     # tile 2: crossings in both
+    shadow[6, 9, 5] = -3.0
+    phi[8:, :8, :8] = -1.0                   # tile 4: all negative in both
+    shadow[8:, :8, :8] = -2.0
+    phi[12, 12, 12] = np.nan                 # tile 7: NaN among positives, no crossing
+    assert CL.crossing_tiles(phi).tolist() == [True, False, True, False, False, False, False,
+                                               False]
+    out, n = CL.judge(phi, shadow)
+    assert n == 2
+    reset = np.zeros(phi.shape, bool)
+    reset[:8, :8, :8] = True
+    reset[:8, :8, 8:] = True
+    assert np.array_equal(out[reset], shadow[reset])
+    keep = ~reset
+    assert np.array_equal(out[keep], phi[keep], equal_nan=True)
+    # identical fields: nothing to reset
+    assert CL.judge(shadow, shadow)[1] == 0
