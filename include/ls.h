@@ -264,6 +264,9 @@ typedef struct ls_tuning {
                          1 off, 2 on */
     int32_t vector;   /* 0 auto (FP32 and FP16s, 8x8x8 tiles, nx a multiple of
                          4, aligned buffers: the vectorised kernel), 1 off */
+    int32_t temporal; /* 0 off (default), 1 on: two steps per launch where the
+                         vectorised kernel runs on grids of whole tiles in y
+                         and z (bit-identical; measured slower) */
 } ls_tuning;
 int ls_set_tuning(const ls_tuning *t);
 int ls_get_tuning(ls_tuning *t);

@@ -90,6 +90,7 @@ struct StepArgs {
     const int32_t *nitems;    // number of records (device)
     const int32_t *range;     // batch: [first, end) records of this launch (device), else null
     const BatchInst *inst;    // batch: grid descriptors (record word 7 = grid), else null
+    const uint8_t *umap;      // single grid: U membership per tile (two-step kernel), else null
     typename Codec<S>::C dx, dt, dtdx, scale;
 };
 
@@ -556,6 +557,259 @@ __global__ __launch_bounds__((VecCfg<TY, TZ, R>::NT)) void upwind_vec_kernel(
             }
         }
         __syncthreads();  // box free for the next item
+    }
+}
+
+// Two steps per launch (temporal blocking) of the vectorised band step, for
+// 8x8x8 tiles on grids whose y and z extents are whole tiles and nx a
+// multiple of 4.  A work item loads its points with a halo two points deep
+// (the y/z rows at distance 1 and 2, the four yz-edge rows, and 4-point x
+// ends of its own and ring rows), computes the first step on its points and
+// on the ring one point outside them (a ring point outside U keeps its
+// value, as it would with one step per launch), then the second step on its
+// points from those.  Every value is computed from the same inputs and with
+// the same arithmetic as with two one-step launches (an intermediate FP16
+// value is rounded to storage as it would be stored), so the result is
+// bit-identical; the item moves its own points once per two steps.  (A
+// tuning option: on the bench grids it runs slower than two one-step
+// launches.)
+// Membership of a halo point's tile in U (read from cur, else frozen in orig)
+// comes from the U map.  A neighbour outside the grid is the point itself
+// (zero-gradient boundary).
+template <int R>
+struct Vec2Cfg {
+    static constexpr int TX = 8, TY = 8, TZ = 8, V = 4;
+    static constexpr int XP = R * TX;          // own points per item row
+    static constexpr int XV = XP / V;          // lanes per item row
+    static constexpr int NT = XP >= 64 ? 2 * kBlock : kBlock;
+    static constexpr int RP = NT / XV;         // item rows per pass
+    static constexpr int ROWS = TY * TZ;       // own rows
+    static constexpr int NOWN = ROWS / RP;
+    static constexpr int NHR = 4 * TZ + 4 * TY + 4;  // distance-1/2 y and z rows, yz-edge rows
+    static constexpr int NHP = (NHR + RP - 1) / RP;
+    static constexpr int NRING = 2 * TZ + 2 * TY;    // ring rows (distance 1)
+    static constexpr int NXH = 2 * (ROWS + NRING);   // 4-point x ends of own and ring rows
+    static constexpr int NXR = 2 * ROWS;             // x-ring points
+    static constexpr int PAD = 4;
+    static constexpr int SX = XP + 2 * PAD;
+    static constexpr int SXY0 = SX * (TY + 4), SXY1 = SX * (TY + 2);
+    static constexpr int B0 = SXY0 * (TZ + 4), B1 = SXY1 * (TZ + 2);
+    static constexpr size_t lds = sizeof(float) * (B0 + B1);
+    static_assert(ROWS % RP == 0 && NRING <= RP, "rows do not tile the block");
+    static_assert(NXH <= NT && NXR <= NT, "x ends exceed one per thread");
+};
+
+// (ly, lz) of halo row h: y rows at ly = -2, -1, 8, 9 for every lz, then z
+// rows at lz = -2, -1, 8, 9 for every ly, then the four yz-edge rows.
+__device__ inline void vec2_halo_row(int h, int *ly, int *lz) {
+    if (h < 32) {
+        const int k = h & 3;
+        *lz = h >> 2;
+        *ly = k < 2 ? k - 2 : k + 6;
+    } else if (h < 64) {
+        const int k = h & 3;
+        *ly = (h - 32) >> 2;
+        *lz = k < 2 ? k - 2 : k + 6;
+    } else {
+        const int k = h - 64;
+        *ly = (k & 1) ? 8 : -1;
+        *lz = (k & 2) ? 8 : -1;
+    }
+}
+
+// (ly, lz) of ring row h: y rows at ly = -1, 8 for every lz, then z rows at
+// lz = -1, 8 for every ly.
+__device__ inline void vec2_ring_row(int h, int *ly, int *lz) {
+    if (h < 16) {
+        *lz = h >> 1;
+        *ly = (h & 1) ? 8 : -1;
+    } else {
+        *ly = (h - 16) >> 1;
+        *lz = (h & 1) ? 8 : -1;
+    }
+}
+
+template <class S, int R>
+__global__ __launch_bounds__((Vec2Cfg<R>::NT)) void upwind_vec2_kernel(StepGeom g,
+                                                                      StepArgs<S, float> a) {
+    using K = Vec2Cfg<R>;
+    using VS = Vec4<S>;
+    using VT = typename VS::T;
+    constexpr int RP = K::RP, NOWN = K::NOWN, NHP = K::NHP, XV = K::XV;
+    constexpr int SX = K::SX, SXY0 = K::SXY0, SXY1 = K::SXY1, PAD = K::PAD;
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *box0 = reinterpret_cast<float *>(smem);  // step-n values, y/z in [-2, 9]
+    float *box1 = box0 + K::B0;                     // step-n+1 values, y/z in [-1, 8]
+
+    int w0, w1;
+    block_slice(0, *a.nitems, &w0, &w1);
+    const int lane = threadIdx.x & 63;
+    const int lx = (threadIdx.x % XV) * 4;
+    const int lr = threadIdx.x / XV;
+    const int nx = g.nx, ny = g.ny, nz = g.nz, plane = ny * nx;
+    const int ntx = g.ntx, nty = g.nty;
+    const float sc = a.scale;
+    auto o0 = [](int x, int y, int z) { return (z + 2) * SXY0 + (y + 2) * SX + PAD + x; };
+    auto o1 = [](int x, int y, int z) { return (z + 1) * SXY1 + (y + 1) * SX + PAD + x; };
+    auto decode = [&](const VT &v) {
+        return make_float4(Codec<S>::load(VS::get(v, 0), sc), Codec<S>::load(VS::get(v, 1), sc),
+                           Codec<S>::load(VS::get(v, 2), sc), Codec<S>::load(VS::get(v, 3), sc));
+    };
+    // the value a one-step launch would store and the next one load
+    auto stored = [&](float v) { return Codec<S>::load(Codec<S>::store(v, sc), sc); };
+    auto in_u = [&](int gx, int gy, int gz) {
+        return a.umap[(static_cast<int64_t>(gz >> 3) * nty + (gy >> 3)) * ntx + (gx >> 3)] != 0;
+    };
+
+    for (int w = w0; w < w1; ++w) {
+        int rv = 0;
+        if (lane < kItemWords) rv = a.rec[static_cast<int64_t>(w) * kItemWords + lane];
+        const int t0 = __builtin_amdgcn_readlane(rv, 0);
+        const int len = __builtin_amdgcn_readlane(rv, 1);
+        if (t0 < 0 || t0 >= g.ntiles) continue;  // uniform
+        const int ti0 = t0 % ntx, rr = t0 / ntx;
+        const int tj = rr % nty, tk = rr / nty;
+        const int x0 = ti0 * 8, y0 = tj * 8, z0 = tk * 8;
+        const int W = min(len * 8, nx - x0);  // a multiple of 4
+        const int64_t base = (static_cast<int64_t>(z0) * ny + y0) * nx + x0;
+        const S *cur = a.cur + base;
+        const S *orig = a.orig + base;
+        const float *Fb = a.F + base;
+        S *nxt = a.nxt + base;
+        const bool col_ok = lx < W;
+        auto off = [&](int x, int y, int z) { return z * plane + y * nx + x; };
+        auto inside = [&](int x, int y, int z) {
+            return x0 + x >= 0 && x0 + x < nx && y0 + y >= 0 && y0 + y < ny && z0 + z >= 0 &&
+                   z0 + z < nz;
+        };
+
+        // (1) global loads
+        VT raw[NOWN];
+        float4 fv[NOWN];
+#pragma unroll
+        for (int q = 0; q < NOWN; ++q) {
+            const int row = lr + q * RP, ly = row & 7, lz = row >> 3;
+            if (col_ok) {
+                raw[q] = *reinterpret_cast<const VT *>(cur + off(lx, ly, lz));
+                fv[q] = *reinterpret_cast<const float4 *>(Fb + off(lx, ly, lz));
+            }
+        }
+        VT hv[NHP];
+        bool hok[NHP];
+        int hslot[NHP];
+#pragma unroll
+        for (int q = 0; q < NHP; ++q) {
+            const int h = lr + q * RP;
+            int ly = 0, lz = 0;
+            if (h < K::NHR) vec2_halo_row(h, &ly, &lz);
+            hok[q] = h < K::NHR && col_ok && inside(lx, ly, lz);
+            hslot[q] = o0(lx, ly, lz);
+            if (hok[q]) {
+                const bool u = in_u(x0 + lx, y0 + ly, z0 + lz);
+                hv[q] = *reinterpret_cast<const VT *>((u ? cur : orig) + off(lx, ly, lz));
+            }
+        }
+        // ring rows: F of their points (their first step is computed by this thread)
+        int rly = 0, rlz = 0;
+        if (lr < K::NRING) vec2_ring_row(lr, &rly, &rlz);
+        const bool rok = lr < K::NRING && col_ok && inside(lx, rly, rlz);
+        const bool ru = rok && in_u(x0 + lx, y0 + rly, z0 + rlz);
+        float4 rf = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (ru) rf = *reinterpret_cast<const float4 *>(Fb + off(lx, rly, rlz));
+        // 4-point x ends of the own and ring rows
+        const int xr = threadIdx.x >> 1, xside = threadIdx.x & 1;
+        int xly = 0, xlz = 0;
+        if (xr < K::ROWS) {
+            xly = xr & 7;
+            xlz = xr >> 3;
+        } else if (xr < K::ROWS + K::NRING) {
+            vec2_ring_row(xr - K::ROWS, &xly, &xlz);
+        }
+        const int xx = xside ? W : -4;
+        const bool xok = threadIdx.x < K::NXH && inside(xx, xly, xlz);
+        VT xh;
+        if (xok) {
+            const bool u = in_u(x0 + xx, y0 + xly, z0 + xlz);
+            xh = *reinterpret_cast<const VT *>((u ? cur : orig) + off(xx, xly, xlz));
+        }
+        // x-ring points (x = -1 or W on the own rows): F and membership
+        const int cxr = xside ? W : -1;
+        const bool cok = threadIdx.x < K::NXR && inside(cxr, xly, xlz);
+        const bool cu = cok && in_u(x0 + cxr, y0 + xly, z0 + xlz);
+        float cf = 0.f;
+        if (cu) cf = Fb[off(cxr, xly, xlz)];
+
+        // (2) the step-n box
+        if (col_ok) {
+#pragma unroll
+            for (int q = 0; q < NOWN; ++q) {
+                const int row = lr + q * RP;
+                *reinterpret_cast<float4 *>(box0 + o0(lx, row & 7, row >> 3)) = decode(raw[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NHP; ++q)
+            if (hok[q]) *reinterpret_cast<float4 *>(box0 + hslot[q]) = decode(hv[q]);
+        if (xok) *reinterpret_cast<float4 *>(box0 + o0(xx, xly, xlz)) = decode(xh);
+        __syncthreads();
+
+        // one step at box point (x, y, z) from box b (strides sxy), F = f
+        auto step = [&](const float *b, int sxy, int o, int x, int y, int z, float f) {
+            const float c = b[o];
+            const float xm = x0 + x > 0 ? b[o - 1] : c, xp = x0 + x < nx - 1 ? b[o + 1] : c;
+            const float ym = y0 + y > 0 ? b[o - SX] : c, yp = y0 + y < ny - 1 ? b[o + SX] : c;
+            const float zm = z0 + z > 0 ? b[o - sxy] : c, zp = z0 + z < nz - 1 ? b[o + sxy] : c;
+            return upwind_point<float, false>(c, xm, xp, ym, yp, zm, zp, f, a.dx, a.dt, a.dtdx);
+        };
+
+        // (3) first step: own points, ring rows, x-ring points -> box1
+        if (col_ok) {
+#pragma unroll
+            for (int q = 0; q < NOWN; ++q) {
+                const int row = lr + q * RP, ly = row & 7, lz = row >> 3;
+                const float f4[4] = {fv[q].x, fv[q].y, fv[q].z, fv[q].w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int oo = o0(lx + e, ly, lz);
+                    const float v = step(box0, SXY0, oo, lx + e, ly, lz, f4[e]);
+                    box1[o1(lx + e, ly, lz)] = f4[e] == 0.f ? box0[oo] : stored(v);
+                }
+            }
+        }
+        if (rok) {
+            const float f4[4] = {rf.x, rf.y, rf.z, rf.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int oo = o0(lx + e, rly, rlz);
+                float v = box0[oo];  // outside U: frozen
+                if (ru && f4[e] != 0.f) v = stored(step(box0, SXY0, oo, lx + e, rly, rlz, f4[e]));
+                box1[o1(lx + e, rly, rlz)] = v;
+            }
+        }
+        if (cok) {
+            const int oo = o0(cxr, xly, xlz);
+            float v = box0[oo];
+            if (cu && cf != 0.f) v = stored(step(box0, SXY0, oo, cxr, xly, xlz, cf));
+            box1[o1(cxr, xly, xlz)] = v;
+        }
+        __syncthreads();
+
+        // (4) second step on the own points -> nxt
+        if (col_ok) {
+#pragma unroll
+            for (int q = 0; q < NOWN; ++q) {
+                const int row = lr + q * RP, ly = row & 7, lz = row >> 3;
+                const float f4[4] = {fv[q].x, fv[q].y, fv[q].z, fv[q].w};
+                S out[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float v = step(box1, SXY1, o1(lx + e, ly, lz), lx + e, ly, lz, f4[e]);
+                    out[e] = f4[e] == 0.f ? VS::get(raw[q], e) : Codec<S>::store(v, sc);
+                }
+                *reinterpret_cast<VT *>(nxt + off(lx, ly, lz)) = VS::make(out);
+            }
+        }
+        __syncthreads();  // boxes free for the next item
     }
 }
 

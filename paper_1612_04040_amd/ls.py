@@ -36,7 +36,8 @@ class ls_grid(ctypes.Structure):
 
 class ls_tuning(ctypes.Structure):
     _fields_ = [("run_width", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("pipeline", ctypes.c_int32), ("vector", ctypes.c_int32)]
+                ("pipeline", ctypes.c_int32), ("vector", ctypes.c_int32),
+                ("temporal", ctypes.c_int32)]
 
 
 class ls_instance(ctypes.Structure):
@@ -293,16 +294,16 @@ def ls_stats_read(which):
     return launches.value, timed.value, ms.value
 
 
-def ls_set_tuning(run_width=0, blocks_per_cu=0, pipeline=0, vector=0):
-    t = ls_tuning(int(run_width), int(blocks_per_cu), int(pipeline), int(vector))
+def ls_set_tuning(run_width=0, blocks_per_cu=0, pipeline=0, vector=0, temporal=0):
+    t = ls_tuning(int(run_width), int(blocks_per_cu), int(pipeline), int(vector), int(temporal))
     return _check(lib().ls_set_tuning(ctypes.byref(t)))
 
 
 def ls_get_tuning():
-    """(run_width, blocks_per_cu, pipeline, vector)."""
+    """(run_width, blocks_per_cu, pipeline, vector, temporal)."""
     t = ls_tuning()
     _check(lib().ls_get_tuning(ctypes.byref(t)))
-    return t.run_width, t.blocks_per_cu, t.pipeline, t.vector
+    return t.run_width, t.blocks_per_cu, t.pipeline, t.vector, t.temporal
 
 
 PRECISION_ID = {"f32": 0, "f64": 1, "f16s": 2}

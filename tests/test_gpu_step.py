@@ -239,3 +239,46 @@ def test_vector_and_scalar_kernels_agree_bitwise_f16s(dims, run_width):
     half_ulp = 2.0 ** (np.floor(np.log2(reach)) - 11)
     bound = steps * half_ulp * float(s) + fp32_step_bound(phi, F, dx, dt, steps)
     assert np.max(np.abs(got - want)) <= bound
+
+
+@pytest.mark.parametrize("precision", ["f32", "f16s"])
+@pytest.mark.parametrize("dims", [(100, 64, 72), (128, 72, 80), (64, 64, 64)])
+@pytest.mark.parametrize("run_width", [32, 64])
+def test_two_step_launches_equal_one_step_launches(precision, dims, run_width):
+    """Two steps per launch (temporal blocking, a tuning option on grids of
+    whole y/z tiles) against one step per launch: the same bits after 1, 2, 3 and 6
+    steps, on random band lists (tiles at every face of the grid, holes, a
+    ragged x tile), with F = 0 points; and within the rounding bound of the
+    FP64 oracle (FP32)."""
+    from paper_1612_04040_amd import ls
+
+    rng = np.random.default_rng(sum(dims) + run_width + (7 if precision == "f16s" else 0))
+    nx, ny, nz = dims
+    F = rng.uniform(-1, 1, (nz, ny, nx)).astype(np.float32)
+    F[rng.random(F.shape) < 0.05] = 0.0
+    dx = 1.0 / nx
+    dt = float(np.float32(W.stable_dt(F, dx)))
+    s = np.float32(0.05)
+    if precision == "f32":
+        phi = rng.uniform(-1, 1, (nz, ny, nx)).astype(np.float32)
+    else:
+        phi = (rng.uniform(-1, 1, (nz, ny, nx)) / float(s)).astype(np.float16)
+    tile = (8, 8, 8)
+    ntiles = -(-nx // 8) * -(-ny // 8) * -(-nz // 8)
+    tiles = random_tiles(rng, ntiles, 0.5)
+    for steps in (1, 2, 3, 6):
+        out = {}
+        try:
+            for temporal in (0, 1):
+                ls.ls_set_tuning(run_width, 0, 0, 0, temporal)
+                bg = BandGrid(dims, tile, precision)
+                pd = torch.from_numpy(phi.copy()).to(dev())
+                bg.step(pd, to_dev(F), dx, dt, steps, scale=float(s) if precision == "f16s" else None,
+                        tiles=to_dev(tiles), ntiles=to_dev(np.array([tiles.size], np.int32)))
+                out[temporal] = host(pd)
+        finally:
+            ls.ls_set_tuning(0, 0, 0, 0, 0)
+        assert out[0].tobytes() == out[1].tobytes(), f"{steps} steps"
+    if precision == "f32":
+        want = oracle.upwind_steps(phi.astype(np.float64), F, dx, dt, tiles, 6, tile)
+        assert np.max(np.abs(out[0] - want)) <= fp32_step_bound(phi, F, dx, dt, 6)
