@@ -6,7 +6,7 @@ function here is the plain definition in numpy float64; the pins are in
 tests/test_oracle_closure.py (finite-difference gradients, scipy
 correlation, closed forms of the restriction, the zero-network identity).
 
-Conventions (readings of a spec addition; the paper has no network):
+Conventions (readings for an addition to the method; the paper has no network):
   restriction  coarse cell (I,J,K) = mean of the 2x2x2 fine points 4I+1..4I+2
                (the coarse cell centre lies midway between them).
   features     c0 = clip(phi / gamma, -2, 2), c1 = F / Fmax,

@@ -12,7 +12,7 @@ target everywhere on the coarse band), and the fine field restricted 4x is
 kept after every `ratio` fine steps (= one coarse step at the same CFL
 number).  A training pair is (restricted field at coarse step n, at n + 1).
 
-    python -m paper_1612_04040_amd.closure_train --out gpurun_out/closure.json
+    python -m paper_1612_04040_amd.closure_train --out closure.json
 """
 import argparse
 import json

@@ -42,9 +42,10 @@ def random_tiles(rng, ntiles, frac):
 
 
 def report(name, **fields):
-    """Append a JSON record to gpurun_out/reports.jsonl when that folder exists."""
-    out = os.environ.get("LS_REPORT_DIR", "gpurun_out")
-    if os.path.isdir(out):
+    """Append a JSON record to $LS_REPORT_DIR/reports.jsonl when that variable
+    names an existing folder."""
+    out = os.environ.get("LS_REPORT_DIR", "")
+    if out and os.path.isdir(out):
         with open(os.path.join(out, "reports.jsonl"), "a") as fh:
             fh.write(json.dumps({"test": name, **fields}) + "\n")
 
