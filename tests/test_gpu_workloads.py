@@ -11,6 +11,10 @@
 * The one-call driver equals build + step window by window, bit for bit.
 * A reduced torus (the 1024^3 scaled-FP16 recipe at 128^3): the FP16-stored
   run stays within the FP16 rounding bound of the FP64 oracle near the front.
+* The 1024^3 FP16 torus at full size: the band list of phi^0 bit-exact and the
+  first step within the FP16 storage bound of the oracle on every band point.
+* The 256-grid batch at full size: sampled grids equal their single-grid runs,
+  bit for bit.
 """
 import numpy as np
 import pytest
@@ -214,3 +218,70 @@ def test_torus_f16s_error_report(n):
     print(f"[f16s torus {n}^3] {rec}", flush=True)
     assert np.abs(got - same).max() <= rec["bound_dx"] * wl.dx
     assert rec["same_lists"]["hausdorff_dx"] <= 1.0
+
+
+@pytest.mark.timeout(1200)
+def test_torus1024_f16s_full_size_first_step():
+    """The 1024^3 scaled-FP16 torus at full size, in the launch configuration
+    the bench times (8^3 tiles, 64-point item rows, the vectorised FP16 step):
+    the band list of phi^0 equals the oracle's bit for bit, and one step
+    matches the FP64 oracle's step of the dequantised phi^0 on every band
+    point within one FP16 storage rounding (half an ulp of |phi|/s, times s)
+    plus the FP32 arithmetic bound."""
+    from gpu_util import fp32_step_bound
+
+    n = 1024
+    wl = W.torus_grf(n, 500)
+    s = np.float32(wl.scale)
+    h = W.quantize_f16s(wl.phi, s)
+    wl.phi = None
+    bg = BandGrid((n, n, n), wl.tile, "f16s")
+    hd, Fd = torch.from_numpy(h).to(dev()), to_dev(wl.F)
+    bg.build(hd, wl.gamma, dilate=True, scale=float(s))
+    got_list = bg.band_list().numpy()
+    phi0 = oracle.dequant_f16s(h, s)
+    want_list = oracle.band_tiles(phi0, wl.tile, np.float32(wl.gamma), True)
+    assert got_list.tolist() == want_list.tolist()
+    bg.step(hd, Fd, wl.dx, wl.dt, 1, scale=float(s))
+    got = oracle.dequant_f16s(host(hd), s)
+    want = oracle.upwind_steps(phi0, wl.F, wl.dx, wl.dt, want_list, 1, wl.tile)
+    mask = np.zeros((n // 8,) * 3, bool)
+    mask.reshape(-1)[want_list] = True
+    g = got.reshape(n // 8, 8, n // 8, 8, n // 8, 8).transpose(0, 2, 4, 1, 3, 5)[mask]
+    w = want.reshape(n // 8, 8, n // 8, 8, n // 8, 8).transpose(0, 2, 4, 1, 3, 5)[mask]
+    del got, want
+    # per point: half an FP16 ulp of |want|/s (2^-25 s in the subnormal range),
+    # the FP32 roundings of v / s and of the decode h * s, and the FP32
+    # arithmetic of the step (global bound)
+    mag = np.maximum(np.abs(w) / float(s), 2.0 ** -14)
+    bound = (2.0 ** (np.floor(np.log2(mag)) - 11) * float(s) + 4 * EPS32 * np.abs(w) +
+             fp32_step_bound(phi0, wl.F, wl.dx, wl.dt, 1))
+    err = np.abs(g.astype(np.float64) - w)
+    report("torus1024_f16s_first_step", band_tiles=int(want_list.size),
+           max_err_dx=float(err.max() / wl.dx), max_err_over_bound=float((err / bound).max()))
+    assert np.all(err <= bound)
+
+
+@pytest.mark.timeout(900)
+def test_batch256_full_size_grids_equal_single_runs():
+    """The 256-grid batch at full size (32^3..192^3), with the autotuner's
+    shapes and pitched rows as the bench runs it: two windows; every eighth
+    grid, run alone through the single-grid driver (dense rows), gives the same
+    bits and the same band list."""
+    from paper_1612_04040_amd.autotune import shape_for, tune
+    from paper_1612_04040_amd.batch import Batch
+
+    insts = W.ellipsoid_batch()
+    table = tune([it.n for it in insts])
+    specs = [((it.n,) * 3, shape_for(it.n, table), it.dx, it.dt, it.gamma) for it in insts]
+    b = Batch(specs, device=dev())
+    b.load([it.phi for it in insts], [it.F for it in insts])
+    b.run(20, 10)
+    lists = b.band_lists()
+    for i in range(0, len(insts), 8):
+        dims, tile, dx, dt, gamma = specs[i]
+        bg = BandGrid(dims, tile, "f32")
+        pd = to_dev(insts[i].phi)
+        bg.run(pd, to_dev(insts[i].F), dx, dt, gamma, 20, 10)
+        assert host(b.view(b.phi, i)).tobytes() == host(pd).tobytes(), f"grid {i} {dims} {tile}"
+        assert lists[i].tolist() == bg.band_list().numpy().tolist(), f"grid {i}"
