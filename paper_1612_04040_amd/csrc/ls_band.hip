@@ -8,44 +8,6 @@
 namespace ls {
 
 // ---------------------------------------------------------------------------
-// one-block exclusive scan of the per-block counts
-
-__global__ __launch_bounds__(1024) void compact_scan_kernel(int32_t *blk_a, int32_t *count_a,
-                                                            int32_t *blk_b, int32_t *count_b,
-                                                            int64_t nblk) {
-    int32_t *blk = blockIdx.x == 0 ? blk_a : blk_b;
-    int32_t *count = blockIdx.x == 0 ? count_a : count_b;
-    __shared__ int wave_sum[1024 / 64];
-    __shared__ int carry_s;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (threadIdx.x == 0) carry_s = 0;
-    __syncthreads();
-    for (int64_t base = 0; base < nblk; base += 1024) {
-        const int64_t i = base + threadIdx.x;
-        const int v = i < nblk ? blk[i] : 0;
-        // inclusive scan inside the wave
-        int s = v;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int t = __shfl_up(s, d, 64);
-            if (lane >= d) s += t;
-        }
-        if (lane == 63) wave_sum[wave] = s;
-        __syncthreads();
-        int before = carry_s;
-        for (int w = 0; w < wave; ++w) before += wave_sum[w];
-        if (i < nblk) blk[i] = before + s - v;  // exclusive
-        __syncthreads();
-        if (threadIdx.x == 1023) carry_s = before + s;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        blk[nblk] = carry_s;
-        *count = carry_s;
-    }
-}
-
-// ---------------------------------------------------------------------------
 // step plan: work items (x-runs of band tiles broken at every R-th tile
 // column) and their records, from the update map
 
@@ -110,7 +72,7 @@ __global__ __launch_bounds__(kBlock) void item_record_kernel(ItemRecordFn f, con
 }
 
 int build_plan(const Geom &g, uint8_t *ws, int32_t *list, int32_t *list_count,
-               hipStream_t stream) {
+               hipStream_t stream, TileAccum accum) {
     const Workspace w = workspace_layout(g);
     const uint8_t *umap = ws + w.u_map;
     int32_t *blk = reinterpret_cast<int32_t *>(ws + w.blk_counts);
@@ -122,7 +84,7 @@ int build_plan(const Geom &g, uint8_t *ws, int32_t *list, int32_t *list_count,
     int rc;
     if (list)
         rc = compact2(MapPred{umap}, EmitIndex{list}, list_count, blk, heads, EmitHeadTile{rec},
-                      nitems, blk2, nullptr, g.ntiles, stream);
+                      nitems, blk2, nullptr, g.ntiles, stream, accum);
     else
         rc = compact(heads, EmitHeadTile{rec}, nullptr, g.ntiles, nitems, blk, stream);
     if (rc != LS_OK) return rc;
@@ -337,7 +299,7 @@ static int band_args(const S *phi, const ls_grid *grid, typename Codec<S>::C gam
 // Dilation (or copy) of the flags into the update map, then the ordered band
 // list and the step plan of that list.
 static int band_finish(const Geom &g, uint8_t *ws, int dilate, int32_t *tiles,
-                       int32_t *ntiles_dev, hipStream_t stream) {
+                       int32_t *ntiles_dev, hipStream_t stream, TileAccum accum) {
     const Workspace w = workspace_layout(g);
     const dim3 dgrid(static_cast<unsigned>(cdiv64(g.ntx, 64)), static_cast<unsigned>(cdiv64(g.nty, 4)),
                      g.ntz);
@@ -345,13 +307,14 @@ static int band_finish(const Geom &g, uint8_t *ws, int dilate, int32_t *tiles,
                        static_cast<const uint8_t *>(ws + w.a_flags), ws + w.u_map, g.ntx, g.nty,
                        g.ntz, dilate);
     LS_LAUNCH_CHECK("band_dilate_kernel");
-    return build_plan(g, ws, tiles, ntiles_dev, stream);
+    return build_plan(g, ws, tiles, ntiles_dev, stream, accum);
 }
 
 template <class S>
 int band_build(const S *phi, typename Codec<S>::C scale, const ls_grid *grid,
                typename Codec<S>::C gamma, int dilate, int32_t *tiles, int64_t capacity,
-               int32_t *ntiles_dev, void *workspace, int64_t ws_bytes, void *stream_) {
+               int32_t *ntiles_dev, void *workspace, int64_t ws_bytes, void *stream_,
+               TileAccum accum) {
     Geom g;
     int rc = band_args(phi, grid, gamma, dilate, tiles, capacity, ntiles_dev, workspace, ws_bytes,
                        &g);
@@ -376,7 +339,7 @@ int band_build(const S *phi, typename Codec<S>::C scale, const ls_grid *grid,
     }
     LS_LAUNCH_CHECK("band_flag_kernel");
     if ((rc = stats_after(LS_KERNEL_BAND_FLAG, stream, slot)) != LS_OK) return rc;
-    return band_finish(g, ws, dilate, tiles, ntiles_dev, stream);
+    return band_finish(g, ws, dilate, tiles, ntiles_dev, stream, accum);
 }
 
 __global__ __launch_bounds__(kBlock) void fill_zero_kernel(uint8_t *p, int64_t n16) {
@@ -403,7 +366,7 @@ int band_rebuild(const S *phi, typename Codec<S>::C scale, const ls_grid *grid,
                  typename Codec<S>::C gamma, const int32_t *prev_tiles,
                  const int32_t *prev_ntiles_dev, int32_t *tiles, int64_t capacity,
                  int32_t *ntiles_dev, void *workspace, int64_t ws_bytes, void *stream_,
-                 bool flags_valid) {
+                 bool flags_valid, TileAccum accum) {
     Geom g;
     int rc = band_args(phi, grid, gamma, 1, tiles, capacity, ntiles_dev, workspace, ws_bytes, &g);
     if (rc != LS_OK) return rc;
@@ -435,24 +398,25 @@ int band_rebuild(const S *phi, typename Codec<S>::C scale, const ls_grid *grid,
                        gamma, scale, prev_tiles, prev_ntiles_dev, ws + w.a_flags, vec_rows);
     LS_LAUNCH_CHECK("band_flag_list_kernel");
     if ((rc = stats_after(LS_KERNEL_BAND_FLAG, stream, slot)) != LS_OK) return rc;
-    return band_finish(g, ws, 1, tiles, ntiles_dev, stream);
+    return band_finish(g, ws, 1, tiles, ntiles_dev, stream, accum);
 }
 
 template int band_build<float>(const float *, float, const ls_grid *, float, int, int32_t *,
-                               int64_t, int32_t *, void *, int64_t, void *);
+                               int64_t, int32_t *, void *, int64_t, void *, TileAccum);
 template int band_build<double>(const double *, double, const ls_grid *, double, int, int32_t *,
-                                int64_t, int32_t *, void *, int64_t, void *);
+                                int64_t, int32_t *, void *, int64_t, void *, TileAccum);
 template int band_build<uint16_t>(const uint16_t *, float, const ls_grid *, float, int,
-                                  int32_t *, int64_t, int32_t *, void *, int64_t, void *);
+                                  int32_t *, int64_t, int32_t *, void *, int64_t, void *,
+                                  TileAccum);
 template int band_rebuild<float>(const float *, float, const ls_grid *, float, const int32_t *,
                                  const int32_t *, int32_t *, int64_t, int32_t *, void *, int64_t,
-                                 void *, bool);
+                                 void *, bool, TileAccum);
 template int band_rebuild<double>(const double *, double, const ls_grid *, double,
                                   const int32_t *, const int32_t *, int32_t *, int64_t, int32_t *,
-                                  void *, int64_t, void *, bool);
+                                  void *, int64_t, void *, bool, TileAccum);
 template int band_rebuild<uint16_t>(const uint16_t *, float, const ls_grid *, float,
                                     const int32_t *, const int32_t *, int32_t *, int64_t,
-                                    int32_t *, void *, int64_t, void *, bool);
+                                    int32_t *, void *, int64_t, void *, bool, TileAccum);
 
 }  // namespace ls
 

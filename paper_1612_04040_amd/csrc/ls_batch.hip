@@ -428,9 +428,6 @@ __global__ __launch_bounds__(kBlock) void batch_copy_kernel(const float *__restr
     }
 }
 
-__global__ void batch_accumulate_kernel(int64_t *acc, const int32_t *count, int nsteps) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *acc += static_cast<int64_t>(*count) * nsteps;
-}
 
 // acc += nsteps * (in-domain points of the listed tiles): a grid-stride sum,
 // one atomic add per block (integer, so the order does not matter).
@@ -510,7 +507,7 @@ static int check_batch_ws(const BatchLayout &L, void *ws, int64_t bytes, BatchWs
 // list into `list` / `*count`, and the plan (records, group ranges).
 static int batch_build(const BatchLayout &L, const float *phi, uint8_t *ws, const BatchWs &w,
                        const int32_t *prev, const int32_t *prev_count, int32_t *list,
-                       int32_t *count, hipStream_t stream) {
+                       int32_t *count, hipStream_t stream, TileAccum accum) {
     const int n = static_cast<int>(L.inst.size());
     const int T = static_cast<int>(L.total_tiles);
     const BatchInst *inst = reinterpret_cast<const BatchInst *>(ws + w.inst);
@@ -542,7 +539,7 @@ static int batch_build(const BatchLayout &L, const float *phi, uint8_t *ws, cons
     LS_LAUNCH_CHECK("batch_dilate_kernel");
     rc = compact2(MapPred{u}, EmitIndex{list}, count, reinterpret_cast<int32_t *>(ws + w.blk),
                   BatchHeadPred{u, inst, n}, EmitHeadGlobal{rec}, nitems,
-                  reinterpret_cast<int32_t *>(ws + w.blk2), nullptr, T, stream);
+                  reinterpret_cast<int32_t *>(ws + w.blk2), nullptr, T, stream, accum);
     if (rc != LS_OK) return rc;
     hipLaunchKernelGGL(batch_range_kernel, dim3(1), dim3(64), 0, stream,
                        static_cast<const int32_t *>(rec), static_cast<const int32_t *>(nitems),
@@ -683,13 +680,9 @@ int ls_batch_run_f32(const ls_instance *inst, int n, float *phi, const float *F,
         const int m = std::min(window, nsteps - k * window);
         const int cur = (nwin - 1 - k) & 1;  // the last window's band lands in list0
         rc = ls::batch_build(L, phi, ws, w, k == 0 ? nullptr : lists[cur ^ 1],
-                             k == 0 ? nullptr : counts[cur ^ 1], lists[cur], counts[cur], stream);
+                             k == 0 ? nullptr : counts[cur ^ 1], lists[cur], counts[cur], stream,
+                             ls::TileAccum{tile_steps_dev, m});
         if (rc != LS_OK) return rc;
-        if (tile_steps_dev) {
-            hipLaunchKernelGGL(ls::batch_accumulate_kernel, dim3(1), dim3(64), 0, stream,
-                               tile_steps_dev, static_cast<const int32_t *>(counts[cur]), m);
-            LS_LAUNCH_CHECK("batch_accumulate_kernel");
-        }
         if (point_steps_dev) {
             const unsigned pb = static_cast<unsigned>(
                 std::min<int64_t>(ls::cdiv64(L.total_tiles, ls::kBlock), 1024));

@@ -778,10 +778,6 @@ __global__ void zero_f32_kernel(float *p, int64_t n) {
 
 namespace ls {
 
-template <class S>
-int band_build(const S *phi, typename Codec<S>::C scale, const ls_grid *grid,
-               typename Codec<S>::C gamma, int dilate, int32_t *tiles, int64_t capacity,
-               int32_t *ntiles_dev, void *workspace, int64_t ws_bytes, void *stream_);  // ls_band.hip
 int plan_step_to_f32(const float *phi, float *out, const float *F, const Geom &G, float dx,
                      float dt, uint8_t *ws, hipStream_t stream);                      // ls_step.hip
 

@@ -124,6 +124,14 @@ struct Codec<uint16_t> {
 // ---------------------------------------------------------------------------
 // wave-level helpers (wave64)
 
+// Optional accumulation by a band build of (listed tiles) x mul into a
+// device counter (the tile-steps numerator of the drivers): added once the
+// list is counted, in the same launch.
+struct TileAccum {
+    int64_t *acc = nullptr;
+    int mul = 0;
+};
+
 __device__ inline int lane_prefix(uint64_t mask) {
     // number of set bits of `mask` below this lane (v_mbcnt_lo / v_mbcnt_hi)
     return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
@@ -142,6 +150,21 @@ int plan_run_tiles(const Geom &g);
 // (count in *list_count), writes the work-item records and their count.  One
 // dual ordered compaction over the tile ids plus a record kernel.
 int build_plan(const Geom &g, uint8_t *ws, int32_t *list, int32_t *list_count,
-               hipStream_t stream);
+               hipStream_t stream, TileAccum accum = TileAccum{});
+
+// Band build (full scan) and exact incremental rebuild of one grid, behind
+// the ls_band_build_* / ls_band_rebuild_* entry points (ls_band.hip); accum
+// adds (band tiles) x accum.mul to *accum.acc in the same launches.
+template <class S>
+int band_build(const S *phi, typename Codec<S>::C scale, const ls_grid *grid,
+               typename Codec<S>::C gamma, int dilate, int32_t *tiles, int64_t capacity,
+               int32_t *ntiles_dev, void *workspace, int64_t ws_bytes, void *stream_,
+               TileAccum accum = TileAccum{});
+template <class S>
+int band_rebuild(const S *phi, typename Codec<S>::C scale, const ls_grid *grid,
+                 typename Codec<S>::C gamma, const int32_t *prev_tiles,
+                 const int32_t *prev_ntiles_dev, int32_t *tiles, int64_t capacity,
+                 int32_t *ntiles_dev, void *workspace, int64_t ws_bytes, void *stream_,
+                 bool flags_valid, TileAccum accum = TileAccum{});
 
 }  // namespace ls

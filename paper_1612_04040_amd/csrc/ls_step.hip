@@ -622,23 +622,6 @@ static int launch_info(const ls_grid *grid, int32_t *blocks, int32_t *lds_bytes,
     return LS_OK;
 }
 
-// declared in ls_band.hip
-template <class S>
-int band_build(const S *phi, typename Codec<S>::C scale, const ls_grid *grid,
-               typename Codec<S>::C gamma, int dilate, int32_t *tiles, int64_t capacity,
-               int32_t *ntiles_dev, void *workspace, int64_t ws_bytes, void *stream_);
-template <class S>
-int band_rebuild(const S *phi, typename Codec<S>::C scale, const ls_grid *grid,
-                 typename Codec<S>::C gamma, const int32_t *prev_tiles,
-                 const int32_t *prev_ntiles_dev, int32_t *tiles, int64_t capacity,
-                 int32_t *ntiles_dev, void *workspace, int64_t ws_bytes, void *stream_,
-                 bool flags_valid);
-
-__global__ void accumulate_kernel(int64_t *acc, const int32_t *count, int nsteps) {
-    if (threadIdx.x == 0 && blockIdx.x == 0)
-        *acc += static_cast<int64_t>(*count) * nsteps;
-}
-
 // The windowed driver: a full band build for the first window, then an exact
 // incremental rebuild from the previous window's band (every point outside
 // that band is unchanged, so no tile outside it can join the tube); each
@@ -681,19 +664,15 @@ static int band_run(S *phi, const FT *F, typename Codec<S>::C scale, const ls_gr
     for (int k = 0; k < nwin; ++k) {
         const int n = std::min(window, nsteps - k * window);
         const int cur = (nwin - 1 - k) & 1;  // the last window writes lists[0]
+        const TileAccum acc{tile_steps_dev, n};  // band tiles x steps, counted by the build
         if (k == 0)
             rc = band_build<S>(phi, scale, grid, gamma, 1, lists[cur], capacity, counts[cur],
-                               workspace, ws_bytes, stream_);
+                               workspace, ws_bytes, stream_, acc);
         else
             rc = band_rebuild<S>(phi, scale, grid, gamma, lists[cur ^ 1], counts[cur ^ 1],
                                  lists[cur], capacity, counts[cur], workspace, ws_bytes, stream_,
-                                 true);
+                                 true, acc);
         if (rc != LS_OK) return rc;
-        if (tile_steps_dev) {
-            hipLaunchKernelGGL(accumulate_kernel, dim3(1), dim3(64), 0, stream, tile_steps_dev,
-                               static_cast<const int32_t *>(counts[cur]), n);
-            LS_LAUNCH_CHECK("accumulate_kernel");
-        }
         rc = upwind_launch<S, FT>(phi, F, scale, G, sg, dx, dt, n, scratch, ws, stream);
         if (rc != LS_OK) return rc;
     }
