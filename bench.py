@@ -331,7 +331,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": prec,
+        "dtype": {"f16s": "f32", "f64": "f64"}.get(prec, "f32"),  # arithmetic (storage: config)
         "data": f["data"],
         "config": f["config"],
         "kernel_glups": round(pts_per_launch / avg_launch_s / 1e9, 3),
