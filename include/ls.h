@@ -301,8 +301,8 @@ int ls_upwind_launch_info(const ls_grid *g, int precision, int32_t *blocks, int3
  * band step kernel, LS_KERNEL_BAND_FLAG: the band build's scan of phi) are
  * bracketed by pairs of HIP events recorded on the launch stream: one pair
  * around each scan, and one pair around the back-to-back step launches of a
- * call (the nsteps launches of a window), so the time per launch includes the
- * short gaps between consecutive launches but not the setup of the call.
+ * call (a window's launches), so the time per launch includes the short gaps
+ * between consecutive launches but not the setup of the call.
  * ls_stats_enable(1) clears the record; ls_stats_read waits for the recorded
  * events and returns the number of launches, how many of them were timed,
  * and the summed duration of the timed ones in ms.  At most 65536 event pairs

@@ -570,6 +570,7 @@ static int batch_steps(const BatchLayout &L, float *phi, const float *F, float *
     args.rec = rec;
     args.nitems = nitems;
     args.inst = inst;
+    args.umap = nullptr;
     args.orig = phi;
     args.dx = args.dt = args.dtdx = 0.f;
     args.scale = 1.f;
