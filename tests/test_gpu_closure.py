@@ -19,6 +19,7 @@ import torch
 
 import oracle
 from oracle import closure as CL
+from oracle.closure import restrict4 as oracle_restrict
 from gpu_util import EPS32, dev, fp32_step_bound, host, report, to_dev
 from paper_1612_04040_amd import closure as C
 from paper_1612_04040_amd import workloads as W
@@ -72,7 +73,7 @@ def _tile_mask(shape, tiles):
 
 
 def _reference_inputs(wl, fmax, plain, params):
-    """Features from the GPU's plain step (FP64, then BF16) and BF16 weights."""
+    """Features from the oracle's plain step (FP64, then BF16) and BF16 weights."""
     phi = wl.phi.astype(np.float64)
     feat = CL.features(phi, wl.F, plain.astype(np.float64) - phi, wl.dx, np.float32(wl.gamma),
                        np.float32(fmax))
@@ -98,7 +99,7 @@ def test_forward_matches_reference():
     pl = host(plain)
     ref_plain = oracle.upwind_steps(wl.phi.astype(np.float64), wl.F, wl.dx, wl.dt, want_band, 1)
     assert np.max(np.abs(pl - ref_plain)) <= fp32_step_bound(wl.phi, wl.F, wl.dx, wl.dt, 1)
-    feat, p = _reference_inputs(wl, fmax, pl, params)
+    feat, p = _reference_inputs(wl, fmax, ref_plain, params)
     want, _ = CL.forward(p, feat)
     got = host(r)
     m = _tile_mask(wl.phi.shape, active)
@@ -114,21 +115,20 @@ def test_gradients_match_reference():
     params = _params(5)
     cg = C.ClosureGrid(wl.phi.shape[::-1])
     pd, Fd = to_dev(wl.phi), to_dev(wl.F)
-    plain = torch.empty_like(pd)
-    cg.forward(pd, Fd, wl.dx, wl.dt, wl.gamma, fmax, to_dev(params), plain=plain)
-    pl = host(plain)
-    # a target one step later that the plain step misses by a smooth field
+    # a target one step later that the oracle's plain step misses by a smooth field
+    band = oracle.band_tiles(wl.phi, TILE, np.float32(wl.gamma), True)
+    ref_plain = oracle.upwind_steps(wl.phi.astype(np.float64), wl.F, wl.dx, wl.dt, band, 1)
     n = wl.phi.shape[0]
     x = (np.arange(n) + 0.5) * wl.dx
     bump = (np.sin(2 * np.pi * x)[:, None, None] * np.cos(2 * np.pi * x)[None, :, None] *
             np.sin(4 * np.pi * x)[None, None, :])
-    target = (pl + 0.2 * wl.dx * bump).astype(np.float32)
+    target = (ref_plain + 0.2 * wl.dx * bump).astype(np.float32)
     cg.backward(pd, to_dev(target), Fd, wl.dx, wl.dt, wl.gamma, fmax, to_dev(params))
     grad = host(cg.grad).astype(np.float64)
     loss = float(host(cg.loss)[0])
     active = oracle.band_tiles(wl.phi, TILE, np.float32(wl.gamma), False)
-    feat, p = _reference_inputs(wl, fmax, pl, params)
-    rstar = (target.astype(np.float64) - pl.astype(np.float64)) / wl.dx
+    feat, p = _reference_inputs(wl, fmax, ref_plain, params)
+    rstar = (target.astype(np.float64) - ref_plain) / wl.dx
     mask = _tile_mask(wl.phi.shape, active)
     gate = CL.cutoff(wl.phi.astype(np.float64), 0.5 * wl.gamma, wl.gamma)
     want_loss, want = CL.loss_and_grad(p, feat, rstar, mask, gate)
@@ -318,3 +318,54 @@ def test_judge_resets_a_bubble_the_plain_run_removes():
     err = np.max(np.abs(runs[True].astype(np.float64) - x))
     report("closure_judge", max_err_dx=float(err / dx), resets=resets)
     assert err <= 1e-3 * dx, err / dx
+
+
+@pytest.mark.timeout(600)
+def test_forward_full_size_sampled_tiles():
+    """The network at the evaluation size (128^3 coarse grid of the closure
+    workload, a trained-size random network): r on 24 sampled active tiles
+    against the FP64 reference evaluated on the 14^3 patch around each tile
+    (the three 3^3 layers see 3 points around a point, so the patch's centre
+    8^3 is exact), features from the oracle's own band and plain step."""
+    case = W.ClosureCase(5, 512)
+    nc = case.n_coarse
+    phi = oracle_restrict(case.phi(512)).astype(np.float32)
+    F = case.F(nc)
+    dx, dt, gamma, fmax = case.dx_coarse, case.dt_coarse, case.gamma_coarse, case.fmax
+    params = _params(9)
+    cg = C.ClosureGrid((nc,) * 3)
+    r = torch.empty((nc,) * 3, dtype=torch.float32, device=dev())
+    cg.forward(to_dev(phi), to_dev(F), dx, dt, gamma, fmax, to_dev(params), r=r)
+    got = host(r)
+    band = oracle.band_tiles(phi, TILE, np.float32(gamma), True)
+    active = oracle.band_tiles(phi, TILE, np.float32(gamma), False)
+    assert cg.band_list().tolist() == band.tolist()
+    ref_plain = oracle.upwind_steps(phi.astype(np.float64), F, dx, dt, band, 1)
+    feat = CL.features(phi.astype(np.float64), F, ref_plain - phi.astype(np.float64), dx,
+                       np.float32(gamma), np.float32(fmax))
+    feat = bf16(feat.astype(np.float32))
+    p = {k: bf16(v.astype(np.float32)) for k, v in C.unflatten(params).items()}
+    for k in ("b0", "b1", "b2"):
+        p[k] = C.unflatten(params)[k].astype(np.float32).astype(np.float64)
+    ntx = nty = nc // 8
+    # tiles whose 14^3 patch lies inside the grid (the patch then needs no
+    # zero activations beyond the grid faces)
+    inner = [t for t in active if all(1 <= c <= ntx - 2 for c in
+                                      (t % ntx, (t // ntx) % nty, t // (ntx * nty)))]
+    rng = np.random.default_rng(1)
+    sample = rng.choice(inner, size=min(24, len(inner)), replace=False)
+    g_all, w_all = [], []
+    for t in sample:
+        ti, tj, tk = t % ntx, (t // ntx) % nty, t // (ntx * nty)
+        lo = np.array([tk, tj, ti]) * 8 - 3
+        patch = np.zeros((3, 14, 14, 14))
+        src = [slice(max(l, 0), min(l + 14, nc)) for l in lo]
+        dst = [slice(sl.start - l, sl.stop - l) for sl, l in zip(src, lo)]
+        patch[(slice(None), *dst)] = feat[(slice(None), *src)]
+        want, _ = CL.forward(p, patch)
+        w_all.append(want[3:11, 3:11, 3:11].ravel())
+        g_all.append(got[tk * 8:tk * 8 + 8, tj * 8:tj * 8 + 8, ti * 8:ti * 8 + 8].ravel())
+    g_all, w_all = np.concatenate(g_all), np.concatenate(w_all)
+    rel, cos = _rel(g_all, w_all), _cos(g_all, w_all)
+    report("closure_forward_128", rel_l2=rel, cosine=cos, active_tiles=int(len(active)))
+    assert rel <= 2e-2 and cos >= 0.999, (rel, cos)
