@@ -131,14 +131,16 @@ def test_rebuild_random_fields():
     phi = np.where(rng.random((nz, ny, nx)) < 0.5, 1.0, -1.0).astype(np.float32)
     phi[10:14, 20:22, 30:40] = rng.uniform(-0.3, 0.3, (4, 2, 10))  # a small tube
     bg = BandGrid(dims, tile, "f32")
-    pd = to_dev(phi)
-    bg.build(pd, gamma, dilate=True)
+    bg.build(to_dev(phi), gamma, dilate=True)
     prev_t, prev_n = bg.tiles.clone(), bg.ntiles.clone()
-    # move values only inside the band, as a step would
-    bg.step(pd, to_dev(rng.uniform(-1, 1, phi.shape).astype(np.float32)), 0.05, 0.01, 3)
-    bg.rebuild(pd, gamma, prev_t, prev_n)
+    # move values only inside the band, as a step would (the oracle's steps)
+    band = oracle.band_tiles(phi, tile, np.float32(gamma), True)
+    assert bg.band_list().numpy().tolist() == band.tolist()
+    F = rng.uniform(-1, 1, phi.shape).astype(np.float32)
+    moved = oracle.upwind_steps(phi, F, 0.05, 0.01, band, 3, tile).astype(np.float32)
+    bg.rebuild(to_dev(moved), gamma, prev_t, prev_n)
     got = bg.band_list().numpy()
-    assert got.tolist() == oracle.band_tiles(host(pd), tile, np.float32(gamma), True).tolist()
+    assert got.tolist() == oracle.band_tiles(moved, tile, np.float32(gamma), True).tolist()
 
 
 def test_torus_f16s_reduced():
@@ -164,11 +166,14 @@ def test_torus_f16s_reduced():
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("n", [256])
 def test_torus_f16s_error_report(n):
-    """The scaled-FP16 torus recipe, 500 steps, against the FP64 oracle on the
-    unquantised inputs.  (a) With the GPU's band lists fed to the oracle the
-    difference is the storage precision alone: reported and bounded by FP16
-    rounding.  (b) With the oracle's own FP64 band decisions the lists can
-    differ at the band margin, which moves stale values; reported."""
+    """The scaled-FP16 torus recipe, 500 steps, against the FP64 oracle run on
+    the unquantised inputs with its own band decisions: the errors near the
+    front and in the tube, and the Hausdorff distance of the fronts, are
+    reported; asserted: the tube error stays within the FP16 storage bound
+    (steps + 1) x half an FP16 ulp of the largest |phi|/s in the band, times s
+    (the update is non-expansive in the max norm and each step adds at most
+    one store rounding; the band lists of the two runs can differ at the band
+    margin, outside the tube), and the fronts lie within 1 dx."""
     from paper_1612_04040_amd import metrics as M
 
     steps = 500
@@ -183,41 +188,32 @@ def test_torus_f16s_error_report(n):
         lists.append(bg.band_list().numpy())
         bg.step(hd, Fd, wl.dx, wl.dt, wl.window, scale=float(s))
     got = oracle.dequant_f16s(host(hd), s).astype(np.float64)
-    same = wl.phi.astype(np.float64)
-    for tl in lists:
-        same = oracle.upwind_steps(same, wl.F, wl.dx, wl.dt, tl, wl.window, wl.tile)
-    own, own_lists = oracle.run_band(wl.phi.astype(np.float64), wl.F, wl.dx, wl.dt,
-                                     np.float32(wl.gamma), steps, window=wl.window,
-                                     record_tiles=True)
-    crossings = M.zero_crossings(got, wl.dx)
+    want, own_lists = oracle.run_band(wl.phi.astype(np.float64), wl.F, wl.dx, wl.dt,
+                                      np.float32(wl.gamma), steps, window=wl.window,
+                                      record_tiles=True)
+    err = np.abs(got - want)
+    front = np.abs(want) < wl.dx
+    tube = np.abs(want) < wl.gamma
     rec = dict(n=n, steps=steps,
                windows_with_other_lists=int(sum(a.tolist() != b.tolist()
-                                                for a, b in zip(lists, own_lists))))
-    for name, want in (("same_lists", same), ("own_lists", own)):
-        err = np.abs(got - want)
-        front = np.abs(want) < wl.dx
-        tube = np.abs(want) < wl.gamma
-        rec[name] = dict(
-            max_err_front_dx=float(err[front].max() / wl.dx),
-            max_err_tube_dx=float(err[tube].max() / wl.dx),
-            rms_err_front_dx=float(np.sqrt(np.mean(err[front] ** 2)) / wl.dx),
-            hausdorff_dx=M.hausdorff(crossings, M.zero_crossings(want, wl.dx)) / wl.dx,
-            by_abs_phi_dx=error_by_band_distance(err, want, wl.dx))
-    # worst case: the update is non-expansive in the max norm, and each step
-    # adds at most one store rounding, half an FP16 ulp of the largest |phi|/s
-    # in the band, times s (plus the initial quantisation, the same size)
-    nx = ny = nz = n
-    band = np.zeros((nz // 8, ny // 8, nx // 8), bool)
-    for tl in lists:
+                                                for a, b in zip(lists, own_lists))),
+               max_err_front_dx=float(err[front].max() / wl.dx),
+               max_err_tube_dx=float(err[tube].max() / wl.dx),
+               rms_err_front_dx=float(np.sqrt(np.mean(err[front] ** 2)) / wl.dx),
+               hausdorff_dx=M.hausdorff(M.zero_crossings(got, wl.dx),
+                                        M.zero_crossings(want, wl.dx)) / wl.dx,
+               by_abs_phi_dx=error_by_band_distance(err, want, wl.dx))
+    band = np.zeros((n // 8,) * 3, bool)
+    for tl in own_lists:
         band.reshape(-1)[tl] = True
     mask = np.repeat(np.repeat(np.repeat(band, 8, 0), 8, 1), 8, 2)
-    hmax = float(max(np.abs(same[mask]).max(), np.abs(wl.phi[mask]).max())) / float(s)
+    hmax = float(max(np.abs(want[mask]).max(), np.abs(wl.phi[mask]).max())) / float(s)
     half_ulp = 2.0 ** (np.floor(np.log2(hmax)) - 11)
     rec["bound_dx"] = (steps + 1) * half_ulp * float(s) / wl.dx
     report("torus_f16s_error", **rec)
     print(f"[f16s torus {n}^3] {rec}", flush=True)
-    assert np.abs(got - same).max() <= rec["bound_dx"] * wl.dx
-    assert rec["same_lists"]["hausdorff_dx"] <= 1.0
+    assert rec["max_err_tube_dx"] <= rec["bound_dx"]
+    assert rec["hausdorff_dx"] <= 1.0
 
 
 @pytest.mark.timeout(1200)
