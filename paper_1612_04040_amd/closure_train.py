@@ -252,12 +252,12 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--n-fine", type=int, default=512)
     ap.add_argument("--coarse-steps", type=int, default=400)
-    ap.add_argument("--train-seeds", default="100-115")
+    ap.add_argument("--train-seeds", default="100-131")
     ap.add_argument("--val-seeds", default="200-203")
     ap.add_argument("--eval-seed", type=int, default=5)
-    ap.add_argument("--iters", type=int, default=8000)
-    ap.add_argument("--rollout-max", type=int, default=2)
-    ap.add_argument("--rollout-prob", type=float, default=0.3)
+    ap.add_argument("--iters", type=int, default=20000)
+    ap.add_argument("--rollout-max", type=int, default=4)
+    ap.add_argument("--rollout-prob", type=float, default=0.5)
     ap.add_argument("--lr", type=float, default=3e-4)
     ap.add_argument("--init-seed", type=int, default=0)
     ap.add_argument("--params-out", default=None, help="save the trained parameters (.npy)")
