@@ -1192,9 +1192,9 @@ int ls_closure_run_f32(float *phi, const float *F, const ls_grid *g, float dx, f
                        int32_t *fallbacks_dev, int32_t *resets_dev, void *ws, int64_t ws_bytes,
                        void *cws, int64_t cws_bytes, void *stream) {
     ls::clear_error();
-    ls::ClosureCall c;
-    int rc = ls::closure_setup(g, dx, dt, gamma, fmax, params, ws, ws_bytes, cws, cws_bytes,
-                               stream, &c);
+    // the host checks first: nothing is launched or queried on an error
+    ls::Geom G0;
+    int rc = ls::closure_geom(g, &G0);
     if (rc != LS_OK) return rc;
     if (!phi || !F || !tiles || !ntiles_dev || !fallbacks_dev || (judge && !resets_dev)) {
         ls::set_error("closure run: NULL argument");
@@ -1204,11 +1204,15 @@ int ls_closure_run_f32(float *phi, const float *F, const ls_grid *g, float dx, f
         ls::set_error("closure run: need nsteps >= 0 and window > 0");
         return LS_ERR_ARG;
     }
-    if (capacity < c.G.ntiles) {
+    if (capacity < G0.ntiles) {
         ls::set_error("closure run: capacity %lld < %lld tiles", (long long)capacity,
-                      (long long)c.G.ntiles);
+                      (long long)G0.ntiles);
         return LS_ERR_CAPACITY;
     }
+    ls::ClosureCall c;
+    rc = ls::closure_setup(g, dx, dt, gamma, fmax, params, ws, ws_bytes, cws, cws_bytes, stream,
+                           &c);
+    if (rc != LS_OK) return rc;
     if ((rc = ls::pack_all(c, params)) != LS_OK) return rc;
     float *shadow = ls::at<float>(c, c.w.shadow);
     float *shadow_scratch = ls::at<float>(c, c.w.shadow_scratch);

@@ -248,3 +248,27 @@ def test_closure_parameter_layout_and_cases():
     assert ls.ls_closure_workspace_bytes(g) > 0
     with pytest.raises(ls.LsError):
         ls.ls_closure_workspace_bytes(ls.grid((60, 64, 64)))
+
+
+def test_closure_run_errors():
+    """Argument errors of the corrected driver come from the host checks,
+    before any device call (so they hold without a GPU)."""
+    g = ls.grid((32, 32, 32))
+    cap = ls.ls_grid_tiles(g)
+    ws, cws = ls.ls_workspace_bytes(g), ls.ls_closure_workspace_bytes(g)
+
+    def call(**over):
+        a = dict(phi=FAKE, F=FAKE, g=g, dx=0.1, dt=0.05, gamma=0.3, fmax=1.0, params=FAKE,
+                 nsteps=10, window=10, judge=1, tiles=FAKE, capacity=cap, ntiles_dev=FAKE,
+                 fallbacks_dev=FAKE, resets_dev=FAKE, ws=FAKE * 256, ws_bytes=ws, cws=FAKE * 512,
+                 cws_bytes=cws, stream=0)
+        a.update(over)
+        return _status(ls.ls_closure_run_f32, *a.values())
+
+    assert call(resets_dev=None) == ls.LS_ERR_ARG  # the judge needs its counter
+    assert call(fallbacks_dev=None) == ls.LS_ERR_ARG
+    assert call(phi=None) == ls.LS_ERR_ARG
+    assert call(nsteps=-1) == ls.LS_ERR_ARG
+    assert call(window=0) == ls.LS_ERR_ARG
+    assert call(capacity=cap - 1) == ls.LS_ERR_CAPACITY
+    assert call(g=ls.grid((36, 32, 32))) == ls.LS_ERR_UNSUPPORTED  # dims must be multiples of 8
