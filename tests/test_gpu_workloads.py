@@ -281,3 +281,37 @@ def test_batch256_full_size_grids_equal_single_runs():
         bg.run(pd, to_dev(insts[i].F), dx, dt, gamma, 20, 10)
         assert host(b.view(b.phi, i)).tobytes() == host(pd).tobytes(), f"grid {i} {dims} {tile}"
         assert lists[i].tolist() == bg.band_list().numpy().tolist(), f"grid {i}"
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64", "f16s"])
+@pytest.mark.parametrize("dims", [(96, 80, 72), (100, 84, 76)])
+def test_incremental_rebuild_equals_full_build_all_storages(precision, dims):
+    """Every storage precision, whole and partial tiles at the high faces:
+    window by window of a moving sphere union, the rescan of the previous band
+    gives the full scan's list, bit for bit."""
+    nx, ny, nz = dims
+    rng = np.random.default_rng(sum(dims))
+    dx = 1.0 / max(dims)
+    centers = rng.uniform(0.3, 0.7, size=(3, 3)) * np.array([nx, ny, nz]) * dx
+    phi = W.sphere_union((nz, ny, nx), dx, centers, rng.uniform(0.1, 0.2, 3) * max(dims) * dx)
+    F = (0.8 * rng.uniform(-1, 1, phi.shape)).astype(np.float32)
+    gamma = 6 * dx
+    s = np.float32(gamma)
+    if precision == "f32":
+        host_phi, Fh, scale = phi.astype(np.float32), F, None
+    elif precision == "f64":
+        host_phi, Fh, scale = phi, F.astype(np.float64), None
+    else:
+        host_phi, Fh, scale = W.quantize_f16s(phi.astype(np.float32), s), F, float(s)
+    dt = 0.5 * dx
+    full = BandGrid(dims, (8, 8, 8), precision)
+    inc = BandGrid(dims, (8, 8, 8), precision)
+    pd, fd = torch.from_numpy(np.ascontiguousarray(host_phi)).to(dev()), to_dev(Fh)
+    inc.build(pd, gamma, dilate=True, scale=scale)
+    for w in range(5):
+        full.build(pd, gamma, dilate=True, scale=scale)
+        if w > 0:
+            inc.rebuild(pd, gamma, prev_t, prev_n, scale=scale)
+        assert inc.band_list().numpy().tolist() == full.band_list().numpy().tolist(), w
+        prev_t, prev_n = inc.tiles.clone(), inc.ntiles.clone()
+        full.step(pd, fd, dx, dt, 10, scale=scale)
