@@ -130,6 +130,37 @@ def upwind_steps(phi, F, dx, dt, tiles, nsteps, tile=(8, 8, 8)):
     return p
 
 
+def cutoff(phi, beta, gamma):
+    """The cut-off function c of Eq. 8: 1 for |phi| <= beta, the cubic
+    (|phi| - gamma)^2 (2|phi| + gamma - 3 beta) / (gamma - beta)^3 for
+    beta < |phi| <= gamma, 0 beyond (NaN -> 0).
+
+    Pinned by its closed forms (c(beta) = 1, c(gamma) = 0, c = 1/2 midway,
+    flat at both ends, non-increasing) and by hand-computed values at the
+    points of a plane.
+    """
+    a = np.abs(np.asarray(phi, dtype=np.float64))
+    mid = (a - gamma) ** 2 * (2 * a + gamma - 3 * beta) / (gamma - beta) ** 3
+    return np.where(a <= beta, 1.0, np.where(a <= gamma, mid, 0.0))
+
+
+def cutoff_steps(phi, F, dx, dt, tiles, nsteps, beta, gamma, tile=(8, 8, 8)):
+    """``nsteps`` explicit steps of the cut-off equation of Eq. 8,
+    phi_t + c(phi) F |grad phi| = 0, with the upwind scheme of Eq. 3-5 on the
+    listed tiles, FP64.
+
+    Each step takes the speed c(phi^n) F from the step-n field, then one
+    Jacobi step of the plain scheme with that speed.  Pinned by the plane
+    closed form, by c = 1 everywhere (the plain steps, bitwise) and by the
+    frozen points |phi| >= gamma.
+    """
+    p = np.array(phi, dtype=np.float64, copy=True)
+    f = np.asarray(F, dtype=np.float64)
+    for _ in range(int(nsteps)):
+        p = upwind_steps(p, cutoff(p, beta, gamma) * f, dx, dt, tiles, 1, tile)
+    return p
+
+
 def decide_precision(phi64, precision):
     """The field on which the band decision is taken, in the kernel's precision.
 
@@ -145,12 +176,14 @@ def decide_precision(phi64, precision):
 
 
 def run_band(phi0, F, dx, dt, gamma, nsteps, window=10, tile=(8, 8, 8), precision="f32",
-             dilate=True, record_tiles=False):
+             dilate=True, record_tiles=False, beta=None):
     """The narrow-band driver (Steps 1-2 of the algorithm in Sec. 1.1), FP64.
 
     Every ``window`` steps the band U is rebuilt from the current state
-    (decision in ``precision``), then the state is advanced on U.  Returns the
-    final FP64 field and, if asked, the tile list of every window.
+    (decision in ``precision``), then the state is advanced on U: by the plain
+    steps of Eq. 3-5, or, with ``beta`` given, by the cut-off steps of Eq. 8
+    with the band's gamma.  Returns the final FP64 field and, if asked, the
+    tile list of every window.
     """
     phi = np.array(phi0, dtype=np.float64, copy=True)
     lists = []
@@ -161,7 +194,10 @@ def run_band(phi0, F, dx, dt, gamma, nsteps, window=10, tile=(8, 8, 8), precisio
         tiles = band_tiles(decide_precision(phi, precision), tile, gam, dilate)
         if record_tiles:
             lists.append(tiles)
-        phi = upwind_steps(phi, F, dx, dt, tiles, n, tile)
+        if beta is None:
+            phi = upwind_steps(phi, F, dx, dt, tiles, n, tile)
+        else:
+            phi = cutoff_steps(phi, F, dx, dt, tiles, n, beta, gamma, tile)
         done += n
     return (phi, lists) if record_tiles else phi
 

@@ -94,12 +94,8 @@ def conv3_backward(x, w, gout):
     return gxp[:, 1:-1, 1:-1, 1:-1], gw, gb
 
 
-def cutoff(phi, beta, gamma):
-    """The cut-off function of Eq. 8 (1 inside |phi| <= beta, a cubic down to
-    0 at |phi| = gamma, 0 beyond)."""
-    a = np.abs(np.asarray(phi, dtype=np.float64))
-    mid = (a - gamma) ** 2 * (2 * a + gamma - 3 * beta) / (gamma - beta) ** 3
-    return np.where(a <= beta, 1.0, np.where(a <= gamma, mid, 0.0))
+# The cut-off function of Eq. 8 (defined with the band driver's steps).
+cutoff = oracle.cutoff
 
 
 def silu(z):
