@@ -11,10 +11,12 @@ previous band afterwards; dilation; ordered compaction) and 10 upwind steps
 driver call.  Inputs are resident in HBM before the timed region starts; the
 run restarts from the initial field after the warm-up windows.
 
-Other workloads (--workload): torus1024_f16s, the 1024^3 torus with phi
-stored as scaled FP16 (500 steps); batch256, 256 uneven grids (32^3..192^3,
-random ellipsoids, tile shapes from the autotuner, 100 steps) captured in one
-HIP graph and timed on replay.
+Other workloads (--workload): spheres512_cutoff, the default run with the
+cut-off of Eq. 8 in every step (speed c(phi) F, beta = 3 dx, gamma = 6 dx,
+the band's); torus1024_f16s, the 1024^3 torus with phi stored as scaled FP16
+(500 steps); batch256, 256 uneven grids (32^3..192^3, random ellipsoids, tile
+shapes from the autotuner, 100 steps) captured in one HIP graph and timed on
+replay.
 
 Prints one JSON line: whole-job band GLUPS (band point-updates per second
 including rebuilds), the roofline of the dominant kernel (the band step,
@@ -43,8 +45,9 @@ def parse():
                          "workload: 20 for spheres512, 50 for torus1024_f16s, 10 for batch256)")
     ap.add_argument("--warmup", type=int, default=2, help="untimed warm-up windows")
     ap.add_argument("--workload", default="spheres512",
-                    choices=["spheres512", "torus1024_f16s", "batch256"],
+                    choices=["spheres512", "spheres512_cutoff", "torus1024_f16s", "batch256"],
                     help="spheres512: the 512^3 FP32 three-sphere run (default); "
+                         "spheres512_cutoff: the same with the cut-off of Eq. 8; "
                          "torus1024_f16s: the 1024^3 scaled-FP16 torus run; "
                          "batch256: 256 uneven grids, autotuned tile shapes, one HIP graph")
     ap.add_argument("--n", type=int, default=None, help="grid points per axis (single grids)")
@@ -55,7 +58,8 @@ def parse():
                          "(the reference for calibrating the traffic counters)")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = {"spheres512": 20, "torus1024_f16s": 50, "batch256": 10}[args.workload]
+        args.steps = {"spheres512": 20, "spheres512_cutoff": 20, "torus1024_f16s": 50,
+                      "batch256": 10}[args.workload]
     return args
 
 
@@ -88,8 +92,9 @@ def measured_traffic(kernel, workload, digest):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, budget_s):
-    """The oracle (FP64, OpenMP) on whole windows of the same workload."""
+def cpu_baseline(wl, budget_s, beta=None):
+    """The oracle (FP64, OpenMP) on whole windows of the same workload (with
+    the cut-off steps when beta is given)."""
     import oracle
 
     if budget_s <= 0:
@@ -100,7 +105,11 @@ def cpu_baseline(wl, budget_s):
     t0 = time.perf_counter()
     while True:
         tiles = oracle.band_tiles(phi.astype(np.float32), wl.tile, g32, dilate=True)
-        phi = oracle.upwind_steps(phi, wl.F, wl.dx, wl.dt, tiles, wl.window, wl.tile)
+        if beta is None:
+            phi = oracle.upwind_steps(phi, wl.F, wl.dx, wl.dt, tiles, wl.window, wl.tile)
+        else:
+            phi = oracle.cutoff_steps(phi, wl.F, wl.dx, wl.dt, tiles, wl.window, beta,
+                                      float(g32), wl.tile)
         updates += int(tiles.size) * int(np.prod(wl.tile)) * wl.window
         windows += 1
         if time.perf_counter() - t0 >= budget_s or windows * wl.window >= wl.nsteps:
@@ -112,16 +121,20 @@ def cpu_baseline(wl, budget_s):
         "cores": oracle.max_threads(),
         "kind": "oracle",
         "sample": f"first {windows} window(s) x {wl.window} steps (band rebuild + FP64 "
-                  f"upwind steps) of the {wl.name} workload, {elapsed:.1f} s",
+                  f"{'cut-off ' if beta is not None else ''}upwind steps) of the "
+                  f"{wl.name}{'_cutoff' if beta is not None else ''} workload, {elapsed:.1f} s",
     }
 
 
 def _single_grid(args, torch, ls, W, BandGrid, dev):
     """The band driver on one grid: (result fields, workload, precision)."""
-    if args.workload == "spheres512":
+    beta = None
+    if args.workload in ("spheres512", "spheres512_cutoff"):
         n = args.n or 512
         wl = W.three_spheres_f32(n, steps=10 * args.steps)
         prec, phi_host, scale = "f32", wl.phi, None
+        if args.workload == "spheres512_cutoff":
+            beta = float(np.float32(3 * wl.dx))
     else:
         n = args.n or 1024
         wl = W.torus_grf(n, steps=10 * args.steps)
@@ -142,7 +155,7 @@ def _single_grid(args, torch, ls, W, BandGrid, dev):
     tile_steps = torch.zeros(1, dtype=torch.int64, device=dev)
     if args.warmup > 0:
         bg.run(phi, F, wl.dx, wl.dt, gamma, args.warmup * wl.window, wl.window, scale=scale,
-               tile_steps=tile_steps, stream=stream)
+               tile_steps=tile_steps, stream=stream, beta=beta)
     phi.copy_(phi0)
     tile_steps.zero_()
     torch.cuda.synchronize()
@@ -151,7 +164,7 @@ def _single_grid(args, torch, ls, W, BandGrid, dev):
     ls.ls_stats_enable(True)
     t0 = time.perf_counter()
     bg.run(phi, F, wl.dx, wl.dt, gamma, args.steps * wl.window, wl.window, scale=scale,
-           tile_steps=tile_steps, stream=stream)
+           tile_steps=tile_steps, stream=stream, beta=beta)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ls.ls_stats_enable(False)
@@ -167,7 +180,7 @@ def _single_grid(args, torch, ls, W, BandGrid, dev):
     torch.cuda.synchronize()
     ls.ls_graph_begin(side)
     bg.run(phi, F, wl.dx, wl.dt, gamma, args.steps * wl.window, wl.window, scale=scale,
-           tile_steps=tile_steps, stream=side)
+           tile_steps=tile_steps, stream=side, beta=beta)
     graph = ls.ls_graph_end(side)
     try:
         phi.copy_(phi0)
@@ -191,10 +204,11 @@ def _single_grid(args, torch, ls, W, BandGrid, dev):
         "upd_ms": upd_ms,
         "launches": launches,
         "config": {
-            "workload": wl.name,
+            "workload": wl.name + ("_cutoff" if beta is not None else ""),
             "grid": [n, n, n],
             "tile": list(wl.tile),
             "band_halfwidth_dx": 6,
+            **({"cutoff_beta_dx": 3, "cutoff_gamma_dx": 6} if beta is not None else {}),
             "steps_per_window": wl.window,
             "upwind_steps": args.steps * wl.window,
             "storage": prec,
@@ -206,9 +220,11 @@ def _single_grid(args, torch, ls, W, BandGrid, dev):
             "timed_as": "one HIP graph replay of the whole driver call",
             "eager_value": round(updates / eager_s / 1e9, 3),
         },
-        "kernel": ("ls::upwind_vec_kernel (f32, 8x8x8 tiles, 32-point rows, 16-byte accesses)"
+        "kernel": ("ls::upwind_vec_kernel (f32, 8x8x8 tiles, 32-point rows, 16-byte accesses"
+                   + (", cut-off of Eq. 8)" if beta is not None else ")")
                    if prec == "f32" else
                    "ls::upwind_vec_kernel (f16s, 8x8x8 tiles, 64-point rows, 8-byte accesses)"),
+        "beta": beta,
         "data": ("synthetic (seeded three-sphere signed distance, sinusoidal speed)"
                  if prec == "f32" else
                  "synthetic (torus signed distance stored as scaled FP16, speed 1 + 0.3 GRF)"),
@@ -357,8 +373,8 @@ def main():
         torch.cuda.synchronize()
         del a, b
     if rank == 0:
-        result["cpu_baseline"] = (cpu_baseline(wl, args.cpu_seconds)
-                                  if args.workload == "spheres512" else None)
+        result["cpu_baseline"] = (cpu_baseline(wl, args.cpu_seconds, f.get("beta"))
+                                  if args.workload.startswith("spheres512") else None)
         print(json.dumps(result), flush=True)
     return 0
 

@@ -178,6 +178,53 @@ int ls_band_run_f16s(uint16_t *phi_h, float scale, const float *F, const ls_grid
                      uint16_t *scratch, void *workspace, int64_t workspace_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Cut-off step and driver (Sec. 1.1, Eq. 7-8): the same calls as
+ * ls_upwind_step_* and ls_band_run_* for the cut-off equation
+ * phi_t + c(phi) F |grad phi| = 0, with
+ *   c(phi) = 1                                                 |phi| <= beta
+ *          = (|phi| - gamma)^2 (2|phi| + gamma - 3 beta) / (gamma - beta)^3
+ *                                                beta < |phi| <= gamma
+ *          = 0                                 |phi| > gamma (and NaN)
+ * taken at each point's step-n value: every step is the upwind step of
+ * Eq. 3-5 with the speed c(phi^n) F.  Points with |phi| >= gamma, and points
+ * whose c(phi) F is zero, keep their bits.  beta and gamma are in phi's units
+ * (for f16s: of phi, not of h); ls_band_run_cutoff_* uses its gamma for the
+ * tube of Eq. 6 as well.  Arithmetic of c: f64 the definition term by term
+ * ((gamma - beta)^3 formed on the host in FP64); f32 and f16s in FP32 with the
+ * reciprocal of (gamma - beta)^3.  Requires 0 < beta < gamma < inf
+ * (LS_ERR_ARG otherwise); the other arguments, buffers and errors as for the
+ * plain calls.  The two-step kernel of ls_tuning.temporal is not used here.
+ * ------------------------------------------------------------------------- */
+int ls_upwind_step_cutoff_f32(float *phi, const float *F, const ls_grid *g, float dx, float dt,
+                              float beta, float gamma, const int32_t *tiles,
+                              const int32_t *ntiles_dev, int nsteps, float *scratch,
+                              void *workspace, int64_t workspace_bytes, void *stream);
+int ls_upwind_step_cutoff_f64(double *phi, const double *F, const ls_grid *g, double dx,
+                              double dt, double beta, double gamma, const int32_t *tiles,
+                              const int32_t *ntiles_dev, int nsteps, double *scratch,
+                              void *workspace, int64_t workspace_bytes, void *stream);
+int ls_upwind_step_cutoff_f16s(uint16_t *phi_h, float scale, const float *F, const ls_grid *g,
+                               float dx, float dt, float beta, float gamma,
+                               const int32_t *tiles, const int32_t *ntiles_dev, int nsteps,
+                               uint16_t *scratch, void *workspace, int64_t workspace_bytes,
+                               void *stream);
+int ls_band_run_cutoff_f32(float *phi, const float *F, const ls_grid *g, float dx, float dt,
+                           float beta, float gamma, int nsteps, int window, int32_t *tiles,
+                           int64_t capacity, int32_t *ntiles_dev, int64_t *tile_steps_dev,
+                           float *scratch, void *workspace, int64_t workspace_bytes,
+                           void *stream);
+int ls_band_run_cutoff_f64(double *phi, const double *F, const ls_grid *g, double dx, double dt,
+                           double beta, double gamma, int nsteps, int window, int32_t *tiles,
+                           int64_t capacity, int32_t *ntiles_dev, int64_t *tile_steps_dev,
+                           double *scratch, void *workspace, int64_t workspace_bytes,
+                           void *stream);
+int ls_band_run_cutoff_f16s(uint16_t *phi_h, float scale, const float *F, const ls_grid *g,
+                            float dx, float dt, float beta, float gamma, int nsteps, int window,
+                            int32_t *tiles, int64_t capacity, int32_t *ntiles_dev,
+                            int64_t *tile_steps_dev, uint16_t *scratch, void *workspace,
+                            int64_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Batches: many grids of uneven size, advanced in lockstep by the same
  * launches (the narrow-band driver above, applied to every grid at once).
  *

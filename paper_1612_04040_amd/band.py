@@ -50,9 +50,23 @@ class BandGrid:
         return self.tiles[:n].cpu()
 
     # -- steps ----------------------------------------------------------------
-    def step(self, phi, F, dx, dt, nsteps, scale=None, tiles=None, ntiles=None, stream=None):
+    def step(self, phi, F, dx, dt, nsteps, scale=None, tiles=None, ntiles=None, stream=None,
+             cutoff=None):
+        """nsteps band steps; ``cutoff=(beta, gamma)`` takes the cut-off steps of Eq. 8."""
         t = self.tiles if tiles is None else tiles
         n = self.ntiles if ntiles is None else ntiles
+        if cutoff is not None:
+            b, c = cutoff
+            if self.precision == "f32":
+                ls.ls_upwind_step_cutoff_f32(phi, F, self.g, dx, dt, b, c, t, n, nsteps,
+                                             self.scratch, self.ws, self.ws_bytes, stream)
+            elif self.precision == "f64":
+                ls.ls_upwind_step_cutoff_f64(phi, F, self.g, dx, dt, b, c, t, n, nsteps,
+                                             self.scratch, self.ws, self.ws_bytes, stream)
+            else:
+                ls.ls_upwind_step_cutoff_f16s(phi, scale, F, self.g, dx, dt, b, c, t, n, nsteps,
+                                              self.scratch, self.ws, self.ws_bytes, stream)
+            return
         if self.precision == "f32":
             ls.ls_upwind_step_f32(phi, F, self.g, dx, dt, t, n, nsteps, self.scratch, self.ws,
                                   self.ws_bytes, stream)
@@ -77,7 +91,23 @@ class BandGrid:
                                     self.ws_bytes, stream)
 
     def run(self, phi, F, dx, dt, gamma, nsteps, window=10, scale=None, tile_steps=None,
-            stream=None):
+            stream=None, beta=None):
+        """The windowed driver; with ``beta`` the cut-off steps of Eq. 8 (with gamma)."""
+        if beta is not None:
+            if self.precision == "f32":
+                ls.ls_band_run_cutoff_f32(phi, F, self.g, dx, dt, beta, gamma, nsteps, window,
+                                          self.tiles, self.capacity, self.ntiles, tile_steps,
+                                          self.scratch, self.ws, self.ws_bytes, stream)
+            elif self.precision == "f64":
+                ls.ls_band_run_cutoff_f64(phi, F, self.g, dx, dt, beta, gamma, nsteps, window,
+                                          self.tiles, self.capacity, self.ntiles, tile_steps,
+                                          self.scratch, self.ws, self.ws_bytes, stream)
+            else:
+                ls.ls_band_run_cutoff_f16s(phi, scale, F, self.g, dx, dt, beta, gamma, nsteps,
+                                           window, self.tiles, self.capacity, self.ntiles,
+                                           tile_steps, self.scratch, self.ws, self.ws_bytes,
+                                           stream)
+            return
         if self.precision == "f32":
             ls.ls_band_run_f32(phi, F, self.g, dx, dt, gamma, nsteps, window, self.tiles,
                                self.capacity, self.ntiles, tile_steps, self.scratch, self.ws,

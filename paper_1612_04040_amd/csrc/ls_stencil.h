@@ -80,6 +80,25 @@ __device__ inline C upwind_point(C c, C xm, C xp, C ym, C yp, C zm, C zp, C f, C
     }
 }
 
+// The cut-off of Eq. 8 at the centre value v: 1 for |v| <= beta, the cubic
+// (|v| - gamma)^2 (2|v| + gamma - 3 beta) / (gamma - beta)^3 up to gamma, 0
+// beyond it and for NaN.  Exact form: the definition term by term, divided by
+// k = (gamma - beta)^3; fast form: times k = 1 / (gamma - beta)^3.
+template <class C, bool EXACT>
+__device__ inline C cutoff(C v, C beta, C gamma, C k) {
+    const C a = v < C(0) ? -v : v;
+    C mid;
+    if constexpr (EXACT) {
+#pragma clang fp contract(off)
+        const C m = (a - gamma) * (a - gamma);
+        const C l = (C(2) * a + gamma) - C(3) * beta;
+        mid = (m * l) / k;
+    } else {
+        mid = (a - gamma) * (a - gamma) * ((C(2) * a + gamma) - C(3) * beta) * k;
+    }
+    return a <= beta ? C(1) : (a <= gamma ? mid : C(0));
+}
+
 template <class S, class FT>
 struct StepArgs {
     const S *cur;
@@ -92,6 +111,9 @@ struct StepArgs {
     const BatchInst *inst;    // batch: grid descriptors (record word 7 = grid), else null
     const uint8_t *umap;      // single grid: U membership per tile (two-step kernel), else null
     typename Codec<S>::C dx, dt, dtdx, scale;
+    // cut-off of Eq. 8 (kernels built with CUT only): beta, gamma and
+    // k = (gamma - beta)^3 (exact form) or 1 / (gamma - beta)^3 (fast form)
+    typename Codec<S>::C cut_beta, cut_gamma, cut_k;
 };
 
 // Slice [w0, w1) of the items [first, end) for this block: contiguous and
@@ -151,7 +173,7 @@ struct FastCfg {
 // outside the band from phi (its value frozen for the call), one outside the
 // grid is the clamped point inside the item (zero-gradient boundary).
 template <class S, class FT, bool EXACT, int TX, int TY, int TZ, int R, bool BATCH, bool PARTIAL,
-          bool PIPE>
+          bool PIPE, bool CUT = false>
 __global__ __launch_bounds__((FastCfg<S, FT, TX, TY, TZ, R>::NT)) void upwind_fast_kernel(
     StepGeom g, StepArgs<S, FT> a) {
     using K = FastCfg<S, FT, TX, TY, TZ, R>;
@@ -325,7 +347,8 @@ __global__ __launch_bounds__((FastCfg<S, FT, TX, TY, TZ, R>::NT)) void upwind_fa
         for (int q = 0; q < NOWN; ++q) {
             if (PARTIAL && !(ly0 + dly(q) < it.H && lz0 + dlz(q) < it.D)) continue;
             const int o = lbase + dlz(q) * SXY + dly(q) * SX;
-            const C f = static_cast<C>(r.fv[q]);
+            C f = static_cast<C>(r.fv[q]);
+            if constexpr (CUT) f = cutoff<C, EXACT>(box[o], a.cut_beta, a.cut_gamma, a.cut_k) * f;
             const C v = upwind_point<C, EXACT>(box[o], box[o - 1], box[o + 1], box[o - SX],
                                                box[o + SX], box[o - SXY], box[o + SXY], f, it.dx,
                                                it.dt, it.dtdx);
@@ -416,7 +439,7 @@ struct VecCfg {
     static_assert(2 * ROWS <= NT, "x-face points exceed one per thread");
 };
 
-template <class S, int TY, int TZ, int R, bool PARTIAL>
+template <class S, int TY, int TZ, int R, bool PARTIAL, bool CUT = false>
 __global__ __launch_bounds__((VecCfg<TY, TZ, R>::NT)) void upwind_vec_kernel(
     StepGeom g, StepArgs<S, float> a) {
     using K = VecCfg<TY, TZ, R>;
@@ -543,11 +566,14 @@ __global__ __launch_bounds__((VecCfg<TY, TZ, R>::NT)) void upwind_vec_kernel(
             for (int q = 0; q < NOWN; ++q) {
                 if (PARTIAL && !(ly0 < H && lz0 + q * DZ < D)) continue;
                 const int o0 = lbase + q * DZ * SXY;
-                const float f4[4] = {fv[q].x, fv[q].y, fv[q].z, fv[q].w};
+                float f4[4] = {fv[q].x, fv[q].y, fv[q].z, fv[q].w};
                 S out[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int o = o0 + e;
+                    if constexpr (CUT)
+                        f4[e] = cutoff<float, false>(box[o], a.cut_beta, a.cut_gamma, a.cut_k) *
+                                f4[e];
                     const float v = upwind_point<float, false>(
                         box[o], box[o - 1], box[o + 1], box[o - SX], box[o + SX], box[o - SXY],
                         box[o + SXY], f4[e], a.dx, a.dt, a.dtdx);

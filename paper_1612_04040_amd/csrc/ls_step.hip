@@ -46,7 +46,7 @@ struct Shape {
     __device__ static inline int sx(const StepGeom &g) { return fixed ? CR * CTX + 2 : g.sx; }
 };
 
-template <class S, class FT, bool EXACT, int NOWN, int NHALO, class SH>
+template <class S, class FT, bool EXACT, int NOWN, int NHALO, class SH, bool CUT>
 __global__ __launch_bounds__(kBlock) void upwind_kernel(StepGeom g, StepArgs<S, FT> a) {
     using C = typename Codec<S>::C;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -186,7 +186,8 @@ __global__ __launch_bounds__(kBlock) void upwind_kernel(StepGeom g, StepArgs<S, 
             if (col_ok && row < rows && ly < H && lz < D) {
                 const int o = (lz + 1) * sxy + (ly + 1) * sx + lx + 1;
                 const C c = box[o];
-                const C f = static_cast<C>(fv[q]);
+                C f = static_cast<C>(fv[q]);
+                if constexpr (CUT) f = cutoff<C, EXACT>(c, a.cut_beta, a.cut_gamma, a.cut_k) * f;
                 S out = raw[q];
                 if (f != C(0)) {
                     const C v = upwind_point<C, EXACT>(c, box[o - 1], box[o + 1], box[o - sx],
@@ -331,19 +332,20 @@ using UpwindFn = void (*)(StepGeom, StepArgs<S, FT>);
 
 using DynShape = Shape<0, 0, 0, 0>;
 
-template <class S, class FT, bool EXACT, int NOWN>
+template <class S, class FT, bool EXACT, int NOWN, bool CUT>
 static UpwindFn<S, FT, EXACT> select_halo(int nhalo) {
     switch (nhalo) {
-    case 1: return upwind_kernel<S, FT, EXACT, NOWN, 1, DynShape>;
-    case 2: return upwind_kernel<S, FT, EXACT, NOWN, 2, DynShape>;
-    case 4: return upwind_kernel<S, FT, EXACT, NOWN, 4, DynShape>;
-    default: return upwind_kernel<S, FT, EXACT, NOWN, 8, DynShape>;
+    case 1: return upwind_kernel<S, FT, EXACT, NOWN, 1, DynShape, CUT>;
+    case 2: return upwind_kernel<S, FT, EXACT, NOWN, 2, DynShape, CUT>;
+    case 4: return upwind_kernel<S, FT, EXACT, NOWN, 4, DynShape, CUT>;
+    default: return upwind_kernel<S, FT, EXACT, NOWN, 8, DynShape, CUT>;
     }
 }
 
 // Kernel for a launch: a compile-time specialisation for the common tile
-// shapes and run lengths, else the run-time-shape kernel.
-template <class S, class FT, bool EXACT>
+// shapes and run lengths, else the run-time-shape kernel.  CUT: the cut-off
+// step of Eq. 8 (the same kernels with the speed scaled by c(phi)).
+template <class S, class FT, bool EXACT, bool CUT = false>
 static UpwindFn<S, FT, EXACT> select_upwind_kernel(const StepGeom &sg, int nown, int nhalo,
                                                    size_t *lds, int *threads,
                                                    bool aligned = false) {
@@ -356,13 +358,13 @@ static UpwindFn<S, FT, EXACT> select_upwind_kernel(const StepGeom &sg, int nown,
             if (sg.R == 4) {
                 *lds = VecCfg<8, 8, 4>::lds;
                 *threads = VecCfg<8, 8, 4>::NT;
-                return whole_yz ? upwind_vec_kernel<S, 8, 8, 4, false>
-                                : upwind_vec_kernel<S, 8, 8, 4, true>;
+                return whole_yz ? upwind_vec_kernel<S, 8, 8, 4, false, CUT>
+                                : upwind_vec_kernel<S, 8, 8, 4, true, CUT>;
             }
             *lds = VecCfg<8, 8, 8>::lds;
             *threads = VecCfg<8, 8, 8>::NT;
-            return whole_yz ? upwind_vec_kernel<S, 8, 8, 8, false>
-                            : upwind_vec_kernel<S, 8, 8, 8, true>;
+            return whole_yz ? upwind_vec_kernel<S, 8, 8, 8, false, CUT>
+                            : upwind_vec_kernel<S, 8, 8, 8, true, CUT>;
         }
     }
     const bool pipe = use_pipeline(int64_t(sg.nx) * sg.ny * sg.nz * int64_t(sizeof(S)), sg.R);
@@ -371,10 +373,10 @@ static UpwindFn<S, FT, EXACT> select_upwind_kernel(const StepGeom &sg, int nown,
         *lds = FastCfg<S, FT, TX_, TY_, TZ_, R_>::lds;                                      \
         *threads = FastCfg<S, FT, TX_, TY_, TZ_, R_>::NT;                                   \
         if (whole_yz)                                                                       \
-            return pipe ? upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, false, true>  \
-                        : upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, false, false>; \
-        return pipe ? upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, true, true>        \
-                    : upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, true, false>;      \
+            return pipe ? upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, false, true, CUT>  \
+                        : upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, false, false, CUT>; \
+        return pipe ? upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, true, true, CUT>        \
+                    : upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, true, false, CUT>;      \
     }
     LS_FAST(8, 8, 8, 4)
     LS_FAST(8, 8, 8, 2)
@@ -387,13 +389,13 @@ static UpwindFn<S, FT, EXACT> select_upwind_kernel(const StepGeom &sg, int nown,
     LS_FAST(4, 4, 4, 8)
 #undef LS_FAST
     if (sg.tx == 8 && sg.ty == 8 && sg.tz == 8 && sg.R == 4)
-        return upwind_kernel<S, FT, EXACT, 8, 4, Shape<8, 8, 8, 4>>;
+        return upwind_kernel<S, FT, EXACT, 8, 4, Shape<8, 8, 8, 4>, CUT>;
     switch (nown) {
-    case 1: return select_halo<S, FT, EXACT, 1>(nhalo);
-    case 2: return select_halo<S, FT, EXACT, 2>(nhalo);
-    case 4: return select_halo<S, FT, EXACT, 4>(nhalo);
-    case 8: return select_halo<S, FT, EXACT, 8>(nhalo);
-    default: return select_halo<S, FT, EXACT, 16>(nhalo);
+    case 1: return select_halo<S, FT, EXACT, 1, CUT>(nhalo);
+    case 2: return select_halo<S, FT, EXACT, 2, CUT>(nhalo);
+    case 4: return select_halo<S, FT, EXACT, 4, CUT>(nhalo);
+    case 8: return select_halo<S, FT, EXACT, 8, CUT>(nhalo);
+    default: return select_halo<S, FT, EXACT, 16, CUT>(nhalo);
     }
 }
 
@@ -478,14 +480,32 @@ static int step_args(S *phi, const FT *F, const ls_grid *grid, typename Codec<S>
     return make_step_geom<S>(*G, sg, &lds);
 }
 
+// The cut-off of Eq. 8 for a step call: off (the plain step) unless `on`.
+template <class C>
+struct CutOff {
+    bool on = false;
+    C beta = C(0), gamma = C(0);
+};
+
+template <class C>
+static int check_cutoff(const CutOff<C> &cut) {
+    if (cut.on && !(cut.beta > C(0) && cut.beta < cut.gamma && cut.gamma < C(INFINITY))) {
+        set_error("cut-off: need 0 < beta < gamma < inf");
+        return LS_ERR_ARG;
+    }
+    return LS_OK;
+}
+
 // nsteps launches of the step kernel on the plan held by the workspace (the
 // update map, the work-item records and their count), then the copy-back of
-// the band when nsteps is odd.
+// the band when nsteps is odd.  With the cut-off on, the kernels scale the
+// speed by c(phi) of the centre point's step-n value.
 template <class S, class FT>
 static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const Geom &G,
                          const StepGeom &sg, typename Codec<S>::C dx, typename Codec<S>::C dt,
                          int nsteps, S *scratch, uint8_t *ws, hipStream_t stream,
-                         bool land_in_scratch = false) {
+                         bool land_in_scratch = false,
+                         const CutOff<typename Codec<S>::C> &cut = {}) {
     using C = typename Codec<S>::C;
     constexpr bool EXACT = sizeof(C) == 8;
     if (nsteps == 0) return LS_OK;
@@ -500,7 +520,10 @@ static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const 
     const bool aligned = reinterpret_cast<uintptr_t>(phi) % 16 == 0 &&
                          reinterpret_cast<uintptr_t>(scratch) % 16 == 0 &&
                          reinterpret_cast<uintptr_t>(F) % 16 == 0;
-    auto kernel = select_upwind_kernel<S, FT, EXACT>(sg, nown, nhalo, &lds, &threads, aligned);
+    auto kernel = cut.on ? select_upwind_kernel<S, FT, EXACT, true>(sg, nown, nhalo, &lds,
+                                                                     &threads, aligned)
+                         : select_upwind_kernel<S, FT, EXACT, false>(sg, nown, nhalo, &lds,
+                                                                      &threads, aligned);
     int nblocks = 0;
     int rc;
     if ((rc = persistent_grid(kernel, threads, lds, &nblocks, nullptr, G.ntiles)) != LS_OK)
@@ -518,11 +541,20 @@ static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const 
     args.dt = dt;
     args.dtdx = static_cast<C>(static_cast<double>(dt) / static_cast<double>(dx));
     args.scale = scale;
+    args.cut_beta = cut.beta;
+    args.cut_gamma = cut.gamma;
+    args.cut_k = C(0);
+    if (cut.on) {
+        // (gamma - beta)^3 from the arguments' values, in FP64
+        const double d3 = std::pow(static_cast<double>(cut.gamma) - static_cast<double>(cut.beta), 3.0);
+        args.cut_k = EXACT ? static_cast<C>(d3) : static_cast<C>(1.0 / d3);
+    }
     // pairs of steps in one launch where the two-step kernel applies, then a
     // single step if one is left; one pair of timing events around them all
     size_t lds2 = 0;
     int threads2 = 0, nblocks2 = 0;
-    auto kernel2 = select_upwind2_kernel<S, FT, EXACT>(sg, aligned, &lds2, &threads2);
+    auto kernel2 = cut.on ? nullptr : select_upwind2_kernel<S, FT, EXACT>(sg, aligned, &lds2,
+                                                                          &threads2);
     const int pairs = (kernel2 && nsteps >= 2 && !land_in_scratch) ? nsteps / 2 : 0;
     const int singles = nsteps - 2 * pairs;
     const int launches = pairs + singles;
@@ -572,11 +604,13 @@ template <class S, class FT>
 static int upwind_step(S *phi, const FT *F, typename Codec<S>::C scale, const ls_grid *grid,
                        typename Codec<S>::C dx, typename Codec<S>::C dt, const int32_t *tiles,
                        const int32_t *ntiles_dev, int nsteps, S *scratch, void *workspace,
-                       int64_t ws_bytes, hipStream_t stream) {
+                       int64_t ws_bytes, hipStream_t stream,
+                       const CutOff<typename Codec<S>::C> &cut = {}) {
     Geom G;
     StepGeom sg;
     int rc = step_args<S, FT>(phi, F, grid, dx, dt, nsteps, scratch, workspace, ws_bytes, &G, &sg);
     if (rc != LS_OK) return rc;
+    if ((rc = check_cutoff(cut)) != LS_OK) return rc;
     if (!tiles || !ntiles_dev) {
         set_error("step: tiles and ntiles_dev must be non-NULL");
         return LS_ERR_ARG;
@@ -593,7 +627,8 @@ static int upwind_step(S *phi, const FT *F, typename Codec<S>::C scale, const ls
                        ntiles_dev, static_cast<int>(G.ntiles));
     LS_LAUNCH_CHECK("map_set_kernel");
     if ((rc = build_plan(G, ws, nullptr, nullptr, stream)) != LS_OK) return rc;
-    return upwind_launch<S, FT>(phi, F, scale, G, sg, dx, dt, nsteps, scratch, ws, stream);
+    return upwind_launch<S, FT>(phi, F, scale, G, sg, dx, dt, nsteps, scratch, ws, stream, false,
+                                cut);
 }
 
 template <class S, class FT>
@@ -627,13 +662,14 @@ static int launch_info(const ls_grid *grid, int32_t *blocks, int32_t *lds_bytes,
 // that band is unchanged, so no tile outside it can join the tube); each
 // build leaves the step plan in the workspace, so the steps need no
 // preparation of their own.  The band lists alternate between the caller's
-// buffer and the workspace so that the last one lands in `tiles`.
+// buffer and the workspace so that the last one lands in `tiles`.  With the
+// cut-off on (Eq. 8) its gamma is the band's.
 template <class S, class FT>
 static int band_run(S *phi, const FT *F, typename Codec<S>::C scale, const ls_grid *grid,
                     typename Codec<S>::C dx, typename Codec<S>::C dt, typename Codec<S>::C gamma,
                     int nsteps, int window, int32_t *tiles, int64_t capacity,
                     int32_t *ntiles_dev, int64_t *tile_steps_dev, S *scratch, void *workspace,
-                    int64_t ws_bytes, void *stream_) {
+                    int64_t ws_bytes, void *stream_, const CutOff<typename Codec<S>::C> &cut = {}) {
     if (window <= 0) {
         set_error("band run: window must be positive (got %d)", window);
         return LS_ERR_ARG;
@@ -650,6 +686,7 @@ static int band_run(S *phi, const FT *F, typename Codec<S>::C scale, const ls_gr
         set_error("band run: gamma is NaN");
         return LS_ERR_ARG;
     }
+    if ((rc = check_cutoff(cut)) != LS_OK) return rc;
     if (capacity < G.ntiles) {
         set_error("band run: capacity %lld < %lld tiles", (long long)capacity,
                   (long long)G.ntiles);
@@ -673,7 +710,8 @@ static int band_run(S *phi, const FT *F, typename Codec<S>::C scale, const ls_gr
                                  lists[cur], capacity, counts[cur], workspace, ws_bytes, stream_,
                                  true, acc);
         if (rc != LS_OK) return rc;
-        rc = upwind_launch<S, FT>(phi, F, scale, G, sg, dx, dt, n, scratch, ws, stream);
+        rc = upwind_launch<S, FT>(phi, F, scale, G, sg, dx, dt, n, scratch, ws, stream, false,
+                                  cut);
         if (rc != LS_OK) return rc;
     }
     return LS_OK;
@@ -784,6 +822,78 @@ int ls_band_run_f16s(uint16_t *phi_h, float scale, const float *F, const ls_grid
     return ls::band_run<uint16_t, float>(phi_h, F, scale, g, dx, dt, gamma, nsteps, window, tiles,
                                          capacity, ntiles_dev, tile_steps_dev, scratch, workspace,
                                          workspace_bytes, stream);
+}
+
+int ls_upwind_step_cutoff_f32(float *phi, const float *F, const ls_grid *g, float dx, float dt,
+                              float beta, float gamma, const int32_t *tiles,
+                              const int32_t *ntiles_dev, int nsteps, float *scratch,
+                              void *workspace, int64_t workspace_bytes, void *stream) {
+    ls::clear_error();
+    return ls::upwind_step<float, float>(phi, F, 1.0f, g, dx, dt, tiles, ntiles_dev, nsteps,
+                                         scratch, workspace, workspace_bytes,
+                                         static_cast<hipStream_t>(stream), {true, beta, gamma});
+}
+
+int ls_upwind_step_cutoff_f64(double *phi, const double *F, const ls_grid *g, double dx,
+                              double dt, double beta, double gamma, const int32_t *tiles,
+                              const int32_t *ntiles_dev, int nsteps, double *scratch,
+                              void *workspace, int64_t workspace_bytes, void *stream) {
+    ls::clear_error();
+    return ls::upwind_step<double, double>(phi, F, 1.0, g, dx, dt, tiles, ntiles_dev, nsteps,
+                                           scratch, workspace, workspace_bytes,
+                                           static_cast<hipStream_t>(stream), {true, beta, gamma});
+}
+
+int ls_upwind_step_cutoff_f16s(uint16_t *phi_h, float scale, const float *F, const ls_grid *g,
+                               float dx, float dt, float beta, float gamma,
+                               const int32_t *tiles, const int32_t *ntiles_dev, int nsteps,
+                               uint16_t *scratch, void *workspace, int64_t workspace_bytes,
+                               void *stream) {
+    ls::clear_error();
+    if (!(scale > 0.0f) || !(scale < INFINITY)) {
+        ls::set_error("step f16s: scale must be positive and finite");
+        return LS_ERR_ARG;
+    }
+    return ls::upwind_step<uint16_t, float>(phi_h, F, scale, g, dx, dt, tiles, ntiles_dev, nsteps,
+                                            scratch, workspace, workspace_bytes,
+                                            static_cast<hipStream_t>(stream), {true, beta, gamma});
+}
+
+int ls_band_run_cutoff_f32(float *phi, const float *F, const ls_grid *g, float dx, float dt,
+                           float beta, float gamma, int nsteps, int window, int32_t *tiles,
+                           int64_t capacity, int32_t *ntiles_dev, int64_t *tile_steps_dev,
+                           float *scratch, void *workspace, int64_t workspace_bytes,
+                           void *stream) {
+    ls::clear_error();
+    return ls::band_run<float, float>(phi, F, 1.0f, g, dx, dt, gamma, nsteps, window, tiles,
+                                      capacity, ntiles_dev, tile_steps_dev, scratch, workspace,
+                                      workspace_bytes, stream, {true, beta, gamma});
+}
+
+int ls_band_run_cutoff_f64(double *phi, const double *F, const ls_grid *g, double dx, double dt,
+                           double beta, double gamma, int nsteps, int window, int32_t *tiles,
+                           int64_t capacity, int32_t *ntiles_dev, int64_t *tile_steps_dev,
+                           double *scratch, void *workspace, int64_t workspace_bytes,
+                           void *stream) {
+    ls::clear_error();
+    return ls::band_run<double, double>(phi, F, 1.0, g, dx, dt, gamma, nsteps, window, tiles,
+                                        capacity, ntiles_dev, tile_steps_dev, scratch, workspace,
+                                        workspace_bytes, stream, {true, beta, gamma});
+}
+
+int ls_band_run_cutoff_f16s(uint16_t *phi_h, float scale, const float *F, const ls_grid *g,
+                            float dx, float dt, float beta, float gamma, int nsteps, int window,
+                            int32_t *tiles, int64_t capacity, int32_t *ntiles_dev,
+                            int64_t *tile_steps_dev, uint16_t *scratch, void *workspace,
+                            int64_t workspace_bytes, void *stream) {
+    ls::clear_error();
+    if (!(scale > 0.0f) || !(scale < INFINITY)) {
+        ls::set_error("band run f16s: scale must be positive and finite");
+        return LS_ERR_ARG;
+    }
+    return ls::band_run<uint16_t, float>(phi_h, F, scale, g, dx, dt, gamma, nsteps, window, tiles,
+                                         capacity, ntiles_dev, tile_steps_dev, scratch, workspace,
+                                         workspace_bytes, stream, {true, beta, gamma});
 }
 
 }  // extern "C"

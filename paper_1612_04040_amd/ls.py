@@ -92,6 +92,18 @@ _SIGNATURES = {
                                _VP, _VP, _I64, _VP]),
     "ls_band_run_f16s": (_I32, [_VP, _F32, _VP, _G, _F32, _F32, _F32, _I32, _I32, _VP, _I64, _VP,
                                 _VP, _VP, _VP, _I64, _VP]),
+    "ls_upwind_step_cutoff_f32": (_I32, [_VP, _VP, _G, _F32, _F32, _F32, _F32, _VP, _VP, _I32,
+                                         _VP, _VP, _I64, _VP]),
+    "ls_upwind_step_cutoff_f64": (_I32, [_VP, _VP, _G, _F64, _F64, _F64, _F64, _VP, _VP, _I32,
+                                         _VP, _VP, _I64, _VP]),
+    "ls_upwind_step_cutoff_f16s": (_I32, [_VP, _F32, _VP, _G, _F32, _F32, _F32, _F32, _VP, _VP,
+                                          _I32, _VP, _VP, _I64, _VP]),
+    "ls_band_run_cutoff_f32": (_I32, [_VP, _VP, _G, _F32, _F32, _F32, _F32, _I32, _I32, _VP, _I64,
+                                      _VP, _VP, _VP, _VP, _I64, _VP]),
+    "ls_band_run_cutoff_f64": (_I32, [_VP, _VP, _G, _F64, _F64, _F64, _F64, _I32, _I32, _VP, _I64,
+                                      _VP, _VP, _VP, _VP, _I64, _VP]),
+    "ls_band_run_cutoff_f16s": (_I32, [_VP, _F32, _VP, _G, _F32, _F32, _F32, _F32, _I32, _I32,
+                                       _VP, _I64, _VP, _VP, _VP, _VP, _I64, _VP]),
     "ls_set_tuning": (_I32, [ctypes.c_void_p]),
     "ls_get_tuning": (_I32, [ctypes.c_void_p]),
     "ls_upwind_launch_info": (_I32, [_G, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
@@ -280,6 +292,60 @@ def ls_band_run_f16s(phi_h, scale, F, g, dx, dt, gamma, nsteps, window, tiles, c
                                          nsteps, window, _ptr(tiles), capacity, _ptr(ntiles_dev),
                                          _ptr(tile_steps_dev), _ptr(scratch), _ptr(workspace),
                                          workspace_bytes, _stream(stream)))
+
+
+def ls_upwind_step_cutoff_f32(phi, F, g, dx, dt, beta, gamma, tiles, ntiles_dev, nsteps, scratch,
+                              workspace, workspace_bytes, stream=None):
+    return _check(lib().ls_upwind_step_cutoff_f32(_ptr(phi), _ptr(F), _g(g), dx, dt, beta, gamma,
+                                                  _ptr(tiles), _ptr(ntiles_dev), nsteps,
+                                                  _ptr(scratch), _ptr(workspace),
+                                                  workspace_bytes, _stream(stream)))
+
+
+def ls_upwind_step_cutoff_f64(phi, F, g, dx, dt, beta, gamma, tiles, ntiles_dev, nsteps, scratch,
+                              workspace, workspace_bytes, stream=None):
+    return _check(lib().ls_upwind_step_cutoff_f64(_ptr(phi), _ptr(F), _g(g), dx, dt, beta, gamma,
+                                                  _ptr(tiles), _ptr(ntiles_dev), nsteps,
+                                                  _ptr(scratch), _ptr(workspace),
+                                                  workspace_bytes, _stream(stream)))
+
+
+def ls_upwind_step_cutoff_f16s(phi_h, scale, F, g, dx, dt, beta, gamma, tiles, ntiles_dev, nsteps,
+                               scratch, workspace, workspace_bytes, stream=None):
+    return _check(lib().ls_upwind_step_cutoff_f16s(_ptr(phi_h), scale, _ptr(F), _g(g), dx, dt,
+                                                   beta, gamma, _ptr(tiles), _ptr(ntiles_dev),
+                                                   nsteps, _ptr(scratch), _ptr(workspace),
+                                                   workspace_bytes, _stream(stream)))
+
+
+def ls_band_run_cutoff_f32(phi, F, g, dx, dt, beta, gamma, nsteps, window, tiles, capacity,
+                           ntiles_dev, tile_steps_dev, scratch, workspace, workspace_bytes,
+                           stream=None):
+    return _check(lib().ls_band_run_cutoff_f32(_ptr(phi), _ptr(F), _g(g), dx, dt, beta, gamma,
+                                               nsteps, window, _ptr(tiles), capacity,
+                                               _ptr(ntiles_dev), _ptr(tile_steps_dev),
+                                               _ptr(scratch), _ptr(workspace), workspace_bytes,
+                                               _stream(stream)))
+
+
+def ls_band_run_cutoff_f64(phi, F, g, dx, dt, beta, gamma, nsteps, window, tiles, capacity,
+                           ntiles_dev, tile_steps_dev, scratch, workspace, workspace_bytes,
+                           stream=None):
+    return _check(lib().ls_band_run_cutoff_f64(_ptr(phi), _ptr(F), _g(g), dx, dt, beta, gamma,
+                                               nsteps, window, _ptr(tiles), capacity,
+                                               _ptr(ntiles_dev), _ptr(tile_steps_dev),
+                                               _ptr(scratch), _ptr(workspace), workspace_bytes,
+                                               _stream(stream)))
+
+
+def ls_band_run_cutoff_f16s(phi_h, scale, F, g, dx, dt, beta, gamma, nsteps, window, tiles,
+                            capacity, ntiles_dev, tile_steps_dev, scratch, workspace,
+                            workspace_bytes, stream=None):
+    return _check(lib().ls_band_run_cutoff_f16s(_ptr(phi_h), scale, _ptr(F), _g(g), dx, dt, beta,
+                                                gamma, nsteps, window, _ptr(tiles), capacity,
+                                                _ptr(ntiles_dev), _ptr(tile_steps_dev),
+                                                _ptr(scratch), _ptr(workspace), workspace_bytes,
+                                                _stream(stream)))
 
 
 def ls_stats_enable(on):

@@ -145,6 +145,29 @@ def test_step_zero_steps_launches_nothing():
     assert ls.ls_upwind_step_f32(*a.values()) == ls.LS_OK
 
 
+@pytest.mark.parametrize("fn", ["f32", "f64", "f16s"])
+def test_cutoff_errors(fn):
+    """The cut-off calls reject beta, gamma outside 0 < beta < gamma < inf on
+    the host, after the plain calls' own checks; zero steps launch nothing."""
+    g = ls.grid((64, 64, 64))
+    step = getattr(ls, f"ls_upwind_step_cutoff_{fn}")
+    run = getattr(ls, f"ls_band_run_cutoff_{fn}")
+    cap = ls.ls_grid_tiles(g)
+    ws = ls.ls_workspace_bytes(g)
+    lead = [FAKE, 0.5] if fn == "f16s" else [FAKE]
+    for beta, gamma in [(0.0, 0.06), (-0.01, 0.06), (0.06, 0.06), (0.07, 0.06),
+                        (0.03, float("inf")), (float("nan"), 0.06), (0.03, float("nan"))]:
+        a = lead + [FAKE, g, 0.01, 0.005, beta, gamma, FAKE, FAKE, 3, FAKE * 2, FAKE * 256, ws, 0]
+        assert _status(step, *a) == ls.LS_ERR_ARG, (beta, gamma)
+        a = lead + [FAKE, g, 0.01, 0.005, beta, gamma, 10, 5, FAKE, cap, FAKE, None, FAKE * 2,
+                    FAKE * 256, ws, 0]
+        assert _status(run, *a) == ls.LS_ERR_ARG, (beta, gamma)
+    a = lead + [None, g, 0.01, 0.005, 0.03, 0.06, FAKE, FAKE, 3, FAKE * 2, FAKE * 256, ws, 0]
+    assert _status(step, *a) == ls.LS_ERR_ARG  # F NULL, before the cut-off check
+    a = lead + [FAKE, g, 0.01, 0.005, 0.03, 0.06, FAKE, FAKE, 0, FAKE * 2, FAKE * 256, ws, 0]
+    assert step(*a) == ls.LS_OK
+
+
 def test_run_errors():
     g = ls.grid((32, 32, 32))
     cap = ls.ls_grid_tiles(g)
