@@ -161,6 +161,62 @@ def cutoff_steps(phi, F, dx, dt, tiles, nsteps, beta, gamma, tile=(8, 8, 8)):
     return p
 
 
+def tile_mask(dims, tiles, tile=(8, 8, 8)):
+    """Boolean (nz, ny, nx) mask of the grid points of the listed tiles."""
+    nx, ny, nz = dims
+    tx, ty, tz = tile
+    ntx, nty = -(-nx // tx), -(-ny // ty)
+    m = np.zeros((nz, ny, nx), dtype=bool)
+    for t in np.asarray(tiles, dtype=np.int64):
+        ti, tj, tk = t % ntx, (t // ntx) % nty, t // (ntx * nty)
+        m[tk * tz:(tk + 1) * tz, tj * ty:(tj + 1) * ty, ti * tx:(ti + 1) * tx] = True
+    return m
+
+
+def smoothed_sign(d, dx):
+    """S of Eq. 13: d / sqrt(d^2 + |Dd|^2 dx^2), FP64.
+
+    Dd is the central difference (d[i+1] - d[i-1]) / (2 dx) per axis with the
+    zero-gradient boundary (an index outside the grid is clamped to it), the
+    squares summed x, then y, then z; S = 0 where d = 0.  Pinned by hand
+    values on a plane, oddness and |S| < 1.
+    """
+    d = np.asarray(d, dtype=np.float64)
+    g2 = np.zeros_like(d)
+    for axis in (2, 1, 0):  # array axes of x, y, z
+        n = d.shape[axis]
+        up = np.take(d, np.minimum(np.arange(n) + 1, n - 1), axis=axis)
+        dn = np.take(d, np.maximum(np.arange(n) - 1, 0), axis=axis)
+        g2 = g2 + ((up - dn) / (2 * dx)) ** 2
+    with np.errstate(invalid="ignore", divide="ignore"):
+        s = d / np.sqrt(d ** 2 + g2 * dx ** 2)
+    return np.where(d == 0, 0.0, s)
+
+
+def reinit_steps(d, dx, dtau, tiles, niter, tile=(8, 8, 8), gamma=None):
+    """``niter`` pseudo-time steps of the reinitialisation equation of Eq. 12,
+    d_tau + S(d) (|grad d| - 1) = 0, on the listed tiles, FP64; then, if
+    ``gamma`` is given, the clamp of Eq. 10 to [-gamma, gamma] on them.
+
+    Each step takes S from the current iterate (Eq. 13) and applies the upwind
+    scheme of Eq. 3-5 with the speed S to the |grad d| term (one Jacobi step
+    of the plain scheme), then adds dtau S for the -1 term.  Points outside
+    the tiles keep their values.  Pinned by the distance plane as a fixed
+    point, the convergence of a steepened plane to the distance, the sphere's
+    front kept in place and the clamp.
+    """
+    p = np.array(d, dtype=np.float64, copy=True)
+    nz, ny, nx = p.shape
+    m = tile_mask((nx, ny, nz), tiles, tile)
+    for _ in range(int(niter)):
+        s = smoothed_sign(p, dx)
+        q = upwind_steps(p, s, dx, dtau, tiles, 1, tile)
+        p = np.where(m, q + dtau * s, p)
+    if gamma is not None:
+        p = np.where(m, np.clip(p, -gamma, gamma), p)
+    return p
+
+
 def decide_precision(phi64, precision):
     """The field on which the band decision is taken, in the kernel's precision.
 
@@ -176,14 +232,16 @@ def decide_precision(phi64, precision):
 
 
 def run_band(phi0, F, dx, dt, gamma, nsteps, window=10, tile=(8, 8, 8), precision="f32",
-             dilate=True, record_tiles=False, beta=None):
-    """The narrow-band driver (Steps 1-2 of the algorithm in Sec. 1.1), FP64.
+             dilate=True, record_tiles=False, beta=None, reinit=None):
+    """The narrow-band driver (Steps 1-3 of the algorithm in Sec. 1.1), FP64.
 
     Every ``window`` steps the band U is rebuilt from the current state
     (decision in ``precision``), then the state is advanced on U: by the plain
     steps of Eq. 3-5, or, with ``beta`` given, by the cut-off steps of Eq. 8
-    with the band's gamma.  Returns the final FP64 field and, if asked, the
-    tile list of every window.
+    with the band's gamma.  With ``reinit = (dtau, niter)`` the window ends
+    with Step 3: ``niter`` reinitialisation steps (Eq. 12-13) on U and the
+    clamp of Eq. 10 to the band's gamma.  Returns the final FP64 field and, if
+    asked, the tile list of every window.
     """
     phi = np.array(phi0, dtype=np.float64, copy=True)
     lists = []
@@ -198,6 +256,8 @@ def run_band(phi0, F, dx, dt, gamma, nsteps, window=10, tile=(8, 8, 8), precisio
             phi = upwind_steps(phi, F, dx, dt, tiles, n, tile)
         else:
             phi = cutoff_steps(phi, F, dx, dt, tiles, n, beta, gamma, tile)
+        if reinit is not None:
+            phi = reinit_steps(phi, dx, reinit[0], tiles, reinit[1], tile, gamma=float(gamma))
         done += n
     return (phi, lists) if record_tiles else phi
 
