@@ -13,7 +13,10 @@ run restarts from the initial field after the warm-up windows.
 
 Other workloads (--workload): spheres512_cutoff, the default run with the
 cut-off of Eq. 8 in every step (speed c(phi) F, beta = 3 dx, gamma = 6 dx,
-the band's); torus1024_f16s, the 1024^3 torus with phi stored as scaled FP16
+the band's); spheres512_reinit, the whole narrow-band algorithm (Steps 1-3):
+the cut-off run with every window ended by 24 reinitialisation steps
+(Eq. 12-13, dtau = dx/2) and the clamp of Eq. 10 (its GLUPS count time steps
+only; the roofline is the reinitialisation kernel's); torus1024_f16s, the 1024^3 torus with phi stored as scaled FP16
 (500 steps); batch256, 256 uneven grids (32^3..192^3, random ellipsoids, tile
 shapes from the autotuner, 100 steps) captured in one HIP graph and timed on
 replay.
@@ -35,6 +38,8 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_POINT = {"f32": 12, "f64": 24, "f16s": 8}  # phi read, F read, phi write
+REINIT_BYTES_PER_POINT = {"f32": 8, "f64": 16, "f16s": 4}  # phi read, phi write (no F)
+REINIT_ITERS = 24  # reinitialisation steps per window of the spheres512_reinit workload
 
 
 def parse():
@@ -45,9 +50,12 @@ def parse():
                          "workload: 20 for spheres512, 50 for torus1024_f16s, 10 for batch256)")
     ap.add_argument("--warmup", type=int, default=2, help="untimed warm-up windows")
     ap.add_argument("--workload", default="spheres512",
-                    choices=["spheres512", "spheres512_cutoff", "torus1024_f16s", "batch256"],
+                    choices=["spheres512", "spheres512_cutoff", "spheres512_reinit",
+                             "torus1024_f16s", "batch256"],
                     help="spheres512: the 512^3 FP32 three-sphere run (default); "
                          "spheres512_cutoff: the same with the cut-off of Eq. 8; "
+                         "spheres512_reinit: the same with Steps 1-3 (cut-off, "
+                         "reinitialisation, clamp); "
                          "torus1024_f16s: the 1024^3 scaled-FP16 torus run; "
                          "batch256: 256 uneven grids, autotuned tile shapes, one HIP graph")
     ap.add_argument("--n", type=int, default=None, help="grid points per axis (single grids)")
@@ -58,8 +66,8 @@ def parse():
                          "(the reference for calibrating the traffic counters)")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = {"spheres512": 20, "spheres512_cutoff": 20, "torus1024_f16s": 50,
-                      "batch256": 10}[args.workload]
+        args.steps = {"spheres512": 20, "spheres512_cutoff": 20, "spheres512_reinit": 20,
+                      "torus1024_f16s": 50, "batch256": 10}[args.workload]
     return args
 
 
@@ -92,9 +100,9 @@ def measured_traffic(kernel, workload, digest):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, budget_s, beta=None):
+def cpu_baseline(wl, budget_s, beta=None, reinit=None):
     """The oracle (FP64, OpenMP) on whole windows of the same workload (with
-    the cut-off steps when beta is given)."""
+    the cut-off steps when beta is given, and Step 3 with reinit)."""
     import oracle
 
     if budget_s <= 0:
@@ -110,6 +118,9 @@ def cpu_baseline(wl, budget_s, beta=None):
         else:
             phi = oracle.cutoff_steps(phi, wl.F, wl.dx, wl.dt, tiles, wl.window, beta,
                                       float(g32), wl.tile)
+        if reinit is not None:
+            phi = oracle.reinit_steps(phi, wl.dx, reinit[0], tiles, reinit[1], wl.tile,
+                                      gamma=float(g32))
         updates += int(tiles.size) * int(np.prod(wl.tile)) * wl.window
         windows += 1
         if time.perf_counter() - t0 >= budget_s or windows * wl.window >= wl.nsteps:
@@ -121,20 +132,27 @@ def cpu_baseline(wl, budget_s, beta=None):
         "cores": oracle.max_threads(),
         "kind": "oracle",
         "sample": f"first {windows} window(s) x {wl.window} steps (band rebuild + FP64 "
-                  f"{'cut-off ' if beta is not None else ''}upwind steps) of the "
-                  f"{wl.name}{'_cutoff' if beta is not None else ''} workload, {elapsed:.1f} s",
+                  f"{'cut-off ' if beta is not None else ''}upwind steps"
+                  f"{' + reinitialisation' if reinit is not None else ''}) of the "
+                  f"{wl.name}{_suffix(beta, reinit)} workload, {elapsed:.1f} s",
     }
+
+
+def _suffix(beta, reinit):
+    return "_reinit" if reinit is not None else ("_cutoff" if beta is not None else "")
 
 
 def _single_grid(args, torch, ls, W, BandGrid, dev):
     """The band driver on one grid: (result fields, workload, precision)."""
-    beta = None
-    if args.workload in ("spheres512", "spheres512_cutoff"):
+    beta = reinit = None
+    if args.workload.startswith("spheres512"):
         n = args.n or 512
         wl = W.three_spheres_f32(n, steps=10 * args.steps)
         prec, phi_host, scale = "f32", wl.phi, None
-        if args.workload == "spheres512_cutoff":
+        if args.workload != "spheres512":
             beta = float(np.float32(3 * wl.dx))
+        if args.workload == "spheres512_reinit":
+            reinit = (float(np.float32(0.5 * wl.dx)), REINIT_ITERS)
     else:
         n = args.n or 1024
         wl = W.torus_grf(n, steps=10 * args.steps)
@@ -155,7 +173,7 @@ def _single_grid(args, torch, ls, W, BandGrid, dev):
     tile_steps = torch.zeros(1, dtype=torch.int64, device=dev)
     if args.warmup > 0:
         bg.run(phi, F, wl.dx, wl.dt, gamma, args.warmup * wl.window, wl.window, scale=scale,
-               tile_steps=tile_steps, stream=stream, beta=beta)
+               tile_steps=tile_steps, stream=stream, beta=beta, reinit=reinit)
     phi.copy_(phi0)
     tile_steps.zero_()
     torch.cuda.synchronize()
@@ -164,7 +182,7 @@ def _single_grid(args, torch, ls, W, BandGrid, dev):
     ls.ls_stats_enable(True)
     t0 = time.perf_counter()
     bg.run(phi, F, wl.dx, wl.dt, gamma, args.steps * wl.window, wl.window, scale=scale,
-           tile_steps=tile_steps, stream=stream, beta=beta)
+           tile_steps=tile_steps, stream=stream, beta=beta, reinit=reinit)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ls.ls_stats_enable(False)
@@ -173,6 +191,11 @@ def _single_grid(args, torch, ls, W, BandGrid, dev):
     launches, timed, upd_ms = ls.ls_stats_read(ls.LS_KERNEL_UPWIND)
     _, ftimed, flag_ms = ls.ls_stats_read(ls.LS_KERNEL_BAND_FLAG)
     assert launches == timed == args.steps * wl.window
+    step_avg_us = upd_ms * 1e3 / max(timed, 1)
+    if reinit is not None:
+        # the dominant kernel of this workload: the reinitialisation step
+        launches, timed, upd_ms = ls.ls_stats_read(ls.LS_KERNEL_REINIT)
+        assert launches == timed == args.steps * reinit[1]
 
     # the timed run: the whole driver call captured in one HIP graph, replayed
     # once to warm up, then timed from the initial field
@@ -180,7 +203,7 @@ def _single_grid(args, torch, ls, W, BandGrid, dev):
     torch.cuda.synchronize()
     ls.ls_graph_begin(side)
     bg.run(phi, F, wl.dx, wl.dt, gamma, args.steps * wl.window, wl.window, scale=scale,
-           tile_steps=tile_steps, stream=side, beta=beta)
+           tile_steps=tile_steps, stream=side, beta=beta, reinit=reinit)
     graph = ls.ls_graph_end(side)
     try:
         phi.copy_(phi0)
@@ -204,11 +227,13 @@ def _single_grid(args, torch, ls, W, BandGrid, dev):
         "upd_ms": upd_ms,
         "launches": launches,
         "config": {
-            "workload": wl.name + ("_cutoff" if beta is not None else ""),
+            "workload": wl.name + _suffix(beta, reinit),
             "grid": [n, n, n],
             "tile": list(wl.tile),
             "band_halfwidth_dx": 6,
             **({"cutoff_beta_dx": 3, "cutoff_gamma_dx": 6} if beta is not None else {}),
+            **({"reinit_steps_per_window": reinit[1], "reinit_dtau_dx": 0.5}
+               if reinit is not None else {}),
             "steps_per_window": wl.window,
             "upwind_steps": args.steps * wl.window,
             "storage": prec,
@@ -219,12 +244,18 @@ def _single_grid(args, torch, ls, W, BandGrid, dev):
             "band_scan_avg_us": round(flag_ms * 1e3 / max(ftimed, 1), 3),
             "timed_as": "one HIP graph replay of the whole driver call",
             "eager_value": round(updates / eager_s / 1e9, 3),
+            **({"step_avg_launch_us": round(step_avg_us, 3),
+                "reinit_updates_per_step": reinit[1] / wl.window} if reinit is not None else {}),
         },
         "kernel": ("ls::upwind_vec_kernel (f32, 8x8x8 tiles, 32-point rows, 16-byte accesses"
-                   + (", cut-off of Eq. 8)" if beta is not None else ")")
+                   + (", reinitialisation step of Eq. 12-13, no F)" if reinit is not None else
+                      ", cut-off of Eq. 8)" if beta is not None else ")")
                    if prec == "f32" else
                    "ls::upwind_vec_kernel (f16s, 8x8x8 tiles, 64-point rows, 8-byte accesses)"),
         "beta": beta,
+        "reinit": reinit,
+        "pts_per_launch": updates / (args.steps * wl.window),
+        "bytes_per_point": (REINIT_BYTES_PER_POINT if reinit is not None else BYTES_PER_POINT)[prec],
         "data": ("synthetic (seeded three-sphere signed distance, sinusoidal speed)"
                  if prec == "f32" else
                  "synthetic (torus signed distance stored as scaled FP16, speed 1 + 0.3 GRF)"),
@@ -330,11 +361,12 @@ def main():
         f, wl, prec = _single_grid(args, torch, ls, W, BandGrid, dev)
     value = f["updates"] / f["elapsed"] / 1e9
     avg_launch_s = f["upd_ms"] / 1e3 / max(f["launches"], 1)
-    pts_per_launch = f["updates"] / max(f["launches"], 1)
-    bytes_per_launch = BYTES_PER_POINT[prec] * pts_per_launch
+    pts_per_launch = f.get("pts_per_launch", f["updates"] / max(f["launches"], 1))
+    bytes_per_launch = f.get("bytes_per_point", BYTES_PER_POINT[prec]) * pts_per_launch
     achieved = bytes_per_launch / avg_launch_s / 1e9
     digest = kernel_source_digest()
-    traffic = measured_traffic("upwind", f["config"]["workload"], digest)
+    traffic = measured_traffic("reinit" if f.get("reinit") else "upwind", f["config"]["workload"],
+                               digest)
 
     result = {
         "metric": "band GLUPS (narrow-band first-order upwind update, incl. band rebuilds)",
@@ -373,7 +405,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
     if rank == 0:
-        result["cpu_baseline"] = (cpu_baseline(wl, args.cpu_seconds, f.get("beta"))
+        result["cpu_baseline"] = (cpu_baseline(wl, args.cpu_seconds, f.get("beta"), f.get("reinit"))
                                   if args.workload.startswith("spheres512") else None)
         print(json.dumps(result), flush=True)
     return 0

@@ -225,6 +225,60 @@ int ls_band_run_cutoff_f16s(uint16_t *phi_h, float scale, const float *F, const 
                             int64_t workspace_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Reinitialisation (Sec. 1.1, Eq. 12-13) and clamp (Eq. 10).
+ *
+ * ls_reinit_step_*: niter pseudo-time steps of d_tau + S(d) (|grad d| - 1) = 0
+ * on every grid point of the listed tiles (the list as for ls_upwind_step_*),
+ * with the smoothed sign S(d) = d / sqrt(d^2 + |Dd|^2 dx^2) of the current
+ * iterate (Dd: central differences; S = 0 where d = 0).  Each step is the
+ * upwind step of Eq. 3-5 with the speed S(d) for the |grad d| term, plus
+ * dtau S(d) for the -1 term:  d' = d - dtau S (|grad d|_upwind - 1).  With
+ * clamp = 1 the last step's values are clamped to [-gamma, gamma] (Eq. 10;
+ * gamma > 0 and finite).  Points outside the tiles keep their bits and are
+ * read as frozen neighbours; the grid faces are zero-gradient; a point with
+ * d == 0 keeps its bits.  No F is read.  dx > 0, dtau >= 0 (stable for
+ * dtau <= dx / sqrt(3)), niter >= 0; scratch as for the step.  S and the
+ * update: f64 the definition term by term; f32 and f16s in FP32 with the
+ * hardware reciprocal square root for 1 / sqrt(d^2 + |Dd|^2 dx^2).
+ *
+ * ls_band_run_reinit_*: the narrow-band algorithm of Sec. 1.1, Steps 1-3, in
+ * windows: for each window of `window` steps, build (or rebuild) the band U
+ * of gamma (Eq. 6, 11; U contains the region N of Eq. 11), take the cut-off
+ * steps of Eq. 8 (beta, gamma as for ls_band_run_cutoff_*) on U, then
+ * reinit_iters reinitialisation steps on U, the last one clamped to the band's
+ * gamma.  tile_steps_dev counts band tiles x time steps (not the
+ * reinitialisation steps).  reinit_iters >= 0, dtau >= 0 and finite;
+ * reinit_iters = 0 is ls_band_run_cutoff_* exactly.  Errors as for the other
+ * calls.
+ * ------------------------------------------------------------------------- */
+int ls_reinit_step_f32(float *phi, const ls_grid *g, float dx, float dtau, float gamma, int clamp,
+                       const int32_t *tiles, const int32_t *ntiles_dev, int niter,
+                       float *scratch, void *workspace, int64_t workspace_bytes, void *stream);
+int ls_reinit_step_f64(double *phi, const ls_grid *g, double dx, double dtau, double gamma,
+                       int clamp, const int32_t *tiles, const int32_t *ntiles_dev, int niter,
+                       double *scratch, void *workspace, int64_t workspace_bytes, void *stream);
+int ls_reinit_step_f16s(uint16_t *phi_h, float scale, const ls_grid *g, float dx, float dtau,
+                        float gamma, int clamp, const int32_t *tiles, const int32_t *ntiles_dev,
+                        int niter, uint16_t *scratch, void *workspace, int64_t workspace_bytes,
+                        void *stream);
+int ls_band_run_reinit_f32(float *phi, const float *F, const ls_grid *g, float dx, float dt,
+                           float beta, float gamma, float dtau, int reinit_iters, int nsteps,
+                           int window, int32_t *tiles, int64_t capacity, int32_t *ntiles_dev,
+                           int64_t *tile_steps_dev, float *scratch, void *workspace,
+                           int64_t workspace_bytes, void *stream);
+int ls_band_run_reinit_f64(double *phi, const double *F, const ls_grid *g, double dx, double dt,
+                           double beta, double gamma, double dtau, int reinit_iters, int nsteps,
+                           int window, int32_t *tiles, int64_t capacity, int32_t *ntiles_dev,
+                           int64_t *tile_steps_dev, double *scratch, void *workspace,
+                           int64_t workspace_bytes, void *stream);
+int ls_band_run_reinit_f16s(uint16_t *phi_h, float scale, const float *F, const ls_grid *g,
+                            float dx, float dt, float beta, float gamma, float dtau,
+                            int reinit_iters, int nsteps, int window, int32_t *tiles,
+                            int64_t capacity, int32_t *ntiles_dev, int64_t *tile_steps_dev,
+                            uint16_t *scratch, void *workspace, int64_t workspace_bytes,
+                            void *stream);
+
+/* ---------------------------------------------------------------------------
  * Batches: many grids of uneven size, advanced in lockstep by the same
  * launches (the narrow-band driver above, applied to every grid at once).
  *
@@ -345,7 +399,8 @@ int ls_upwind_launch_info(const ls_grid *g, int precision, int32_t *blocks, int3
  * Kernel timing (measurement support, not part of the method).
  *
  * While enabled, the launches of the kernel `which` (LS_KERNEL_UPWIND: the
- * band step kernel, LS_KERNEL_BAND_FLAG: the band build's scan of phi) are
+ * band step kernel, LS_KERNEL_BAND_FLAG: the band build's scan of phi,
+ * LS_KERNEL_REINIT: the reinitialisation steps) are
  * bracketed by pairs of HIP events recorded on the launch stream: one pair
  * around each scan, and one pair around the back-to-back step launches of a
  * call (a window's launches), so the time per launch includes the short gaps
@@ -356,7 +411,7 @@ int ls_upwind_launch_info(const ls_grid *g, int precision, int32_t *blocks, int3
  * per kernel are recorded.  Do not enable it while a stream is being captured
  * into a HIP graph.
  * ------------------------------------------------------------------------- */
-enum { LS_KERNEL_UPWIND = 0, LS_KERNEL_BAND_FLAG = 1 };
+enum { LS_KERNEL_UPWIND = 0, LS_KERNEL_BAND_FLAG = 1, LS_KERNEL_REINIT = 2 };
 int ls_stats_enable(int on);
 int ls_stats_read(int which, int64_t *launches, int64_t *timed, double *total_ms);
 

@@ -77,6 +77,23 @@ class BandGrid:
             ls.ls_upwind_step_f16s(phi, scale, F, self.g, dx, dt, t, n, nsteps, self.scratch,
                                    self.ws, self.ws_bytes, stream)
 
+    def reinit(self, phi, dx, dtau, niter, gamma=None, scale=None, tiles=None, ntiles=None,
+               stream=None):
+        """niter reinitialisation steps (Eq. 12-13) on the band list; with
+        gamma the last is clamped to [-gamma, gamma] (Eq. 10)."""
+        t = self.tiles if tiles is None else tiles
+        n = self.ntiles if ntiles is None else ntiles
+        clamp, g = (0, 0.0) if gamma is None else (1, gamma)
+        if self.precision == "f32":
+            ls.ls_reinit_step_f32(phi, self.g, dx, dtau, g, clamp, t, n, niter, self.scratch,
+                                  self.ws, self.ws_bytes, stream)
+        elif self.precision == "f64":
+            ls.ls_reinit_step_f64(phi, self.g, dx, dtau, g, clamp, t, n, niter, self.scratch,
+                                  self.ws, self.ws_bytes, stream)
+        else:
+            ls.ls_reinit_step_f16s(phi, scale, self.g, dx, dtau, g, clamp, t, n, niter,
+                                   self.scratch, self.ws, self.ws_bytes, stream)
+
     def rebuild(self, phi, gamma, prev_tiles, prev_ntiles, scale=None, stream=None):
         """Incremental rebuild from a previous band (see ls_band_rebuild_*)."""
         if self.precision == "f32":
@@ -91,8 +108,30 @@ class BandGrid:
                                     self.ws_bytes, stream)
 
     def run(self, phi, F, dx, dt, gamma, nsteps, window=10, scale=None, tile_steps=None,
-            stream=None, beta=None):
-        """The windowed driver; with ``beta`` the cut-off steps of Eq. 8 (with gamma)."""
+            stream=None, beta=None, reinit=None):
+        """The windowed driver; with ``beta`` the cut-off steps of Eq. 8 (with gamma); with
+        ``reinit = (dtau, iters)`` as well, Step 3 (reinitialisation and clamp) ends each
+        window."""
+        if reinit is not None:
+            if beta is None:
+                raise ValueError("the reinitialising driver takes the cut-off steps: give beta")
+            dtau, iters = reinit
+            if self.precision == "f32":
+                ls.ls_band_run_reinit_f32(phi, F, self.g, dx, dt, beta, gamma, dtau, iters,
+                                          nsteps, window, self.tiles, self.capacity, self.ntiles,
+                                          tile_steps, self.scratch, self.ws, self.ws_bytes,
+                                          stream)
+            elif self.precision == "f64":
+                ls.ls_band_run_reinit_f64(phi, F, self.g, dx, dt, beta, gamma, dtau, iters,
+                                          nsteps, window, self.tiles, self.capacity, self.ntiles,
+                                          tile_steps, self.scratch, self.ws, self.ws_bytes,
+                                          stream)
+            else:
+                ls.ls_band_run_reinit_f16s(phi, scale, F, self.g, dx, dt, beta, gamma, dtau,
+                                           iters, nsteps, window, self.tiles, self.capacity,
+                                           self.ntiles, tile_steps, self.scratch, self.ws,
+                                           self.ws_bytes, stream)
+            return
         if beta is not None:
             if self.precision == "f32":
                 ls.ls_band_run_cutoff_f32(phi, F, self.g, dx, dt, beta, gamma, nsteps, window,

@@ -99,6 +99,65 @@ __device__ inline C cutoff(C v, C beta, C gamma, C k) {
     return a <= beta ? C(1) : (a <= gamma ? mid : C(0));
 }
 
+// The smoothed sign S of Eq. 13 at the centre value c from its six
+// neighbours: c / sqrt(c^2 + |Dc|^2 dx^2), Dc the central differences; 0
+// where c = 0.  Exact form: the definition term by term (the squares summed x,
+// then y, then z); fast form: c / sqrt(c^2 + sum of the squared neighbour
+// differences / 4), with the hardware reciprocal square root.
+template <class C, bool EXACT>
+__device__ inline C smoothed_sign(C c, C xm, C xp, C ym, C yp, C zm, C zp, C dx) {
+    if constexpr (EXACT) {
+#pragma clang fp contract(off)
+        const C gx = (xp - xm) / (C(2) * dx), gy = (yp - ym) / (C(2) * dx);
+        const C gz = (zp - zm) / (C(2) * dx);
+        const C g2 = (gx * gx + gy * gy) + gz * gz;
+        const C s = c / sqrt(c * c + g2 * (dx * dx));
+        return c == C(0) ? C(0) : s;
+    } else {
+        const C ex = xp - xm, ey = yp - ym, ez = zp - zm;
+        const C q = c * c + 0.25f * (ex * ex + ey * ey + ez * ez);
+        return c == C(0) ? C(0) : c * __builtin_amdgcn_rsqf(q);
+    }
+}
+
+// What a step launch computes (a compile-time kernel parameter).
+enum StepMode : int {
+    kPlain = 0,        // the step of Eq. 3-5 with the speed F
+    kCutoff = 1,       // the step of Eq. 8: speed c(phi) F
+    kReinit = 2,       // a step of Eq. 12: speed S(d) (Eq. 13), plus dtau S; reads no F
+    kReinitClamp = 3,  // kReinit, then the clamp of Eq. 10 to [-gamma, gamma]
+};
+
+// The speed of the centre point for the mode: F, c(phi) F or S(d).
+template <int MODE, class C, bool EXACT, class A>
+__device__ inline C mode_speed(C f, C c, C xm, C xp, C ym, C yp, C zm, C zp, const A &a) {
+    if constexpr (MODE >= kReinit)
+        return smoothed_sign<C, EXACT>(c, xm, xp, ym, yp, zm, zp, a.dx);
+    else if constexpr (MODE == kCutoff)
+        return cutoff<C, EXACT>(c, a.cut_beta, a.cut_gamma, a.cut_k) * f;
+    else
+        return f;
+}
+
+// The new value for the mode from the upwind value v = c - dt f |grad|:
+// v itself, or v + dt S (the -1 of Eq. 12), clamped for kReinitClamp.
+template <int MODE, class C, bool EXACT>
+__device__ inline C mode_finish(C v, C f, C dt, C gamma) {
+    if constexpr (MODE >= kReinit) {
+        C w;
+        if constexpr (EXACT) {
+#pragma clang fp contract(off)
+            w = v + dt * f;
+        } else {
+            w = v + dt * f;
+        }
+        if constexpr (MODE == kReinitClamp) w = w < -gamma ? -gamma : (w > gamma ? gamma : w);
+        return w;
+    } else {
+        return v;
+    }
+}
+
 template <class S, class FT>
 struct StepArgs {
     const S *cur;
@@ -111,8 +170,9 @@ struct StepArgs {
     const BatchInst *inst;    // batch: grid descriptors (record word 7 = grid), else null
     const uint8_t *umap;      // single grid: U membership per tile (two-step kernel), else null
     typename Codec<S>::C dx, dt, dtdx, scale;
-    // cut-off of Eq. 8 (kernels built with CUT only): beta, gamma and
-    // k = (gamma - beta)^3 (exact form) or 1 / (gamma - beta)^3 (fast form)
+    // cut-off of Eq. 8 (kCutoff kernels): beta, gamma and k = (gamma - beta)^3
+    // (exact form) or 1 / (gamma - beta)^3 (fast form); the clamp of Eq. 10
+    // (kReinitClamp kernels) uses cut_gamma.  F is not read by kReinit*.
     typename Codec<S>::C cut_beta, cut_gamma, cut_k;
 };
 
@@ -173,7 +233,7 @@ struct FastCfg {
 // outside the band from phi (its value frozen for the call), one outside the
 // grid is the clamped point inside the item (zero-gradient boundary).
 template <class S, class FT, bool EXACT, int TX, int TY, int TZ, int R, bool BATCH, bool PARTIAL,
-          bool PIPE, bool CUT = false>
+          bool PIPE, int MODE = kPlain>
 __global__ __launch_bounds__((FastCfg<S, FT, TX, TY, TZ, R>::NT)) void upwind_fast_kernel(
     StepGeom g, StepArgs<S, FT> a) {
     using K = FastCfg<S, FT, TX, TY, TZ, R>;
@@ -267,7 +327,7 @@ __global__ __launch_bounds__((FastCfg<S, FT, TX, TY, TZ, R>::NT)) void upwind_fa
         it.base = goff + (static_cast<int64_t>(z0) * ny + y0) * px + x0;
         const S *cur = a.cur + it.base;
         const S *orig = a.orig + it.base;
-        const FT *Fb = a.F + it.base;
+        const FT *Fb = MODE < kReinit ? a.F + it.base : nullptr;
         // faces on the domain boundary: the clamped neighbour lies in the item
         const int ebits = (y0 == 0 ? 1 : 0) | (y0 + H == ny ? 2 : 0) | (z0 == 0 ? 4 : 0) |
                           (z0 + D == nz ? 8 : 0);
@@ -279,7 +339,7 @@ __global__ __launch_bounds__((FastCfg<S, FT, TX, TY, TZ, R>::NT)) void upwind_fa
             if (ok) {
                 const int u = dlz(q) * plane + dly(q) * px;  // uniform
                 r.raw[q] = (cur + u)[toff];
-                r.fv[q] = (Fb + u)[toff];
+                if constexpr (MODE < kReinit) r.fv[q] = (Fb + u)[toff];
             }
         }
 #pragma unroll
@@ -347,11 +407,14 @@ __global__ __launch_bounds__((FastCfg<S, FT, TX, TY, TZ, R>::NT)) void upwind_fa
         for (int q = 0; q < NOWN; ++q) {
             if (PARTIAL && !(ly0 + dly(q) < it.H && lz0 + dlz(q) < it.D)) continue;
             const int o = lbase + dlz(q) * SXY + dly(q) * SX;
-            C f = static_cast<C>(r.fv[q]);
-            if constexpr (CUT) f = cutoff<C, EXACT>(box[o], a.cut_beta, a.cut_gamma, a.cut_k) * f;
-            const C v = upwind_point<C, EXACT>(box[o], box[o - 1], box[o + 1], box[o - SX],
-                                               box[o + SX], box[o - SXY], box[o + SXY], f, it.dx,
-                                               it.dt, it.dtdx);
+            const C c = box[o], xm = box[o - 1], xp = box[o + 1], ym = box[o - SX],
+                    yp = box[o + SX], zm = box[o - SXY], zp = box[o + SXY];
+            C f = C(0);
+            if constexpr (MODE < kReinit) f = static_cast<C>(r.fv[q]);
+            f = mode_speed<MODE, C, EXACT>(f, c, xm, xp, ym, yp, zm, zp, a);
+            const C v = mode_finish<MODE, C, EXACT>(
+                upwind_point<C, EXACT>(c, xm, xp, ym, yp, zm, zp, f, it.dx, it.dt, it.dtdx), f,
+                it.dt, a.cut_gamma);
             const S out = (f == C(0)) ? r.raw[q] : Codec<S>::store(v, a.scale);
             (nxt + dlz(q) * it.plane + dly(q) * it.px)[toff] = out;
         }
@@ -439,7 +502,7 @@ struct VecCfg {
     static_assert(2 * ROWS <= NT, "x-face points exceed one per thread");
 };
 
-template <class S, int TY, int TZ, int R, bool PARTIAL, bool CUT = false>
+template <class S, int TY, int TZ, int R, bool PARTIAL, int MODE = kPlain>
 __global__ __launch_bounds__((VecCfg<TY, TZ, R>::NT)) void upwind_vec_kernel(
     StepGeom g, StepArgs<S, float> a) {
     using K = VecCfg<TY, TZ, R>;
@@ -487,7 +550,7 @@ __global__ __launch_bounds__((VecCfg<TY, TZ, R>::NT)) void upwind_vec_kernel(
         const int64_t base = (static_cast<int64_t>(z0) * ny + y0) * nx + x0;
         const S *cur = a.cur + base;
         const S *orig = a.orig + base;
-        const float *Fb = a.F + base;
+        const float *Fb = MODE < kReinit ? a.F + base : nullptr;
         S *nxt = a.nxt + base;
         const int ebits = (y0 == 0 ? 1 : 0) | (y0 + H == ny ? 2 : 0) | (z0 == 0 ? 4 : 0) |
                           (z0 + D == nz ? 8 : 0);
@@ -501,7 +564,8 @@ __global__ __launch_bounds__((VecCfg<TY, TZ, R>::NT)) void upwind_vec_kernel(
             if (col_ok && (!PARTIAL || (ly0 < H && lz0 + q * DZ < D))) {
                 const int u = q * DZ * plane;
                 raw[q] = *reinterpret_cast<const VT *>(cur + u + toff);
-                fv[q] = *reinterpret_cast<const float4 *>(Fb + u + toff);
+                if constexpr (MODE < kReinit)
+                    fv[q] = *reinterpret_cast<const float4 *>(Fb + u + toff);
             }
         }
         VT hv[NHALO];
@@ -566,18 +630,23 @@ __global__ __launch_bounds__((VecCfg<TY, TZ, R>::NT)) void upwind_vec_kernel(
             for (int q = 0; q < NOWN; ++q) {
                 if (PARTIAL && !(ly0 < H && lz0 + q * DZ < D)) continue;
                 const int o0 = lbase + q * DZ * SXY;
-                float f4[4] = {fv[q].x, fv[q].y, fv[q].z, fv[q].w};
+                float f4[4] = {0.f, 0.f, 0.f, 0.f};
+                if constexpr (MODE < kReinit) {
+                    f4[0] = fv[q].x, f4[1] = fv[q].y, f4[2] = fv[q].z, f4[3] = fv[q].w;
+                }
                 S out[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int o = o0 + e;
-                    if constexpr (CUT)
-                        f4[e] = cutoff<float, false>(box[o], a.cut_beta, a.cut_gamma, a.cut_k) *
-                                f4[e];
-                    const float v = upwind_point<float, false>(
-                        box[o], box[o - 1], box[o + 1], box[o - SX], box[o + SX], box[o - SXY],
-                        box[o + SXY], f4[e], a.dx, a.dt, a.dtdx);
-                    out[e] = (f4[e] == 0.f) ? VS::get(raw[q], e) : Codec<S>::store(v, sc);
+                    const float c = box[o], xm = box[o - 1], xp = box[o + 1], ym = box[o - SX],
+                                yp = box[o + SX], zm = box[o - SXY], zp = box[o + SXY];
+                    const float f = mode_speed<MODE, float, false>(f4[e], c, xm, xp, ym, yp, zm,
+                                                                   zp, a);
+                    const float v = mode_finish<MODE, float, false>(
+                        upwind_point<float, false>(c, xm, xp, ym, yp, zm, zp, f, a.dx, a.dt,
+                                                   a.dtdx),
+                        f, a.dt, a.cut_gamma);
+                    out[e] = (f == 0.f) ? VS::get(raw[q], e) : Codec<S>::store(v, sc);
                 }
                 *reinterpret_cast<VT *>(nxt + q * DZ * plane + toff) = VS::make(out);
             }

@@ -46,7 +46,7 @@ struct Shape {
     __device__ static inline int sx(const StepGeom &g) { return fixed ? CR * CTX + 2 : g.sx; }
 };
 
-template <class S, class FT, bool EXACT, int NOWN, int NHALO, class SH, bool CUT>
+template <class S, class FT, bool EXACT, int NOWN, int NHALO, class SH, int MODE>
 __global__ __launch_bounds__(kBlock) void upwind_kernel(StepGeom g, StepArgs<S, FT> a) {
     using C = typename Codec<S>::C;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void upwind_kernel(StepGeom g, StepArgs<S, 
         const int64_t base = (static_cast<int64_t>(z0) * g.ny + y0) * g.nx + x0;
         const S *cur = a.cur + base;    // item-relative (uniform) bases
         const S *orig = a.orig + base;
-        const FT *Fb = a.F + base;
+        const FT *Fb = MODE < kReinit ? a.F + base : nullptr;
         S *nxt = a.nxt + base;
         const bool col_ok = lx < W;
 
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void upwind_kernel(StepGeom g, StepArgs<S, 
             const int o = lz * plane + ly * g.nx + lx;
             if (col_ok && row < rows && ly < H && lz < D) {
                 raw[q] = cur[o];
-                fv[q] = Fb[o];
+                if constexpr (MODE < kReinit) fv[q] = Fb[o];
             }
         }
         S hv[NHALO];
@@ -185,14 +185,16 @@ __global__ __launch_bounds__(kBlock) void upwind_kernel(StepGeom g, StepArgs<S, 
             const int ly = row % TY, lz = row / TY;
             if (col_ok && row < rows && ly < H && lz < D) {
                 const int o = (lz + 1) * sxy + (ly + 1) * sx + lx + 1;
-                const C c = box[o];
-                C f = static_cast<C>(fv[q]);
-                if constexpr (CUT) f = cutoff<C, EXACT>(c, a.cut_beta, a.cut_gamma, a.cut_k) * f;
+                const C c = box[o], xm = box[o - 1], xp = box[o + 1], ym = box[o - sx],
+                        yp = box[o + sx], zm = box[o - sxy], zp = box[o + sxy];
+                C f = C(0);
+                if constexpr (MODE < kReinit) f = static_cast<C>(fv[q]);
+                f = mode_speed<MODE, C, EXACT>(f, c, xm, xp, ym, yp, zm, zp, a);
                 S out = raw[q];
                 if (f != C(0)) {
-                    const C v = upwind_point<C, EXACT>(c, box[o - 1], box[o + 1], box[o - sx],
-                                                       box[o + sx], box[o - sxy], box[o + sxy], f,
-                                                       a.dx, a.dt, a.dtdx);
+                    const C v = mode_finish<MODE, C, EXACT>(
+                        upwind_point<C, EXACT>(c, xm, xp, ym, yp, zm, zp, f, a.dx, a.dt, a.dtdx),
+                        f, a.dt, a.cut_gamma);
                     out = Codec<S>::store(v, a.scale);
                 }
                 nxt[lz * plane + ly * g.nx + lx] = out;
@@ -332,20 +334,20 @@ using UpwindFn = void (*)(StepGeom, StepArgs<S, FT>);
 
 using DynShape = Shape<0, 0, 0, 0>;
 
-template <class S, class FT, bool EXACT, int NOWN, bool CUT>
+template <class S, class FT, bool EXACT, int NOWN, int MODE>
 static UpwindFn<S, FT, EXACT> select_halo(int nhalo) {
     switch (nhalo) {
-    case 1: return upwind_kernel<S, FT, EXACT, NOWN, 1, DynShape, CUT>;
-    case 2: return upwind_kernel<S, FT, EXACT, NOWN, 2, DynShape, CUT>;
-    case 4: return upwind_kernel<S, FT, EXACT, NOWN, 4, DynShape, CUT>;
-    default: return upwind_kernel<S, FT, EXACT, NOWN, 8, DynShape, CUT>;
+    case 1: return upwind_kernel<S, FT, EXACT, NOWN, 1, DynShape, MODE>;
+    case 2: return upwind_kernel<S, FT, EXACT, NOWN, 2, DynShape, MODE>;
+    case 4: return upwind_kernel<S, FT, EXACT, NOWN, 4, DynShape, MODE>;
+    default: return upwind_kernel<S, FT, EXACT, NOWN, 8, DynShape, MODE>;
     }
 }
 
 // Kernel for a launch: a compile-time specialisation for the common tile
-// shapes and run lengths, else the run-time-shape kernel.  CUT: the cut-off
-// step of Eq. 8 (the same kernels with the speed scaled by c(phi)).
-template <class S, class FT, bool EXACT, bool CUT = false>
+// shapes and run lengths, else the run-time-shape kernel, compiled for the
+// step mode MODE (StepMode: plain, cut-off, reinitialisation).
+template <class S, class FT, bool EXACT, int MODE = kPlain>
 static UpwindFn<S, FT, EXACT> select_upwind_kernel(const StepGeom &sg, int nown, int nhalo,
                                                    size_t *lds, int *threads,
                                                    bool aligned = false) {
@@ -358,13 +360,13 @@ static UpwindFn<S, FT, EXACT> select_upwind_kernel(const StepGeom &sg, int nown,
             if (sg.R == 4) {
                 *lds = VecCfg<8, 8, 4>::lds;
                 *threads = VecCfg<8, 8, 4>::NT;
-                return whole_yz ? upwind_vec_kernel<S, 8, 8, 4, false, CUT>
-                                : upwind_vec_kernel<S, 8, 8, 4, true, CUT>;
+                return whole_yz ? upwind_vec_kernel<S, 8, 8, 4, false, MODE>
+                                : upwind_vec_kernel<S, 8, 8, 4, true, MODE>;
             }
             *lds = VecCfg<8, 8, 8>::lds;
             *threads = VecCfg<8, 8, 8>::NT;
-            return whole_yz ? upwind_vec_kernel<S, 8, 8, 8, false, CUT>
-                            : upwind_vec_kernel<S, 8, 8, 8, true, CUT>;
+            return whole_yz ? upwind_vec_kernel<S, 8, 8, 8, false, MODE>
+                            : upwind_vec_kernel<S, 8, 8, 8, true, MODE>;
         }
     }
     const bool pipe = use_pipeline(int64_t(sg.nx) * sg.ny * sg.nz * int64_t(sizeof(S)), sg.R);
@@ -373,10 +375,10 @@ static UpwindFn<S, FT, EXACT> select_upwind_kernel(const StepGeom &sg, int nown,
         *lds = FastCfg<S, FT, TX_, TY_, TZ_, R_>::lds;                                      \
         *threads = FastCfg<S, FT, TX_, TY_, TZ_, R_>::NT;                                   \
         if (whole_yz)                                                                       \
-            return pipe ? upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, false, true, CUT>  \
-                        : upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, false, false, CUT>; \
-        return pipe ? upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, true, true, CUT>        \
-                    : upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, true, false, CUT>;      \
+            return pipe ? upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, false, true, MODE>  \
+                        : upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, false, false, MODE>; \
+        return pipe ? upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, true, true, MODE>        \
+                    : upwind_fast_kernel<S, FT, EXACT, TX_, TY_, TZ_, R_, false, true, false, MODE>;      \
     }
     LS_FAST(8, 8, 8, 4)
     LS_FAST(8, 8, 8, 2)
@@ -389,13 +391,13 @@ static UpwindFn<S, FT, EXACT> select_upwind_kernel(const StepGeom &sg, int nown,
     LS_FAST(4, 4, 4, 8)
 #undef LS_FAST
     if (sg.tx == 8 && sg.ty == 8 && sg.tz == 8 && sg.R == 4)
-        return upwind_kernel<S, FT, EXACT, 8, 4, Shape<8, 8, 8, 4>, CUT>;
+        return upwind_kernel<S, FT, EXACT, 8, 4, Shape<8, 8, 8, 4>, MODE>;
     switch (nown) {
-    case 1: return select_halo<S, FT, EXACT, 1, CUT>(nhalo);
-    case 2: return select_halo<S, FT, EXACT, 2, CUT>(nhalo);
-    case 4: return select_halo<S, FT, EXACT, 4, CUT>(nhalo);
-    case 8: return select_halo<S, FT, EXACT, 8, CUT>(nhalo);
-    default: return select_halo<S, FT, EXACT, 16, CUT>(nhalo);
+    case 1: return select_halo<S, FT, EXACT, 1, MODE>(nhalo);
+    case 2: return select_halo<S, FT, EXACT, 2, MODE>(nhalo);
+    case 4: return select_halo<S, FT, EXACT, 4, MODE>(nhalo);
+    case 8: return select_halo<S, FT, EXACT, 8, MODE>(nhalo);
+    default: return select_halo<S, FT, EXACT, 16, MODE>(nhalo);
     }
 }
 
@@ -450,13 +452,14 @@ static int persistent_grid(K kernel, int threads, size_t lds, int *grid, int *li
 template <class S, class FT>
 static int step_args(S *phi, const FT *F, const ls_grid *grid, typename Codec<S>::C dx,
                      typename Codec<S>::C dt, int nsteps, S *scratch, void *workspace,
-                     int64_t ws_bytes, Geom *G, StepGeom *sg) {
+                     int64_t ws_bytes, Geom *G, StepGeom *sg, bool need_F = true) {
     using C = typename Codec<S>::C;
     int rc = make_geom(grid, G);
     if (rc != LS_OK) return rc;
     G->elem_bytes = static_cast<int32_t>(sizeof(S));
-    if (!phi || !F || !scratch) {
-        set_error("step: phi, F and scratch must be non-NULL");
+    if (!phi || (need_F && !F) || !scratch) {
+        set_error(need_F ? "step: phi, F and scratch must be non-NULL"
+                         : "step: phi and scratch must be non-NULL");
         return LS_ERR_ARG;
     }
     if (static_cast<const void *>(phi) == static_cast<const void *>(scratch)) {
@@ -520,10 +523,10 @@ static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const 
     const bool aligned = reinterpret_cast<uintptr_t>(phi) % 16 == 0 &&
                          reinterpret_cast<uintptr_t>(scratch) % 16 == 0 &&
                          reinterpret_cast<uintptr_t>(F) % 16 == 0;
-    auto kernel = cut.on ? select_upwind_kernel<S, FT, EXACT, true>(sg, nown, nhalo, &lds,
-                                                                     &threads, aligned)
-                         : select_upwind_kernel<S, FT, EXACT, false>(sg, nown, nhalo, &lds,
-                                                                      &threads, aligned);
+    auto kernel = cut.on ? select_upwind_kernel<S, FT, EXACT, kCutoff>(sg, nown, nhalo, &lds,
+                                                                        &threads, aligned)
+                         : select_upwind_kernel<S, FT, EXACT, kPlain>(sg, nown, nhalo, &lds,
+                                                                       &threads, aligned);
     int nblocks = 0;
     int rc;
     if ((rc = persistent_grid(kernel, threads, lds, &nblocks, nullptr, G.ntiles)) != LS_OK)
@@ -585,6 +588,73 @@ static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const 
     return LS_OK;
 }
 
+// Step 3 of the algorithm in Sec. 1.1 on the plan held by the workspace:
+// niter reinitialisation steps (Eq. 12-13, pseudo-time step dtau) on the band,
+// the last one followed by the clamp of Eq. 10 to [-gamma, gamma] when clamp
+// is set; ping-pong as in upwind_launch, the band copied back into phi when
+// niter is odd.  The kernels read no F.
+template <class S, class FT>
+static int reinit_launch(S *phi, typename Codec<S>::C scale, const Geom &G, const StepGeom &sg,
+                         typename Codec<S>::C dx, typename Codec<S>::C dtau,
+                         typename Codec<S>::C gamma, bool clamp, int niter, S *scratch,
+                         uint8_t *ws, hipStream_t stream) {
+    using C = typename Codec<S>::C;
+    constexpr bool EXACT = sizeof(C) == 8;
+    if (niter == 0) return LS_OK;
+    const Workspace w = workspace_layout(G);
+    int32_t *items = reinterpret_cast<int32_t *>(ws + w.items);
+    int32_t *nitems = reinterpret_cast<int32_t *>(ws + w.counters);
+    const int rp = kBlock / sg.xl;
+    const int nown = pow2_at_least((G.ty * G.tz + rp - 1) / rp);
+    const int nhalo = pow2_at_least((2 * (G.ty + G.tz) + rp - 1) / rp);
+    size_t lds = static_cast<size_t>(sg.sx) * sg.sy * (G.tz + 2) * sizeof(C);
+    int threads = kBlock;
+    const bool aligned = reinterpret_cast<uintptr_t>(phi) % 16 == 0 &&
+                         reinterpret_cast<uintptr_t>(scratch) % 16 == 0;
+    auto kernel = select_upwind_kernel<S, FT, EXACT, kReinit>(sg, nown, nhalo, &lds, &threads,
+                                                              aligned);
+    auto last = clamp ? select_upwind_kernel<S, FT, EXACT, kReinitClamp>(sg, nown, nhalo, &lds,
+                                                                          &threads, aligned)
+                      : kernel;
+    int nblocks = 0;
+    int rc;
+    if ((rc = persistent_grid(kernel, threads, lds, &nblocks, nullptr, G.ntiles)) != LS_OK)
+        return rc;
+    StepArgs<S, FT> args;
+    args.F = nullptr;
+    args.rec = items;
+    args.nitems = nitems;
+    args.range = nullptr;
+    args.inst = nullptr;
+    args.umap = ws + w.u_map;
+    args.orig = phi;
+    args.dx = dx;
+    args.dt = dtau;
+    args.dtdx = static_cast<C>(static_cast<double>(dtau) / static_cast<double>(dx));
+    args.scale = scale;
+    args.cut_beta = C(0);
+    args.cut_gamma = gamma;
+    args.cut_k = C(0);
+    int64_t slot;
+    if ((rc = stats_before(LS_KERNEL_REINIT, stream, &slot, niter)) != LS_OK) return rc;
+    for (int l = 0; l < niter; ++l) {
+        args.cur = (l & 1) ? scratch : phi;
+        args.nxt = (l & 1) ? phi : scratch;
+        hipLaunchKernelGGL(l == niter - 1 ? last : kernel, dim3(nblocks), dim3(threads), lds,
+                           stream, sg, args);
+        LS_LAUNCH_CHECK("upwind_kernel (reinit)");
+    }
+    if ((rc = stats_after(LS_KERNEL_REINIT, stream, slot)) != LS_OK) return rc;
+    if (niter & 1) {
+        hipLaunchKernelGGL(band_copy_kernel<S>, dim3(nblocks), dim3(kBlock), 0, stream, sg,
+                           static_cast<const S *>(scratch), phi,
+                           static_cast<const int32_t *>(items),
+                           static_cast<const int32_t *>(nitems));
+        LS_LAUNCH_CHECK("band_copy_kernel");
+    }
+    return LS_OK;
+}
+
 int fill_zero(uint8_t *p, int64_t bytes, hipStream_t stream);  // ls_band.hip
 
 // One FP32 step of the plan the workspace holds (the band of the last build),
@@ -598,6 +668,22 @@ int plan_step_to_f32(const float *phi, float *out, const float *F, const Geom &G
     if (rc != LS_OK) return rc;
     return upwind_launch<float, float>(const_cast<float *>(phi), F, 1.0f, G, sg, dx, dt, 1, out,
                                        ws, stream, true);
+}
+
+// The step plan of a caller's band list: its membership map, then the work
+// items, in the workspace.
+static int plan_list(const Geom &G, uint8_t *ws, const int32_t *tiles, const int32_t *ntiles_dev,
+                     hipStream_t stream) {
+    const Workspace w = workspace_layout(G);
+    uint8_t *umap = ws + w.u_map;
+    int rc;
+    if ((rc = fill_zero(umap, G.ntiles, stream)) != LS_OK) return rc;
+    const unsigned set_blocks =
+        static_cast<unsigned>(std::min<int64_t>(cdiv64(G.ntiles, kBlock), 4096));
+    hipLaunchKernelGGL(map_set_kernel, dim3(set_blocks), dim3(kBlock), 0, stream, umap, tiles,
+                       ntiles_dev, static_cast<int>(G.ntiles));
+    LS_LAUNCH_CHECK("map_set_kernel");
+    return build_plan(G, ws, nullptr, nullptr, stream);
 }
 
 template <class S, class FT>
@@ -616,19 +702,43 @@ static int upwind_step(S *phi, const FT *F, typename Codec<S>::C scale, const ls
         return LS_ERR_ARG;
     }
     if (nsteps == 0) return LS_OK;
-    const Workspace w = workspace_layout(G);
     uint8_t *ws = static_cast<uint8_t *>(workspace);
-    uint8_t *umap = ws + w.u_map;
-    // plan of the given list: its membership map, then the work items
-    if ((rc = fill_zero(umap, G.ntiles, stream)) != LS_OK) return rc;
-    const unsigned set_blocks =
-        static_cast<unsigned>(std::min<int64_t>(cdiv64(G.ntiles, kBlock), 4096));
-    hipLaunchKernelGGL(map_set_kernel, dim3(set_blocks), dim3(kBlock), 0, stream, umap, tiles,
-                       ntiles_dev, static_cast<int>(G.ntiles));
-    LS_LAUNCH_CHECK("map_set_kernel");
-    if ((rc = build_plan(G, ws, nullptr, nullptr, stream)) != LS_OK) return rc;
+    if ((rc = plan_list(G, ws, tiles, ntiles_dev, stream)) != LS_OK) return rc;
     return upwind_launch<S, FT>(phi, F, scale, G, sg, dx, dt, nsteps, scratch, ws, stream, false,
                                 cut);
+}
+
+// niter reinitialisation steps (Eq. 12-13) on the listed tiles, optionally
+// followed by the clamp of Eq. 10.
+template <class S, class FT>
+static int reinit_step(S *phi, typename Codec<S>::C scale, const ls_grid *grid,
+                       typename Codec<S>::C dx, typename Codec<S>::C dtau,
+                       typename Codec<S>::C gamma, int clamp, const int32_t *tiles,
+                       const int32_t *ntiles_dev, int niter, S *scratch, void *workspace,
+                       int64_t ws_bytes, hipStream_t stream) {
+    using C = typename Codec<S>::C;
+    Geom G;
+    StepGeom sg;
+    int rc = step_args<S, FT>(phi, nullptr, grid, dx, dtau, niter, scratch, workspace, ws_bytes,
+                              &G, &sg, false);
+    if (rc != LS_OK) return rc;
+    if (clamp != 0 && clamp != 1) {
+        set_error("reinit: clamp must be 0 or 1");
+        return LS_ERR_ARG;
+    }
+    if (clamp && !(gamma > C(0) && gamma < C(INFINITY))) {
+        set_error("reinit: gamma must be positive and finite");
+        return LS_ERR_ARG;
+    }
+    if (!tiles || !ntiles_dev) {
+        set_error("reinit: tiles and ntiles_dev must be non-NULL");
+        return LS_ERR_ARG;
+    }
+    if (niter == 0) return LS_OK;
+    uint8_t *ws = static_cast<uint8_t *>(workspace);
+    if ((rc = plan_list(G, ws, tiles, ntiles_dev, stream)) != LS_OK) return rc;
+    return reinit_launch<S, FT>(phi, scale, G, sg, dx, dtau, gamma, clamp != 0, niter, scratch,
+                                ws, stream);
 }
 
 template <class S, class FT>
@@ -669,7 +779,8 @@ static int band_run(S *phi, const FT *F, typename Codec<S>::C scale, const ls_gr
                     typename Codec<S>::C dx, typename Codec<S>::C dt, typename Codec<S>::C gamma,
                     int nsteps, int window, int32_t *tiles, int64_t capacity,
                     int32_t *ntiles_dev, int64_t *tile_steps_dev, S *scratch, void *workspace,
-                    int64_t ws_bytes, void *stream_, const CutOff<typename Codec<S>::C> &cut = {}) {
+                    int64_t ws_bytes, void *stream_, const CutOff<typename Codec<S>::C> &cut = {},
+                    int reinit_iters = 0, typename Codec<S>::C dtau = 0) {
     if (window <= 0) {
         set_error("band run: window must be positive (got %d)", window);
         return LS_ERR_ARG;
@@ -687,6 +798,10 @@ static int band_run(S *phi, const FT *F, typename Codec<S>::C scale, const ls_gr
         return LS_ERR_ARG;
     }
     if ((rc = check_cutoff(cut)) != LS_OK) return rc;
+    if (reinit_iters < 0 || !(dtau >= 0) || !(dtau < INFINITY)) {
+        set_error("band run: reinit_iters must be >= 0 and dtau >= 0 and finite");
+        return LS_ERR_ARG;
+    }
     if (capacity < G.ntiles) {
         set_error("band run: capacity %lld < %lld tiles", (long long)capacity,
                   (long long)G.ntiles);
@@ -712,6 +827,10 @@ static int band_run(S *phi, const FT *F, typename Codec<S>::C scale, const ls_gr
         if (rc != LS_OK) return rc;
         rc = upwind_launch<S, FT>(phi, F, scale, G, sg, dx, dt, n, scratch, ws, stream, false,
                                   cut);
+        if (rc != LS_OK) return rc;
+        // Step 3: reinitialisation on the same band, then the clamp to the band's gamma
+        rc = reinit_launch<S, FT>(phi, scale, G, sg, dx, dtau, gamma, true, reinit_iters, scratch,
+                                  ws, stream);
         if (rc != LS_OK) return rc;
     }
     return LS_OK;
@@ -894,6 +1013,79 @@ int ls_band_run_cutoff_f16s(uint16_t *phi_h, float scale, const float *F, const 
     return ls::band_run<uint16_t, float>(phi_h, F, scale, g, dx, dt, gamma, nsteps, window, tiles,
                                          capacity, ntiles_dev, tile_steps_dev, scratch, workspace,
                                          workspace_bytes, stream, {true, beta, gamma});
+}
+
+int ls_reinit_step_f32(float *phi, const ls_grid *g, float dx, float dtau, float gamma, int clamp,
+                       const int32_t *tiles, const int32_t *ntiles_dev, int niter,
+                       float *scratch, void *workspace, int64_t workspace_bytes, void *stream) {
+    ls::clear_error();
+    return ls::reinit_step<float, float>(phi, 1.0f, g, dx, dtau, gamma, clamp, tiles, ntiles_dev,
+                                         niter, scratch, workspace, workspace_bytes,
+                                         static_cast<hipStream_t>(stream));
+}
+
+int ls_reinit_step_f64(double *phi, const ls_grid *g, double dx, double dtau, double gamma,
+                       int clamp, const int32_t *tiles, const int32_t *ntiles_dev, int niter,
+                       double *scratch, void *workspace, int64_t workspace_bytes, void *stream) {
+    ls::clear_error();
+    return ls::reinit_step<double, double>(phi, 1.0, g, dx, dtau, gamma, clamp, tiles, ntiles_dev,
+                                           niter, scratch, workspace, workspace_bytes,
+                                           static_cast<hipStream_t>(stream));
+}
+
+int ls_reinit_step_f16s(uint16_t *phi_h, float scale, const ls_grid *g, float dx, float dtau,
+                        float gamma, int clamp, const int32_t *tiles, const int32_t *ntiles_dev,
+                        int niter, uint16_t *scratch, void *workspace, int64_t workspace_bytes,
+                        void *stream) {
+    ls::clear_error();
+    if (!(scale > 0.0f) || !(scale < INFINITY)) {
+        ls::set_error("reinit f16s: scale must be positive and finite");
+        return LS_ERR_ARG;
+    }
+    return ls::reinit_step<uint16_t, float>(phi_h, scale, g, dx, dtau, gamma, clamp, tiles,
+                                            ntiles_dev, niter, scratch, workspace,
+                                            workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+int ls_band_run_reinit_f32(float *phi, const float *F, const ls_grid *g, float dx, float dt,
+                           float beta, float gamma, float dtau, int reinit_iters, int nsteps,
+                           int window, int32_t *tiles, int64_t capacity, int32_t *ntiles_dev,
+                           int64_t *tile_steps_dev, float *scratch, void *workspace,
+                           int64_t workspace_bytes, void *stream) {
+    ls::clear_error();
+    return ls::band_run<float, float>(phi, F, 1.0f, g, dx, dt, gamma, nsteps, window, tiles,
+                                      capacity, ntiles_dev, tile_steps_dev, scratch, workspace,
+                                      workspace_bytes, stream, {true, beta, gamma}, reinit_iters,
+                                      dtau);
+}
+
+int ls_band_run_reinit_f64(double *phi, const double *F, const ls_grid *g, double dx, double dt,
+                           double beta, double gamma, double dtau, int reinit_iters, int nsteps,
+                           int window, int32_t *tiles, int64_t capacity, int32_t *ntiles_dev,
+                           int64_t *tile_steps_dev, double *scratch, void *workspace,
+                           int64_t workspace_bytes, void *stream) {
+    ls::clear_error();
+    return ls::band_run<double, double>(phi, F, 1.0, g, dx, dt, gamma, nsteps, window, tiles,
+                                        capacity, ntiles_dev, tile_steps_dev, scratch, workspace,
+                                        workspace_bytes, stream, {true, beta, gamma},
+                                        reinit_iters, dtau);
+}
+
+int ls_band_run_reinit_f16s(uint16_t *phi_h, float scale, const float *F, const ls_grid *g,
+                            float dx, float dt, float beta, float gamma, float dtau,
+                            int reinit_iters, int nsteps, int window, int32_t *tiles,
+                            int64_t capacity, int32_t *ntiles_dev, int64_t *tile_steps_dev,
+                            uint16_t *scratch, void *workspace, int64_t workspace_bytes,
+                            void *stream) {
+    ls::clear_error();
+    if (!(scale > 0.0f) || !(scale < INFINITY)) {
+        ls::set_error("band run f16s: scale must be positive and finite");
+        return LS_ERR_ARG;
+    }
+    return ls::band_run<uint16_t, float>(phi_h, F, scale, g, dx, dt, gamma, nsteps, window, tiles,
+                                         capacity, ntiles_dev, tile_steps_dev, scratch, workspace,
+                                         workspace_bytes, stream, {true, beta, gamma},
+                                         reinit_iters, dtau);
 }
 
 }  // extern "C"

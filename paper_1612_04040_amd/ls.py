@@ -104,6 +104,18 @@ _SIGNATURES = {
                                       _VP, _VP, _VP, _VP, _I64, _VP]),
     "ls_band_run_cutoff_f16s": (_I32, [_VP, _F32, _VP, _G, _F32, _F32, _F32, _F32, _I32, _I32,
                                        _VP, _I64, _VP, _VP, _VP, _VP, _I64, _VP]),
+    "ls_reinit_step_f32": (_I32, [_VP, _G, _F32, _F32, _F32, _I32, _VP, _VP, _I32, _VP, _VP, _I64,
+                                  _VP]),
+    "ls_reinit_step_f64": (_I32, [_VP, _G, _F64, _F64, _F64, _I32, _VP, _VP, _I32, _VP, _VP, _I64,
+                                  _VP]),
+    "ls_reinit_step_f16s": (_I32, [_VP, _F32, _G, _F32, _F32, _F32, _I32, _VP, _VP, _I32, _VP,
+                                   _VP, _I64, _VP]),
+    "ls_band_run_reinit_f32": (_I32, [_VP, _VP, _G, _F32, _F32, _F32, _F32, _F32, _I32, _I32,
+                                      _I32, _VP, _I64, _VP, _VP, _VP, _VP, _I64, _VP]),
+    "ls_band_run_reinit_f64": (_I32, [_VP, _VP, _G, _F64, _F64, _F64, _F64, _F64, _I32, _I32,
+                                      _I32, _VP, _I64, _VP, _VP, _VP, _VP, _I64, _VP]),
+    "ls_band_run_reinit_f16s": (_I32, [_VP, _F32, _VP, _G, _F32, _F32, _F32, _F32, _F32, _I32,
+                                       _I32, _I32, _VP, _I64, _VP, _VP, _VP, _VP, _I64, _VP]),
     "ls_set_tuning": (_I32, [ctypes.c_void_p]),
     "ls_get_tuning": (_I32, [ctypes.c_void_p]),
     "ls_upwind_launch_info": (_I32, [_G, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
@@ -137,6 +149,7 @@ _SIGNATURES = {
 
 LS_KERNEL_UPWIND = 0
 LS_KERNEL_BAND_FLAG = 1
+LS_KERNEL_REINIT = 2
 
 
 def lib():
@@ -345,6 +358,58 @@ def ls_band_run_cutoff_f16s(phi_h, scale, F, g, dx, dt, beta, gamma, nsteps, win
                                                 gamma, nsteps, window, _ptr(tiles), capacity,
                                                 _ptr(ntiles_dev), _ptr(tile_steps_dev),
                                                 _ptr(scratch), _ptr(workspace), workspace_bytes,
+                                                _stream(stream)))
+
+
+def ls_reinit_step_f32(phi, g, dx, dtau, gamma, clamp, tiles, ntiles_dev, niter, scratch,
+                       workspace, workspace_bytes, stream=None):
+    return _check(lib().ls_reinit_step_f32(_ptr(phi), _g(g), dx, dtau, gamma, clamp, _ptr(tiles),
+                                           _ptr(ntiles_dev), niter, _ptr(scratch),
+                                           _ptr(workspace), workspace_bytes, _stream(stream)))
+
+
+def ls_reinit_step_f64(phi, g, dx, dtau, gamma, clamp, tiles, ntiles_dev, niter, scratch,
+                       workspace, workspace_bytes, stream=None):
+    return _check(lib().ls_reinit_step_f64(_ptr(phi), _g(g), dx, dtau, gamma, clamp, _ptr(tiles),
+                                           _ptr(ntiles_dev), niter, _ptr(scratch),
+                                           _ptr(workspace), workspace_bytes, _stream(stream)))
+
+
+def ls_reinit_step_f16s(phi_h, scale, g, dx, dtau, gamma, clamp, tiles, ntiles_dev, niter,
+                        scratch, workspace, workspace_bytes, stream=None):
+    return _check(lib().ls_reinit_step_f16s(_ptr(phi_h), scale, _g(g), dx, dtau, gamma, clamp,
+                                            _ptr(tiles), _ptr(ntiles_dev), niter, _ptr(scratch),
+                                            _ptr(workspace), workspace_bytes, _stream(stream)))
+
+
+def ls_band_run_reinit_f32(phi, F, g, dx, dt, beta, gamma, dtau, reinit_iters, nsteps, window,
+                           tiles, capacity, ntiles_dev, tile_steps_dev, scratch, workspace,
+                           workspace_bytes, stream=None):
+    return _check(lib().ls_band_run_reinit_f32(_ptr(phi), _ptr(F), _g(g), dx, dt, beta, gamma,
+                                               dtau, reinit_iters, nsteps, window, _ptr(tiles),
+                                               capacity, _ptr(ntiles_dev), _ptr(tile_steps_dev),
+                                               _ptr(scratch), _ptr(workspace), workspace_bytes,
+                                               _stream(stream)))
+
+
+def ls_band_run_reinit_f64(phi, F, g, dx, dt, beta, gamma, dtau, reinit_iters, nsteps, window,
+                           tiles, capacity, ntiles_dev, tile_steps_dev, scratch, workspace,
+                           workspace_bytes, stream=None):
+    return _check(lib().ls_band_run_reinit_f64(_ptr(phi), _ptr(F), _g(g), dx, dt, beta, gamma,
+                                               dtau, reinit_iters, nsteps, window, _ptr(tiles),
+                                               capacity, _ptr(ntiles_dev), _ptr(tile_steps_dev),
+                                               _ptr(scratch), _ptr(workspace), workspace_bytes,
+                                               _stream(stream)))
+
+
+def ls_band_run_reinit_f16s(phi_h, scale, F, g, dx, dt, beta, gamma, dtau, reinit_iters, nsteps,
+                            window, tiles, capacity, ntiles_dev, tile_steps_dev, scratch,
+                            workspace, workspace_bytes, stream=None):
+    return _check(lib().ls_band_run_reinit_f16s(_ptr(phi_h), scale, _ptr(F), _g(g), dx, dt, beta,
+                                                gamma, dtau, reinit_iters, nsteps, window,
+                                                _ptr(tiles), capacity, _ptr(ntiles_dev),
+                                                _ptr(tile_steps_dev), _ptr(scratch),
+                                                _ptr(workspace), workspace_bytes,
                                                 _stream(stream)))
 
 

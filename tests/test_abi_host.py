@@ -168,6 +168,44 @@ def test_cutoff_errors(fn):
     assert step(*a) == ls.LS_OK
 
 
+@pytest.mark.parametrize("fn", ["f32", "f64", "f16s"])
+def test_reinit_errors(fn):
+    """Reinitialisation calls: bad clamp flag, gamma with the clamp, dtau,
+    NULL pointers and negative counts are rejected on the host; zero steps
+    launch nothing."""
+    g = ls.grid((64, 64, 64))
+    step = getattr(ls, f"ls_reinit_step_{fn}")
+    run = getattr(ls, f"ls_band_run_reinit_{fn}")
+    cap = ls.ls_grid_tiles(g)
+    ws = ls.ls_workspace_bytes(g)
+    lead = [FAKE, 0.5] if fn == "f16s" else [FAKE]
+
+    def step_args(**o):
+        a = dict(g=g, dx=0.01, dtau=0.005, gamma=0.06, clamp=1, tiles=FAKE, n=FAKE, niter=3,
+                 scratch=FAKE * 2, ws=FAKE * 256, wsb=ws, stream=0)
+        a.update(o)
+        return lead + list(a.values())
+
+    for over in [dict(clamp=2), dict(clamp=-1), dict(gamma=0.0), dict(gamma=float("inf")),
+                 dict(dtau=float("nan")), dict(dtau=-1.0), dict(dx=0.0), dict(niter=-1),
+                 dict(tiles=None), dict(scratch=None), dict(scratch=FAKE)]:
+        assert _status(step, *step_args(**over)) == ls.LS_ERR_ARG, over
+    assert step(*step_args(gamma=0.0, clamp=0, niter=0)) == ls.LS_OK
+    assert step(*step_args(niter=0)) == ls.LS_OK
+
+    def run_args(**o):
+        a = dict(F=FAKE, g=g, dx=0.01, dt=0.005, beta=0.03, gamma=0.06, dtau=0.005, iters=4,
+                 nsteps=10, window=5, tiles=FAKE, cap=cap, n=FAKE, acc=None, scratch=FAKE * 2,
+                 ws=FAKE * 256, wsb=ws, stream=0)
+        a.update(o)
+        return lead + list(a.values())
+
+    for over in [dict(iters=-1), dict(dtau=float("nan")), dict(dtau=-0.1), dict(beta=0.07),
+                 dict(F=None), dict(window=0)]:
+        assert _status(run, *run_args(**over)) == ls.LS_ERR_ARG, over
+    assert _status(run, *run_args(cap=cap - 1)) == ls.LS_ERR_CAPACITY
+
+
 def test_run_errors():
     g = ls.grid((32, 32, 32))
     cap = ls.ls_grid_tiles(g)
