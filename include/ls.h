@@ -190,10 +190,12 @@ int ls_band_run_f16s(uint16_t *phi_h, float scale, const float *F, const ls_grid
  * whose c(phi) F is zero, keep their bits.  beta and gamma are in phi's units
  * (for f16s: of phi, not of h); ls_band_run_cutoff_* uses its gamma for the
  * tube of Eq. 6 as well.  Arithmetic of c: f64 the definition term by term
- * ((gamma - beta)^3 formed on the host in FP64); f32 and f16s in FP32 with the
- * reciprocal of (gamma - beta)^3.  Requires 0 < beta < gamma < inf
- * (LS_ERR_ARG otherwise); the other arguments, buffers and errors as for the
- * plain calls.  The two-step kernel of ls_tuning.temporal is not used here.
+ * ((gamma - beta)^3 formed on the host in FP64); f32 and f16s in FP32 as the
+ * equal cubic u^2 (3 - 2u), u = (gamma - |phi|) / (gamma - beta) clamped to
+ * [0, 1] (1 for |phi| <= beta and 0 from gamma on, as in f64).  Requires
+ * 0 < beta < gamma < inf (LS_ERR_ARG otherwise); the other arguments, buffers
+ * and errors as for the plain calls.  The two-step kernel of
+ * ls_tuning.temporal is not used here.
  * ------------------------------------------------------------------------- */
 int ls_upwind_step_cutoff_f32(float *phi, const float *F, const ls_grid *g, float dx, float dt,
                               float beta, float gamma, const int32_t *tiles,

@@ -548,9 +548,10 @@ static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const 
     args.cut_gamma = cut.gamma;
     args.cut_k = C(0);
     if (cut.on) {
-        // (gamma - beta)^3 from the arguments' values, in FP64
-        const double d3 = std::pow(static_cast<double>(cut.gamma) - static_cast<double>(cut.beta), 3.0);
-        args.cut_k = EXACT ? static_cast<C>(d3) : static_cast<C>(1.0 / d3);
+        // from the arguments' values, in FP64: (gamma - beta)^3 for the exact
+        // form, 1 / (gamma - beta) for the fast form
+        const double d = static_cast<double>(cut.gamma) - static_cast<double>(cut.beta);
+        args.cut_k = EXACT ? static_cast<C>(std::pow(d, 3.0)) : static_cast<C>(1.0 / d);
     }
     // pairs of steps in one launch where the two-step kernel applies, then a
     // single step if one is left; one pair of timing events around them all
