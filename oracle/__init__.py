@@ -217,6 +217,26 @@ def reinit_steps(d, dx, dtau, tiles, niter, tile=(8, 8, 8), gamma=None):
     return p
 
 
+def gather_tiles(phi, tiles, tile=(8, 8, 8)):
+    """The band snapshot: the values of the listed tiles, tile by tile in list
+    order, each as a (tz, ty, tx) block (x fastest); points of a partial tile
+    that lie outside the grid are 0.  The snapshot output of the algorithm in
+    Sec. 1.1 (Step 4), restricted to the band.  Keeps the input dtype.
+    Pinned by explicit loops on a tiny grid and the scatter round trip.
+    """
+    phi = np.asarray(phi)
+    nz, ny, nx = phi.shape
+    tx, ty, tz = tile
+    ntx, nty = -(-nx // tx), -(-ny // ty)
+    t = np.asarray(tiles, dtype=np.int64)
+    out = np.zeros((t.size, tz, ty, tx), dtype=phi.dtype)
+    for p, tid in enumerate(t):
+        ti, tj, tk = tid % ntx, (tid // ntx) % nty, tid // (ntx * nty)
+        blk = phi[tk * tz:(tk + 1) * tz, tj * ty:(tj + 1) * ty, ti * tx:(ti + 1) * tx]
+        out[p, :blk.shape[0], :blk.shape[1], :blk.shape[2]] = blk
+    return out
+
+
 def decide_precision(phi64, precision):
     """The field on which the band decision is taken, in the kernel's precision.
 

@@ -256,3 +256,32 @@ def test_spheres512_reinit_full_size_window(precision):
     report("spheres512_reinit_f64_block", band_tiles=int(band.size), block_origin=lo.tolist(),
            max_err=err)
     assert np.array_equal(a, b), err
+
+
+def test_driver_f16s_equals_its_steps():
+    """Scaled FP16 storage: the cut-off driver and the Steps 1-3 driver equal
+    build + cut-off steps (+ reinitialisation with clamp), window by window,
+    bit for bit."""
+    n = 64
+    rng = np.random.default_rng(8)
+    dx = 1.0 / n
+    centers = rng.uniform(0.3, 0.7, size=(3, 3))
+    phi = W.sphere_union((n, n, n), dx, centers, rng.uniform(0.1, 0.2, 3))
+    s = float(np.float32(6 * dx))
+    h = W.quantize_f16s(phi, s)
+    F = rng.uniform(-1, 1, (n, n, n)).astype(np.float32)
+    dt = float(np.float32(0.5 * dx))
+    beta, gamma, dtau = float(np.float32(3 * dx)), float(np.float32(6 * dx)), float(np.float32(0.5 * dx))
+    bg = BandGrid((n, n, n), (8, 8, 8), "f16s")
+    fd = to_dev(F)
+    for reinit in (None, (dtau, 6)):
+        a = torch.from_numpy(h.copy()).to(dev())
+        bg.run(a, fd, dx, dt, gamma, 20, 10, scale=s, beta=beta, reinit=reinit)
+        b = torch.from_numpy(h.copy()).to(dev())
+        for _ in range(2):
+            bg.build(b, gamma, dilate=True, scale=s)
+            bg.step(b, fd, dx, dt, 10, scale=s, cutoff=(beta, gamma))
+            if reinit is not None:
+                bg.reinit(b, dx, dtau, 6, gamma=gamma, scale=s)
+        assert host(a).tobytes() == host(b).tobytes(), reinit
+        assert not np.array_equal(host(a), h)
