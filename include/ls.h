@@ -281,6 +281,32 @@ int ls_band_run_reinit_f16s(uint16_t *phi_h, float scale, const float *F, const 
                             void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Band snapshot (the output of Step 4 of the algorithm in Sec. 1.1,
+ * restricted to the band): copies the values of the tiles listed in
+ * tiles[0 .. n), n = min(*ntiles_dev, capacity), into out, tile by tile in
+ * list order: tile p occupies out[p*tp .. (p+1)*tp), tp = tx*ty*tz, its
+ * points x fastest, then y, then z within the tile; points of a partial tile
+ * outside the grid, and every point of a tile whose id is not in
+ * [0, ls_grid_tiles(g)), are written as zero bits.  With ids_out non-NULL,
+ * ids_out[p] = tiles[p] for p < n (a copy of the list, so that the snapshot
+ * outlives the next band build).  out holds capacity*tp elements of phi's type
+ * (f16s: the stored FP16 codes, unscaled), ids_out capacity int32;
+ * 0 <= capacity <= ls_grid_tiles(g).  Nothing is read from the host: the call
+ * is stream-ordered and can be captured; a device-to-host copy of the first
+ * n tiles of out (n read back from *ntiles_dev) takes the snapshot off the
+ * GPU.
+ * ------------------------------------------------------------------------- */
+int ls_band_gather_f32(const float *phi, const ls_grid *g, const int32_t *tiles,
+                       const int32_t *ntiles_dev, float *out, int32_t *ids_out, int64_t capacity,
+                       void *stream);
+int ls_band_gather_f64(const double *phi, const ls_grid *g, const int32_t *tiles,
+                       const int32_t *ntiles_dev, double *out, int32_t *ids_out,
+                       int64_t capacity, void *stream);
+int ls_band_gather_f16s(const uint16_t *phi_h, const ls_grid *g, const int32_t *tiles,
+                        const int32_t *ntiles_dev, uint16_t *out, int32_t *ids_out,
+                        int64_t capacity, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Batches: many grids of uneven size, advanced in lockstep by the same
  * launches (the narrow-band driver above, applied to every grid at once).
  *
@@ -402,7 +428,8 @@ int ls_upwind_launch_info(const ls_grid *g, int precision, int32_t *blocks, int3
  *
  * While enabled, the launches of the kernel `which` (LS_KERNEL_UPWIND: the
  * band step kernel, LS_KERNEL_BAND_FLAG: the band build's scan of phi,
- * LS_KERNEL_REINIT: the reinitialisation steps) are
+ * LS_KERNEL_REINIT: the reinitialisation steps, LS_KERNEL_GATHER: the band
+ * snapshot's gather) are
  * bracketed by pairs of HIP events recorded on the launch stream: one pair
  * around each scan, and one pair around the back-to-back step launches of a
  * call (a window's launches), so the time per launch includes the short gaps
@@ -413,7 +440,7 @@ int ls_upwind_launch_info(const ls_grid *g, int precision, int32_t *blocks, int3
  * per kernel are recorded.  Do not enable it while a stream is being captured
  * into a HIP graph.
  * ------------------------------------------------------------------------- */
-enum { LS_KERNEL_UPWIND = 0, LS_KERNEL_BAND_FLAG = 1, LS_KERNEL_REINIT = 2 };
+enum { LS_KERNEL_UPWIND = 0, LS_KERNEL_BAND_FLAG = 1, LS_KERNEL_REINIT = 2, LS_KERNEL_GATHER = 3 };
 int ls_stats_enable(int on);
 int ls_stats_read(int which, int64_t *launches, int64_t *timed, double *total_ms);
 

@@ -94,6 +94,16 @@ class BandGrid:
             ls.ls_reinit_step_f16s(phi, scale, self.g, dx, dtau, g, clamp, t, n, niter,
                                    self.scratch, self.ws, self.ws_bytes, stream)
 
+    def gather(self, phi, out, ids=None, capacity=None, tiles=None, ntiles=None, stream=None):
+        """The band snapshot: the listed tiles' values into out (tile-major; see
+        ls_band_gather_*), their ids into ids."""
+        t = self.tiles if tiles is None else tiles
+        n = self.ntiles if ntiles is None else ntiles
+        cap = self.capacity if capacity is None else capacity
+        fn = {"f32": ls.ls_band_gather_f32, "f64": ls.ls_band_gather_f64,
+              "f16s": ls.ls_band_gather_f16s}[self.precision]
+        fn(phi, self.g, t, n, out, ids, cap, stream)
+
     def rebuild(self, phi, gamma, prev_tiles, prev_ntiles, scale=None, stream=None):
         """Incremental rebuild from a previous band (see ls_band_rebuild_*)."""
         if self.precision == "f32":

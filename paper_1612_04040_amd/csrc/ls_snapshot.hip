@@ -1,0 +1,164 @@
+// Band snapshot: the values of the band tiles copied, tile by tile in list
+// order, into a dense tile-major buffer (the output of Step 4 of the
+// algorithm in Sec. 1.1, restricted to the band), so that one contiguous
+// device-to-host copy of the first n tiles takes the snapshot off the GPU.
+//
+// One thread moves 4 x-consecutive points of a tile row (a 16-byte FP32 or an
+// 8-byte FP16 access) when the rows allow it, else one point; a grid-stride
+// loop over (tile, row, quad) keeps the reads of a tile row and the writes of
+// the dense buffer contiguous.  The band count is read on the device, so the
+// call needs no host synchronisation.
+#include <algorithm>
+#include <type_traits>
+
+#include "ls_internal.h"
+#include "ls_stats.h"
+
+namespace ls {
+
+struct GatherGeom {
+    int32_t nx, ny, nz, tx, ty, tz, ntx, nty;
+    int32_t tp;        // points per tile
+    int64_t ntiles;    // tiles of the grid
+    int64_t capacity;  // tiles the output holds
+};
+
+template <class S>
+struct GatherQuad;
+template <>
+struct GatherQuad<float> {
+    using T = float4;
+    __device__ static inline T zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+};
+template <>
+struct GatherQuad<uint16_t> {
+    using T = uint2;
+    __device__ static inline T zero() { return make_uint2(0u, 0u); }
+};
+
+// V = 4: quads of x-consecutive points (tx and nx multiples of 4); V = 1:
+// single points.  Points outside the grid (partial tiles) and tiles with an
+// invalid id are written as zero.
+template <class S, class T, int V>
+__global__ __launch_bounds__(kBlock) void band_gather_kernel(GatherGeom g, const S *__restrict__ phi,
+                                                             const int32_t *__restrict__ tiles,
+                                                             const int32_t *__restrict__ ntiles_dev,
+                                                             S *__restrict__ out,
+                                                             int32_t *__restrict__ ids_out) {
+    const int64_t n = min(static_cast<int64_t>(max(*ntiles_dev, 0)), g.capacity);
+    const int per_row = g.tx / V;
+    const int per_tile = g.tp / V;
+    const int64_t total = n * per_tile;
+    for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < total;
+         q += static_cast<int64_t>(gridDim.x) * kBlock) {
+        const int64_t p = q / per_tile;
+        const int r = static_cast<int>(q - p * per_tile);
+        const int t = tiles[p];
+        const int row = r / per_row, xq = r - row * per_row;
+        const int ly = row % g.ty, lz = row / g.ty;
+        T v;
+        if constexpr (V == 4)
+            v = GatherQuad<S>::zero();
+        else
+            v = T(0);
+        if (t >= 0 && t < g.ntiles) {
+            const int ti = t % g.ntx, rr = t / g.ntx;
+            const int x = ti * g.tx + xq * V, y = (rr % g.nty) * g.ty + ly,
+                      z = (rr / g.nty) * g.tz + lz;
+            if (x < g.nx && y < g.ny && z < g.nz)
+                v = *reinterpret_cast<const T *>(
+                    phi + (static_cast<int64_t>(z) * g.ny + y) * g.nx + x);
+        }
+        *reinterpret_cast<T *>(out + p * g.tp + static_cast<int64_t>(r) * V) = v;
+        if (ids_out && r == 0) ids_out[p] = t;
+    }
+}
+
+template <class S>
+static int band_gather(const S *phi, const ls_grid *grid, const int32_t *tiles,
+                       const int32_t *ntiles_dev, S *out, int32_t *ids_out, int64_t capacity,
+                       hipStream_t stream) {
+    Geom G;
+    int rc = make_geom(grid, &G);
+    if (rc != LS_OK) return rc;
+    if (!phi || !tiles || !ntiles_dev || !out) {
+        set_error("gather: phi, tiles, ntiles_dev and out must be non-NULL");
+        return LS_ERR_ARG;
+    }
+    if (capacity < 0 || capacity > G.ntiles) {
+        set_error("gather: capacity must be in [0, %lld] (got %lld)", (long long)G.ntiles,
+                  (long long)capacity);
+        return LS_ERR_ARG;
+    }
+    if (capacity == 0) return LS_OK;
+    const int64_t tp = int64_t(G.tx) * G.ty * G.tz;
+    if (tp > INT32_MAX / 4) {
+        set_error("gather: tile of %lld points too large", (long long)tp);
+        return LS_ERR_UNSUPPORTED;
+    }
+    GatherGeom g;
+    g.nx = G.nx, g.ny = G.ny, g.nz = G.nz;
+    g.tx = G.tx, g.ty = G.ty, g.tz = G.tz;
+    g.ntx = G.ntx, g.nty = G.nty;
+    g.tp = static_cast<int32_t>(tp);
+    g.ntiles = G.ntiles;
+    g.capacity = capacity;
+    DeviceInfo di;
+    if ((rc = device_info(&di)) != LS_OK) return rc;
+    int64_t slot;
+    if ((rc = stats_before(LS_KERNEL_GATHER, stream, &slot)) != LS_OK) return rc;
+    bool quads = false;
+    if constexpr (!std::is_same<S, double>::value) {
+        using T = typename GatherQuad<S>::T;
+        quads = G.tx % 4 == 0 && G.nx % 4 == 0 &&
+                reinterpret_cast<uintptr_t>(phi) % sizeof(T) == 0 &&
+                reinterpret_cast<uintptr_t>(out) % sizeof(T) == 0;
+        if (quads) {
+            const int64_t work = capacity * (tp / 4);
+            const unsigned blocks = static_cast<unsigned>(
+                std::max<int64_t>(1, std::min<int64_t>(cdiv64(work, kBlock), int64_t(di.cus) * 16)));
+            hipLaunchKernelGGL((band_gather_kernel<S, T, 4>), dim3(blocks), dim3(kBlock), 0, stream,
+                               g, phi, tiles, ntiles_dev, out, ids_out);
+            LS_LAUNCH_CHECK("band_gather_kernel");
+        }
+    }
+    if (!quads) {
+        const int64_t work = capacity * tp;
+        const unsigned blocks = static_cast<unsigned>(
+            std::max<int64_t>(1, std::min<int64_t>(cdiv64(work, kBlock), int64_t(di.cus) * 16)));
+        hipLaunchKernelGGL((band_gather_kernel<S, S, 1>), dim3(blocks), dim3(kBlock), 0, stream, g,
+                           phi, tiles, ntiles_dev, out, ids_out);
+        LS_LAUNCH_CHECK("band_gather_kernel");
+    }
+    return stats_after(LS_KERNEL_GATHER, stream, slot);
+}
+
+}  // namespace ls
+
+extern "C" {
+
+int ls_band_gather_f32(const float *phi, const ls_grid *g, const int32_t *tiles,
+                       const int32_t *ntiles_dev, float *out, int32_t *ids_out, int64_t capacity,
+                       void *stream) {
+    ls::clear_error();
+    return ls::band_gather<float>(phi, g, tiles, ntiles_dev, out, ids_out, capacity,
+                                  static_cast<hipStream_t>(stream));
+}
+
+int ls_band_gather_f64(const double *phi, const ls_grid *g, const int32_t *tiles,
+                       const int32_t *ntiles_dev, double *out, int32_t *ids_out,
+                       int64_t capacity, void *stream) {
+    ls::clear_error();
+    return ls::band_gather<double>(phi, g, tiles, ntiles_dev, out, ids_out, capacity,
+                                   static_cast<hipStream_t>(stream));
+}
+
+int ls_band_gather_f16s(const uint16_t *phi_h, const ls_grid *g, const int32_t *tiles,
+                        const int32_t *ntiles_dev, uint16_t *out, int32_t *ids_out,
+                        int64_t capacity, void *stream) {
+    ls::clear_error();
+    return ls::band_gather<uint16_t>(phi_h, g, tiles, ntiles_dev, out, ids_out, capacity,
+                                     static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

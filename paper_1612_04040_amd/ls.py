@@ -116,6 +116,9 @@ _SIGNATURES = {
                                       _I32, _VP, _I64, _VP, _VP, _VP, _VP, _I64, _VP]),
     "ls_band_run_reinit_f16s": (_I32, [_VP, _F32, _VP, _G, _F32, _F32, _F32, _F32, _F32, _I32,
                                        _I32, _I32, _VP, _I64, _VP, _VP, _VP, _VP, _I64, _VP]),
+    "ls_band_gather_f32": (_I32, [_VP, _G, _VP, _VP, _VP, _VP, _I64, _VP]),
+    "ls_band_gather_f64": (_I32, [_VP, _G, _VP, _VP, _VP, _VP, _I64, _VP]),
+    "ls_band_gather_f16s": (_I32, [_VP, _G, _VP, _VP, _VP, _VP, _I64, _VP]),
     "ls_set_tuning": (_I32, [ctypes.c_void_p]),
     "ls_get_tuning": (_I32, [ctypes.c_void_p]),
     "ls_upwind_launch_info": (_I32, [_G, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
@@ -150,6 +153,7 @@ _SIGNATURES = {
 LS_KERNEL_UPWIND = 0
 LS_KERNEL_BAND_FLAG = 1
 LS_KERNEL_REINIT = 2
+LS_KERNEL_GATHER = 3
 
 
 def lib():
@@ -411,6 +415,26 @@ def ls_band_run_reinit_f16s(phi_h, scale, F, g, dx, dt, beta, gamma, dtau, reini
                                                 _ptr(tile_steps_dev), _ptr(scratch),
                                                 _ptr(workspace), workspace_bytes,
                                                 _stream(stream)))
+
+
+def _gather(name, phi, g, tiles, ntiles_dev, out, ids_out, capacity, stream):
+    return _check(getattr(lib(), name)(_ptr(phi), _g(g), _ptr(tiles), _ptr(ntiles_dev),
+                                       _ptr(out), _ptr(ids_out), capacity, _stream(stream)))
+
+
+def ls_band_gather_f32(phi, g, tiles, ntiles_dev, out, ids_out, capacity, stream=None):
+    return _gather("ls_band_gather_f32", phi, g, tiles, ntiles_dev, out, ids_out, capacity,
+                   stream)
+
+
+def ls_band_gather_f64(phi, g, tiles, ntiles_dev, out, ids_out, capacity, stream=None):
+    return _gather("ls_band_gather_f64", phi, g, tiles, ntiles_dev, out, ids_out, capacity,
+                   stream)
+
+
+def ls_band_gather_f16s(phi_h, g, tiles, ntiles_dev, out, ids_out, capacity, stream=None):
+    return _gather("ls_band_gather_f16s", phi_h, g, tiles, ntiles_dev, out, ids_out, capacity,
+                   stream)
 
 
 def ls_stats_enable(on):

@@ -1,0 +1,103 @@
+"""Asynchronous band snapshots of a running field.
+
+The output of the narrow-band algorithm (Sec. 1.1, Step 4) taken off the GPU
+without stalling it: ``take`` enqueues, on the compute stream, the band gather
+(``ls_band_gather_*``: the band tiles' values, tile-major, and their ids) into
+one of two device staging buffers and a 4-byte copy of the band count into
+pinned host memory.  The large device-to-host copy of a snapshot is enqueued
+on a separate copy stream once its count is on the host, which is at the
+next ``take`` (a window later, so the host never waits on work the GPU has
+not reached) or at ``Snapshot.wait``.  Gather k + 2 reuses the staging buffer
+of snapshot k and waits, on the GPU, for that buffer's copy to finish; the
+host buffer of snapshot k is reused by snapshot k + 2, so a snapshot's data
+must be read (``wait``) before two more are taken.
+
+Streams, events and pinned buffers are torch's; the gather is the library's
+kernel, the copies are DMA transfers.
+"""
+import numpy as np
+import torch
+
+_DTYPES = {"f32": torch.float32, "f64": torch.float64, "f16s": torch.float16}
+
+
+class Snapshot:
+    """A snapshot in flight; ``wait`` returns (tile ids, values (n, tz, ty, tx))."""
+
+    def __init__(self, owner, slot, serial):
+        self._owner, self._slot, self._serial = owner, slot, serial
+        self._result = None
+
+    def wait(self):
+        if self._result is None:
+            self._result = self._owner._finish(self._slot, self._serial)
+        return self._result
+
+
+class Snapshots:
+    def __init__(self, bg, capacity=None):
+        self.bg = bg
+        dev = bg.tiles.device
+        self.tile = bg.tile
+        self.tp = int(np.prod(self.tile))
+        self.cap = bg.capacity if capacity is None else int(capacity)
+        dt = _DTYPES[bg.precision]
+        self.stage = [torch.empty(self.cap * self.tp, dtype=dt, device=dev) for _ in range(2)]
+        self.stage_ids = [torch.empty(self.cap, dtype=torch.int32, device=dev) for _ in range(2)]
+        self.host = [torch.empty(self.cap * self.tp, dtype=dt).pin_memory() for _ in range(2)]
+        self.host_ids = [torch.empty(self.cap, dtype=torch.int32).pin_memory() for _ in range(2)]
+        self.count = torch.zeros(2, dtype=torch.int32).pin_memory()
+        self.copy_stream = torch.cuda.Stream(dev)
+        self.gathered = [torch.cuda.Event() for _ in range(2)]
+        self.copied = [torch.cuda.Event() for _ in range(2)]
+        self.serial = [-1, -1]       # snapshot held by each slot
+        self.copy_issued = [True, True]
+        self.consumed = [True, True]
+        self.taken = 0
+
+    def take(self, phi, stream=None):
+        """Snapshot of phi on the band the BandGrid holds, enqueued on `stream`."""
+        s = torch.cuda.current_stream(self.bg.tiles.device) if stream is None else stream
+        # the previous snapshot's count is on the host by now: start its copy
+        prev = (self.taken - 1) % 2
+        if self.taken > 0 and not self.copy_issued[prev]:
+            self._issue_copy(prev)
+        i = self.taken % 2
+        if not self.consumed[i]:
+            raise RuntimeError("snapshot buffers full: wait() on the snapshot taken two "
+                               "takes ago before taking another")
+        if self.serial[i] >= 0:
+            s.wait_event(self.copied[i])  # its staging buffer is free once copied
+        self.bg.gather(phi, self.stage[i], ids=self.stage_ids[i], capacity=self.cap, stream=s)
+        with torch.cuda.stream(s):
+            self.count[i:i + 1].copy_(self.bg.ntiles[:1], non_blocking=True)
+        self.gathered[i].record(s)
+        self.serial[i] = self.taken
+        self.copy_issued[i] = False
+        self.consumed[i] = False
+        snap = Snapshot(self, i, self.taken)
+        self.taken += 1
+        return snap
+
+    def _issue_copy(self, i):
+        self.gathered[i].synchronize()  # gather and count done
+        n = min(int(self.count[i]), self.cap)
+        with torch.cuda.stream(self.copy_stream):
+            self.copy_stream.wait_event(self.gathered[i])
+            self.host[i][: n * self.tp].copy_(self.stage[i][: n * self.tp], non_blocking=True)
+            self.host_ids[i][:n].copy_(self.stage_ids[i][:n], non_blocking=True)
+            self.copied[i].record(self.copy_stream)
+        self.copy_issued[i] = True
+
+    def _finish(self, i, serial):
+        if self.serial[i] != serial:
+            raise RuntimeError("snapshot overwritten before it was read")
+        if not self.copy_issued[i]:
+            self._issue_copy(i)
+        self.copied[i].synchronize()
+        n = min(int(self.count[i]), self.cap)
+        ids = self.host_ids[i][:n].numpy().copy()
+        vals = self.host[i][: n * self.tp].numpy().copy()
+        tx, ty, tz = self.tile
+        self.consumed[i] = True
+        return ids, vals.reshape(n, tz, ty, tx)

@@ -206,6 +206,22 @@ def test_reinit_errors(fn):
     assert _status(run, *run_args(cap=cap - 1)) == ls.LS_ERR_CAPACITY
 
 
+@pytest.mark.parametrize("fn", ["f32", "f64", "f16s"])
+def test_gather_errors(fn):
+    g = ls.grid((40, 24, 16))
+    cap = ls.ls_grid_tiles(g)
+    gather = getattr(ls, f"ls_band_gather_{fn}")
+    base = dict(phi=FAKE, g=g, tiles=FAKE, n=FAKE, out=FAKE * 2, ids=None, cap=cap, stream=0)
+    for over in [dict(phi=None), dict(tiles=None), dict(n=None), dict(out=None),
+                 dict(cap=-1), dict(cap=cap + 1), dict(g=ls.grid((40, 24, 0)))]:
+        a = dict(base)
+        a.update(over)
+        assert _status(gather, *a.values()) == ls.LS_ERR_ARG, over
+    a = dict(base)
+    a.update(cap=0)
+    assert gather(*a.values()) == ls.LS_OK
+
+
 def test_run_errors():
     g = ls.grid((32, 32, 32))
     cap = ls.ls_grid_tiles(g)

@@ -1,0 +1,98 @@
+"""Band snapshots on the GPU: the gather against the oracle's definition, bit
+for bit, and the asynchronous snapshot pipeline against synchronous copies of
+the same (deterministic) run."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import dev, host, random_tiles, to_dev
+from paper_1612_04040_amd import workloads as W
+from paper_1612_04040_amd.band import BandGrid
+from paper_1612_04040_amd.snapshot import Snapshots
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # dims, tile, precision, tile fraction, capacity cut
+    ((64, 64, 64), (8, 8, 8), "f32", 0.4, None),    # quads
+    ((68, 45, 33), (8, 8, 8), "f32", 0.6, None),    # quads, partial tiles in y and z
+    ((67, 45, 33), (8, 8, 8), "f32", 0.6, None),    # nx odd: single points
+    ((40, 24, 16), (8, 8, 8), "f16s", 0.5, None),
+    ((13, 9, 7), (4, 3, 2), "f64", 0.7, None),
+    ((100, 36, 20), (16, 4, 4), "f32", 0.5, 7),     # capacity below the count
+    ((37, 21, 18), (8, 8, 8), "f64", 1.0, None),
+]
+
+
+@pytest.mark.parametrize("dims,tile,precision,frac,cap", CASES)
+def test_gather_equals_oracle(dims, tile, precision, frac, cap):
+    rng = np.random.default_rng(sum(dims) + len(precision))
+    nx, ny, nz = dims
+    dtype = {"f32": np.float32, "f64": np.float64, "f16s": np.float16}[precision]
+    phi = rng.standard_normal((nz, ny, nx)).astype(dtype)
+    tiles = random_tiles(rng, oracle.tile_count(dims, tile), frac)
+    bg = BandGrid(dims, tile, precision)
+    bg.tiles[: tiles.size] = torch.from_numpy(tiles).to(dev())
+    bg.ntiles.fill_(int(tiles.size))
+    capacity = bg.capacity if cap is None else cap
+    tp = int(np.prod(tile))
+    out = torch.full((capacity * tp,), 7, dtype=bg.scratch.dtype, device=dev())
+    ids = torch.full((capacity,), -5, dtype=torch.int32, device=dev())
+    bg.gather(torch.from_numpy(phi).to(dev()), out, ids=ids, capacity=capacity)
+    n = min(tiles.size, capacity)
+    want = oracle.gather_tiles(phi, tiles[:n], tile)
+    got = host(out)[: n * tp].reshape(want.shape)
+    assert got.tobytes() == want.tobytes()
+    assert host(ids)[:n].tolist() == tiles[:n].tolist()
+    # nothing beyond the first n tiles is written
+    assert np.all(host(out)[n * tp:] == 7) and np.all(host(ids)[n:] == -5)
+
+
+def test_async_snapshots_equal_synchronous_ones():
+    """Six windows of the band driver with a snapshot after each, no host
+    synchronisation between them (the copies run on their own stream while the
+    next windows compute), against the same run with the field and the band
+    list read back after every window."""
+    n = 96
+    wl = W.three_spheres_f32(n, 60)
+    g = float(np.float32(wl.gamma))
+    bg = BandGrid((n, n, n), wl.tile, "f32")
+    fd = to_dev(wl.F)
+
+    ref = []
+    p = to_dev(wl.phi)
+    for _ in range(6):
+        bg.run(p, fd, wl.dx, wl.dt, g, 10, 10)
+        band = bg.band_list().numpy()
+        ref.append((band, oracle.gather_tiles(host(p), band)))
+
+    snaps = Snapshots(bg)
+    p = to_dev(wl.phi)
+    got = []
+    pending = []
+    for _ in range(6):
+        bg.run(p, fd, wl.dx, wl.dt, g, 10, 10)
+        pending.append(snaps.take(p))
+        if len(pending) == 2:
+            got.append(pending.pop(0).wait())
+    got += [s.wait() for s in pending]
+    assert len(got) == 6
+    for k, ((ids, vals), (band, want)) in enumerate(zip(got, ref)):
+        assert ids.tolist() == band.tolist(), k
+        assert vals.tobytes() == want.tobytes(), k
+
+
+def test_snapshot_buffers_full_is_an_error():
+    bg = BandGrid((32, 32, 32), (8, 8, 8), "f32")
+    bg.tiles[:4] = torch.arange(4, dtype=torch.int32, device=dev())
+    bg.ntiles.fill_(4)
+    phi = torch.zeros((32, 32, 32), device=dev())
+    snaps = Snapshots(bg)
+    a = snaps.take(phi)
+    snaps.take(phi)
+    with pytest.raises(RuntimeError):
+        snaps.take(phi)
+    ids, vals = a.wait()
+    assert ids.tolist() == [0, 1, 2, 3] and vals.shape == (4, 8, 8, 8)
+    snaps.take(phi)
