@@ -76,14 +76,15 @@ def parse():
 
 
 STEP_KERNEL_SOURCES = ("ls_internal.h", "ls_stencil.h", "ls_step.hip", "ls_batch.hip")
+GATHER_KERNEL_SOURCES = ("ls_internal.h", "ls_snapshot.hip")
 
 
-def kernel_source_digest():
-    """Digest of the sources the band step kernel is compiled from."""
+def kernel_source_digest(sources=None):
+    """Digest of the sources a kernel is compiled from (default: the band step)."""
     here = os.path.dirname(os.path.abspath(__file__))
     csrc = os.path.join(here, "paper_1612_04040_amd", "csrc")
     h = hashlib.sha256()
-    for f in STEP_KERNEL_SOURCES:
+    for f in (STEP_KERNEL_SOURCES if sources is None else sources):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -436,6 +437,7 @@ def main():
             return 2
         r = _snapshot_run(args, torch, ls, W, BandGrid, dev)
         gbps = r["gather_bytes_per_launch"] / (r["gather_avg_us"] * 1e-6) / 1e9
+        gdigest = kernel_source_digest(GATHER_KERNEL_SOURCES)
         if args.calibrate_copy:
             _calibration_copies(torch, ls, dev)
         if rank == 0:
@@ -455,9 +457,12 @@ def main():
                 "snapshot_mb": round(r["snapshot_mb"], 2),
                 "roofline": {"bound": "hbm", "kernel": "ls::band_gather_kernel (f32 quads)",
                              "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": round(gbps / HBM_PEAK_GBS, 4), "traffic": None,
+                             "frac": round(gbps / HBM_PEAK_GBS, 4),
+                             "traffic": measured_traffic("gather", r["config"]["workload"],
+                                                         gdigest),
                              "bytes_per_launch_alg": int(r["gather_bytes_per_launch"]),
                              "avg_launch_us": round(r["gather_avg_us"], 3)},
+                "kernel_source_digest": gdigest,
                 "cpu_baseline": None,
             }), flush=True)
         return 0

@@ -1,16 +1,16 @@
 """Asynchronous band snapshots of a running field.
 
 The output of the narrow-band algorithm (Sec. 1.1, Step 4) taken off the GPU
-without stalling it: ``take`` enqueues, on the compute stream, the band gather
-(``ls_band_gather_*``: the band tiles' values, tile-major, and their ids) into
-one of two device staging buffers and a 4-byte copy of the band count into
-pinned host memory.  The large device-to-host copy of a snapshot is enqueued
-on a separate copy stream once its count is on the host, which is at the
-next ``take`` (a window later, so the host never waits on work the GPU has
-not reached) or at ``Snapshot.wait``.  Gather k + 2 reuses the staging buffer
-of snapshot k and waits, on the GPU, for that buffer's copy to finish; the
-host buffer of snapshot k is reused by snapshot k + 2, so a snapshot's data
-must be read (``wait``) before two more are taken.
+while it keeps computing: ``take`` enqueues, on the compute stream, the band
+gather (``ls_band_gather_*``: the band tiles' values, tile-major, and their
+ids) into one of two device staging buffers and a 4-byte copy of the band
+count into pinned host memory, waits on the host until the gather is done
+(the size of the copy is the band count), then enqueues the device-to-host
+copy of exactly that many tiles on a separate copy stream and returns; the
+caller enqueues the next windows while the copy runs.  Gather k + 2 reuses
+the staging buffer of snapshot k and waits, on the GPU, for that buffer's
+copy to finish; the host buffer of snapshot k is reused by snapshot k + 2,
+so a snapshot's data must be read (``wait``) before two more are taken.
 
 Streams, events and pinned buffers are torch's; the gather is the library's
 kernel, the copies are DMA transfers.
@@ -58,10 +58,6 @@ class Snapshots:
     def take(self, phi, stream=None):
         """Snapshot of phi on the band the BandGrid holds, enqueued on `stream`."""
         s = torch.cuda.current_stream(self.bg.tiles.device) if stream is None else stream
-        # the previous snapshot's count is on the host by now: start its copy
-        prev = (self.taken - 1) % 2
-        if self.taken > 0 and not self.copy_issued[prev]:
-            self._issue_copy(prev)
         i = self.taken % 2
         if not self.consumed[i]:
             raise RuntimeError("snapshot buffers full: wait() on the snapshot taken two "
@@ -75,6 +71,7 @@ class Snapshots:
         self.serial[i] = self.taken
         self.copy_issued[i] = False
         self.consumed[i] = False
+        self._issue_copy(i)
         snap = Snapshot(self, i, self.taken)
         self.taken += 1
         return snap
