@@ -10,7 +10,10 @@ copy of exactly that many tiles on a separate copy stream and returns; the
 caller enqueues the next windows while the copy runs.  Gather k + 2 reuses
 the staging buffer of snapshot k and waits, on the GPU, for that buffer's
 copy to finish; the host buffer of snapshot k is reused by snapshot k + 2,
-so a snapshot's data must be read (``wait``) before two more are taken.
+so a snapshot must be waited for before two more are taken, and the arrays
+``wait`` returns are views of the pinned buffers, valid until then (``wait(
+copy=True)`` returns owned copies, at the cost of a host copy of the whole
+snapshot, which stalls the thread that enqueues the GPU work).
 
 Streams, events and pinned buffers are torch's; the gather is the library's
 kernel, the copies are DMA transfers.
@@ -28,10 +31,11 @@ class Snapshot:
         self._owner, self._slot, self._serial = owner, slot, serial
         self._result = None
 
-    def wait(self):
+    def wait(self, copy=False):
         if self._result is None:
             self._result = self._owner._finish(self._slot, self._serial)
-        return self._result
+        ids, vals = self._result
+        return (ids.copy(), vals.copy()) if copy else (ids, vals)
 
 
 class Snapshots:
@@ -93,8 +97,8 @@ class Snapshots:
             self._issue_copy(i)
         self.copied[i].synchronize()
         n = min(int(self.count[i]), self.cap)
-        ids = self.host_ids[i][:n].numpy().copy()
-        vals = self.host[i][: n * self.tp].numpy().copy()
+        ids = self.host_ids[i][:n].numpy()
+        vals = self.host[i][: n * self.tp].numpy()
         tx, ty, tz = self.tile
         self.consumed[i] = True
         return ids, vals.reshape(n, tz, ty, tx)

@@ -75,8 +75,8 @@ def test_async_snapshots_equal_synchronous_ones():
         bg.run(p, fd, wl.dx, wl.dt, g, 10, 10)
         pending.append(snaps.take(p))
         if len(pending) == 2:
-            got.append(pending.pop(0).wait())
-    got += [s.wait() for s in pending]
+            got.append(pending.pop(0).wait(copy=True))
+    got += [s.wait(copy=True) for s in pending]
     assert len(got) == 6
     for k, ((ids, vals), (band, want)) in enumerate(zip(got, ref)):
         assert ids.tolist() == band.tolist(), k
