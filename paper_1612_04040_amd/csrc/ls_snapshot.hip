@@ -3,11 +3,13 @@
 // algorithm in Sec. 1.1, restricted to the band), so that one contiguous
 // device-to-host copy of the first n tiles takes the snapshot off the GPU.
 //
-// One thread moves 4 x-consecutive points of a tile row (a 16-byte FP32 or an
-// 8-byte FP16 access) when the rows allow it, else one point; a grid-stride
-// loop over (tile, row, quad) keeps the reads of a tile row and the writes of
-// the dense buffer contiguous.  The band count is read on the device, so the
-// call needs no host synchronisation.
+// When the rows allow 4-point vector accesses (a 16-byte FP32 or an 8-byte
+// FP16 access per thread), a block gathers a chunk of G consecutive band tiles
+// through LDS: it reads each grid row across the chunk's tiles together (band
+// tiles that follow each other in x are adjacent in the grid, so an x-run of
+// them is read as whole cache lines), then writes the chunk, tile-major, as
+// one contiguous block.  Otherwise one thread moves one point.  The band count
+// is read on the device, so the call needs no host synchronisation.
 #include <algorithm>
 #include <type_traits>
 
@@ -74,6 +76,48 @@ __global__ __launch_bounds__(kBlock) void band_gather_kernel(GatherGeom g, const
     }
 }
 
+// Chunked form: G tiles per chunk, tp / 4 quads per tile staged in LDS.
+template <class S, class T>
+__global__ __launch_bounds__(kBlock) void band_gather_chunk_kernel(
+    GatherGeom g, int G, const S *__restrict__ phi, const int32_t *__restrict__ tiles,
+    const int32_t *__restrict__ ntiles_dev, S *__restrict__ out, int32_t *__restrict__ ids_out) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *lds = reinterpret_cast<T *>(smem);
+    const int64_t n = min(static_cast<int64_t>(max(*ntiles_dev, 0)), g.capacity);
+    const int per_row = g.tx / 4, per_tile = g.tp / 4;
+    const int64_t nchunks = (n + G - 1) / G;
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {  // uniform per block
+        const int cnt = static_cast<int>(min(static_cast<int64_t>(G), n - c * G));
+        // reads: quad xq of row `row` of chunk tile gt, xq fastest, then the tile
+        for (int e = threadIdx.x; e < G * per_tile; e += kBlock) {
+            const int xq = e % per_row, t2 = e / per_row, gt = t2 % G, row = t2 / G;
+            if (gt >= cnt) continue;
+            const int t = tiles[c * G + gt];
+            T v = GatherQuad<S>::zero();
+            if (t >= 0 && t < g.ntiles) {
+                const int ti = t % g.ntx, rr = t / g.ntx;
+                const int ly = row % g.ty, lz = row / g.ty;
+                const int x = ti * g.tx + xq * 4, y = (rr % g.nty) * g.ty + ly,
+                          z = (rr / g.nty) * g.tz + lz;
+                if (x < g.nx && y < g.ny && z < g.nz)
+                    v = *reinterpret_cast<const T *>(
+                        phi + (static_cast<int64_t>(z) * g.ny + y) * g.nx + x);
+            }
+            lds[gt * per_tile + row * per_row + xq] = v;
+        }
+        __syncthreads();
+        // writes: the chunk's cnt tiles, contiguous
+        T *dst = reinterpret_cast<T *>(out + c * G * g.tp);
+        for (int e = threadIdx.x; e < cnt * per_tile; e += kBlock) dst[e] = lds[e];
+        if (ids_out)
+            for (int e = threadIdx.x; e < cnt; e += kBlock) ids_out[c * G + e] = tiles[c * G + e];
+        __syncthreads();  // LDS free for the next chunk
+    }
+}
+
+// LDS bytes staged per chunk of the chunked form.
+constexpr int kGatherChunkBytes = 16384;
+
 template <class S>
 static int band_gather(const S *phi, const ls_grid *grid, const int32_t *tiles,
                        const int32_t *ntiles_dev, S *out, int32_t *ids_out, int64_t capacity,
@@ -113,7 +157,17 @@ static int band_gather(const S *phi, const ls_grid *grid, const int32_t *tiles,
         quads = G.tx % 4 == 0 && G.nx % 4 == 0 &&
                 reinterpret_cast<uintptr_t>(phi) % sizeof(T) == 0 &&
                 reinterpret_cast<uintptr_t>(out) % sizeof(T) == 0;
-        if (quads) {
+        const int64_t chunk_tiles = kGatherChunkBytes / (tp * int64_t(sizeof(S)));
+        if (quads && chunk_tiles >= 2) {
+            const int chunk = static_cast<int>(chunk_tiles);
+            const int64_t chunks = cdiv64(capacity, chunk);
+            const unsigned blocks = static_cast<unsigned>(
+                std::max<int64_t>(1, std::min<int64_t>(chunks, int64_t(di.cus) * 8)));
+            const size_t lds = static_cast<size_t>(chunk) * tp * sizeof(S);
+            hipLaunchKernelGGL((band_gather_chunk_kernel<S, T>), dim3(blocks), dim3(kBlock), lds,
+                               stream, g, chunk, phi, tiles, ntiles_dev, out, ids_out);
+            LS_LAUNCH_CHECK("band_gather_chunk_kernel");
+        } else if (quads) {
             const int64_t work = capacity * (tp / 4);
             const unsigned blocks = static_cast<unsigned>(
                 std::max<int64_t>(1, std::min<int64_t>(cdiv64(work, kBlock), int64_t(di.cus) * 16)));
