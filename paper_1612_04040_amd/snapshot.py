@@ -39,6 +39,11 @@ class Snapshot:
 
 
 class Snapshots:
+    """Snapshots of the fields of one BandGrid.  capacity: the most band tiles a
+    snapshot holds (default: every tile of the grid; a band beyond it is cut to
+    its first capacity tiles); two device staging buffers and two pinned host
+    buffers of that size are allocated up front."""
+
     def __init__(self, bg, capacity=None):
         self.bg = bg
         dev = bg.tiles.device
