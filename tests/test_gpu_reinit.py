@@ -285,3 +285,22 @@ def test_driver_f16s_equals_its_steps():
                 bg.reinit(b, dx, dtau, 6, gamma=gamma, scale=s)
         assert host(a).tobytes() == host(b).tobytes(), reinit
         assert not np.array_equal(host(a), h)
+
+
+def test_empty_band_changes_nothing():
+    """An empty band list: the cut-off steps, the reinitialisation steps (with
+    the clamp) and the gather leave every byte as it was."""
+    rng = np.random.default_rng(12)
+    dims = (40, 32, 24)
+    phi, dx = _field(rng, dims, np.float32)
+    bg = BandGrid(dims, (8, 8, 8), "f32")
+    bg.ntiles.zero_()
+    pd = to_dev(phi)
+    F = to_dev(rng.uniform(-1, 1, phi.shape).astype(np.float32))
+    bg.step(pd, F, dx, 0.5 * dx, 3, cutoff=(3 * dx, 6 * dx))
+    bg.reinit(pd, dx, 0.5 * dx, 4, gamma=2 * dx)
+    assert host(pd).tobytes() == phi.tobytes()
+    out = torch.full((bg.capacity * 512,), 3.0, device=dev())
+    ids = torch.full((bg.capacity,), -2, dtype=torch.int32, device=dev())
+    bg.gather(pd, out, ids=ids)
+    assert np.all(host(out) == 3.0) and np.all(host(ids) == -2)
