@@ -163,6 +163,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_1612_04040_amd.build` (no fallback exists)")
+        # torch first: its HIP runtime is then the one libls binds to (loading
+        # libls first would bring in a second runtime that sees no device once
+        # torch initialises its own)
+        import torch  # noqa: F401
         handle = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGNATURES.items():
             fn = getattr(handle, name)
