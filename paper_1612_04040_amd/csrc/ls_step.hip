@@ -499,10 +499,65 @@ static int check_cutoff(const CutOff<C> &cut) {
     return LS_OK;
 }
 
-// nsteps launches of the step kernel on the plan held by the workspace (the
-// update map, the work-item records and their count), then the copy-back of
-// the band when nsteps is odd.  With the cut-off on, the kernels scale the
-// speed by c(phi) of the centre point's step-n value.
+// What every launch sequence on the plan held by the workspace (the update
+// map, the work-item records and their count) shares: the kernel's row counts
+// and LDS size, whether the buffers allow the vectorised kernels, and the
+// arguments of every mode (the cut-off fields zero).
+template <class S, class FT>
+struct StepLaunch {
+    int nown, nhalo;
+    size_t lds;
+    int threads;
+    bool aligned;
+    StepArgs<S, FT> args;
+};
+
+template <class S, class FT>
+static StepLaunch<S, FT> step_launch(S *phi, const FT *F, typename Codec<S>::C scale,
+                                     const Geom &G, const StepGeom &sg, typename Codec<S>::C dx,
+                                     typename Codec<S>::C dt, S *scratch, uint8_t *ws) {
+    using C = typename Codec<S>::C;
+    const Workspace w = workspace_layout(G);
+    StepLaunch<S, FT> L;
+    const int rp = kBlock / sg.xl;
+    L.nown = pow2_at_least((G.ty * G.tz + rp - 1) / rp);
+    L.nhalo = pow2_at_least((2 * (G.ty + G.tz) + rp - 1) / rp);
+    L.lds = static_cast<size_t>(sg.sx) * sg.sy * (G.tz + 2) * sizeof(C);
+    L.threads = kBlock;
+    L.aligned = reinterpret_cast<uintptr_t>(phi) % 16 == 0 &&
+                reinterpret_cast<uintptr_t>(scratch) % 16 == 0 &&
+                reinterpret_cast<uintptr_t>(F) % 16 == 0;
+    StepArgs<S, FT> &a = L.args;
+    a.F = F;
+    a.rec = reinterpret_cast<int32_t *>(ws + w.items);
+    a.nitems = reinterpret_cast<int32_t *>(ws + w.counters);
+    a.range = nullptr;
+    a.inst = nullptr;
+    a.umap = ws + w.u_map;
+    a.orig = phi;
+    a.dx = dx;
+    a.dt = dt;
+    a.dtdx = static_cast<C>(static_cast<double>(dt) / static_cast<double>(dx));
+    a.scale = scale;
+    a.cut_beta = C(0);
+    a.cut_gamma = C(0);
+    a.cut_k = C(0);
+    return L;
+}
+
+// The band copied from scratch back into phi (after an odd number of launches).
+template <class S, class FT>
+static int copy_back(const StepGeom &sg, const StepLaunch<S, FT> &L, int nblocks, S *scratch,
+                     S *phi, hipStream_t stream) {
+    hipLaunchKernelGGL(band_copy_kernel<S>, dim3(nblocks), dim3(kBlock), 0, stream, sg,
+                       static_cast<const S *>(scratch), phi, L.args.rec, L.args.nitems);
+    LS_LAUNCH_CHECK("band_copy_kernel");
+    return LS_OK;
+}
+
+// nsteps launches of the step kernel on the plan held by the workspace, then
+// the copy-back of the band when nsteps is odd.  With the cut-off on, the
+// kernels scale the speed by c(phi) of the centre point's step-n value.
 template <class S, class FT>
 static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const Geom &G,
                          const StepGeom &sg, typename Codec<S>::C dx, typename Codec<S>::C dt,
@@ -512,42 +567,19 @@ static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const 
     using C = typename Codec<S>::C;
     constexpr bool EXACT = sizeof(C) == 8;
     if (nsteps == 0) return LS_OK;
-    const Workspace w = workspace_layout(G);
-    int32_t *items = reinterpret_cast<int32_t *>(ws + w.items);
-    int32_t *nitems = reinterpret_cast<int32_t *>(ws + w.counters);
-    const int rp = kBlock / sg.xl;
-    const int nown = pow2_at_least((G.ty * G.tz + rp - 1) / rp);
-    const int nhalo = pow2_at_least((2 * (G.ty + G.tz) + rp - 1) / rp);
-    size_t lds = static_cast<size_t>(sg.sx) * sg.sy * (G.tz + 2) * sizeof(C);
-    int threads = kBlock;
-    const bool aligned = reinterpret_cast<uintptr_t>(phi) % 16 == 0 &&
-                         reinterpret_cast<uintptr_t>(scratch) % 16 == 0 &&
-                         reinterpret_cast<uintptr_t>(F) % 16 == 0;
-    auto kernel = cut.on ? select_upwind_kernel<S, FT, EXACT, kCutoff>(sg, nown, nhalo, &lds,
-                                                                        &threads, aligned)
-                         : select_upwind_kernel<S, FT, EXACT, kPlain>(sg, nown, nhalo, &lds,
-                                                                       &threads, aligned);
+    StepLaunch<S, FT> L = step_launch<S, FT>(phi, F, scale, G, sg, dx, dt, scratch, ws);
+    auto kernel = cut.on ? select_upwind_kernel<S, FT, EXACT, kCutoff>(
+                               sg, L.nown, L.nhalo, &L.lds, &L.threads, L.aligned)
+                         : select_upwind_kernel<S, FT, EXACT, kPlain>(
+                               sg, L.nown, L.nhalo, &L.lds, &L.threads, L.aligned);
     int nblocks = 0;
     int rc;
-    if ((rc = persistent_grid(kernel, threads, lds, &nblocks, nullptr, G.ntiles)) != LS_OK)
+    if ((rc = persistent_grid(kernel, L.threads, L.lds, &nblocks, nullptr, G.ntiles)) != LS_OK)
         return rc;
-
-    StepArgs<S, FT> args;
-    args.F = F;
-    args.rec = items;
-    args.nitems = nitems;
-    args.range = nullptr;
-    args.inst = nullptr;
-    args.umap = ws + w.u_map;
-    args.orig = phi;
-    args.dx = dx;
-    args.dt = dt;
-    args.dtdx = static_cast<C>(static_cast<double>(dt) / static_cast<double>(dx));
-    args.scale = scale;
-    args.cut_beta = cut.beta;
-    args.cut_gamma = cut.gamma;
-    args.cut_k = C(0);
+    StepArgs<S, FT> &args = L.args;
     if (cut.on) {
+        args.cut_beta = cut.beta;
+        args.cut_gamma = cut.gamma;
         // from the arguments' values, in FP64: (gamma - beta)^3 for the exact
         // form, 1 / (gamma - beta) for the fast form
         const double d = static_cast<double>(cut.gamma) - static_cast<double>(cut.beta);
@@ -557,7 +589,7 @@ static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const 
     // single step if one is left; one pair of timing events around them all
     size_t lds2 = 0;
     int threads2 = 0, nblocks2 = 0;
-    auto kernel2 = cut.on ? nullptr : select_upwind2_kernel<S, FT, EXACT>(sg, aligned, &lds2,
+    auto kernel2 = cut.on ? nullptr : select_upwind2_kernel<S, FT, EXACT>(sg, L.aligned, &lds2,
                                                                           &threads2);
     const int pairs = (kernel2 && nsteps >= 2 && !land_in_scratch) ? nsteps / 2 : 0;
     const int singles = nsteps - 2 * pairs;
@@ -574,18 +606,12 @@ static int upwind_launch(S *phi, const FT *F, typename Codec<S>::C scale, const 
             hipLaunchKernelGGL(kernel2, dim3(nblocks2), dim3(threads2), lds2, stream, sg, args);
             LS_LAUNCH_CHECK("upwind_vec2_kernel");
         } else {
-            hipLaunchKernelGGL(kernel, dim3(nblocks), dim3(threads), lds, stream, sg, args);
+            hipLaunchKernelGGL(kernel, dim3(nblocks), dim3(L.threads), L.lds, stream, sg, args);
             LS_LAUNCH_CHECK("upwind_kernel");
         }
     }
     if ((rc = stats_after(LS_KERNEL_UPWIND, stream, slot)) != LS_OK) return rc;
-    if ((launches & 1) && !land_in_scratch) {
-        hipLaunchKernelGGL(band_copy_kernel<S>, dim3(nblocks), dim3(kBlock), 0, stream, sg,
-                           static_cast<const S *>(scratch), phi,
-                           static_cast<const int32_t *>(items),
-                           static_cast<const int32_t *>(nitems));
-        LS_LAUNCH_CHECK("band_copy_kernel");
-    }
+    if ((launches & 1) && !land_in_scratch) return copy_back(sg, L, nblocks, scratch, phi, stream);
     return LS_OK;
 }
 
@@ -602,57 +628,31 @@ static int reinit_launch(S *phi, typename Codec<S>::C scale, const Geom &G, cons
     using C = typename Codec<S>::C;
     constexpr bool EXACT = sizeof(C) == 8;
     if (niter == 0) return LS_OK;
-    const Workspace w = workspace_layout(G);
-    int32_t *items = reinterpret_cast<int32_t *>(ws + w.items);
-    int32_t *nitems = reinterpret_cast<int32_t *>(ws + w.counters);
-    const int rp = kBlock / sg.xl;
-    const int nown = pow2_at_least((G.ty * G.tz + rp - 1) / rp);
-    const int nhalo = pow2_at_least((2 * (G.ty + G.tz) + rp - 1) / rp);
-    size_t lds = static_cast<size_t>(sg.sx) * sg.sy * (G.tz + 2) * sizeof(C);
-    int threads = kBlock;
-    const bool aligned = reinterpret_cast<uintptr_t>(phi) % 16 == 0 &&
-                         reinterpret_cast<uintptr_t>(scratch) % 16 == 0;
-    auto kernel = select_upwind_kernel<S, FT, EXACT, kReinit>(sg, nown, nhalo, &lds, &threads,
-                                                              aligned);
-    auto last = clamp ? select_upwind_kernel<S, FT, EXACT, kReinitClamp>(sg, nown, nhalo, &lds,
-                                                                          &threads, aligned)
+    StepLaunch<S, FT> L =
+        step_launch<S, FT>(phi, static_cast<const FT *>(nullptr), scale, G, sg, dx, dtau, scratch,
+                           ws);
+    auto kernel = select_upwind_kernel<S, FT, EXACT, kReinit>(sg, L.nown, L.nhalo, &L.lds,
+                                                              &L.threads, L.aligned);
+    auto last = clamp ? select_upwind_kernel<S, FT, EXACT, kReinitClamp>(
+                            sg, L.nown, L.nhalo, &L.lds, &L.threads, L.aligned)
                       : kernel;
     int nblocks = 0;
     int rc;
-    if ((rc = persistent_grid(kernel, threads, lds, &nblocks, nullptr, G.ntiles)) != LS_OK)
+    if ((rc = persistent_grid(kernel, L.threads, L.lds, &nblocks, nullptr, G.ntiles)) != LS_OK)
         return rc;
-    StepArgs<S, FT> args;
-    args.F = nullptr;
-    args.rec = items;
-    args.nitems = nitems;
-    args.range = nullptr;
-    args.inst = nullptr;
-    args.umap = ws + w.u_map;
-    args.orig = phi;
-    args.dx = dx;
-    args.dt = dtau;
-    args.dtdx = static_cast<C>(static_cast<double>(dtau) / static_cast<double>(dx));
-    args.scale = scale;
-    args.cut_beta = C(0);
+    StepArgs<S, FT> &args = L.args;
     args.cut_gamma = gamma;
-    args.cut_k = C(0);
     int64_t slot;
     if ((rc = stats_before(LS_KERNEL_REINIT, stream, &slot, niter)) != LS_OK) return rc;
     for (int l = 0; l < niter; ++l) {
         args.cur = (l & 1) ? scratch : phi;
         args.nxt = (l & 1) ? phi : scratch;
-        hipLaunchKernelGGL(l == niter - 1 ? last : kernel, dim3(nblocks), dim3(threads), lds,
+        hipLaunchKernelGGL(l == niter - 1 ? last : kernel, dim3(nblocks), dim3(L.threads), L.lds,
                            stream, sg, args);
         LS_LAUNCH_CHECK("upwind_kernel (reinit)");
     }
     if ((rc = stats_after(LS_KERNEL_REINIT, stream, slot)) != LS_OK) return rc;
-    if (niter & 1) {
-        hipLaunchKernelGGL(band_copy_kernel<S>, dim3(nblocks), dim3(kBlock), 0, stream, sg,
-                           static_cast<const S *>(scratch), phi,
-                           static_cast<const int32_t *>(items),
-                           static_cast<const int32_t *>(nitems));
-        LS_LAUNCH_CHECK("band_copy_kernel");
-    }
+    if (niter & 1) return copy_back(sg, L, nblocks, scratch, phi, stream);
     return LS_OK;
 }
 
