@@ -228,7 +228,7 @@ def test_spheres512_reinit_full_size_window(precision):
     del pd, fd
     want_band = oracle.band_tiles(phi0, wl.tile, g, dilate=True)
     assert band.tolist() == want_band.tolist()
-    m = oracle.tile_mask((512,) * 3, band)
+    m = oracle.tile_mask((512,) * 3, want_band)
     assert np.all(np.abs(got[m]) <= g)
     assert got[~m].tobytes() == phi0[~m].tobytes()
     moved = np.abs(got[m].astype(np.float64) - phi0[m]).max()
@@ -241,7 +241,7 @@ def test_spheres512_reinit_full_size_window(precision):
     c = near[rng.integers(len(near))]
     lo = np.clip((c - 64) // 8 * 8, 0, 512 - 128)
     crop = tuple(slice(int(a), int(a) + 128) for a in lo)
-    t = np.array(band, dtype=np.int64)
+    t = np.array(want_band, dtype=np.int64)
     ti, tj, tk = t % 64, (t // 64) % 64, t // 4096
     lt = lo // 8
     keep = ((ti >= lt[2]) & (ti < lt[2] + 16) & (tj >= lt[1]) & (tj < lt[1] + 16)
