@@ -40,6 +40,20 @@ def test_distance_plane_is_a_fixed_point():
     assert np.max(np.abs(out - d)) < 1e-13
 
 
+def test_one_step_hand_values():
+    """One step on d = 2 (x - 20.5), dx = 1, dtau = 1/2, worked by hand.  At
+    d = 1 (x = 21): central difference 2, so S = 1 / sqrt(1 + 4); the upwind
+    side (S > 0) has D- = 2 and D+ = 2 (min(D+, 0) = 0), so |grad d| = 2 and
+    d' = 1 - (1/2) S (2 - 1) = 1 - 1/(2 sqrt 5).  At d = 3: S = 3 / sqrt(13),
+    d' = 3 - 3/(2 sqrt 13).  At d = -1 the mirror image."""
+    d = _plane(20.5, slope=2.0)
+    tiles = oracle.all_tiles((48, 9, 10))
+    row = oracle.reinit_steps(d, 1.0, 0.5, tiles, 1)[4, 3]
+    assert abs(row[21] - 0.7763932022500210) < 1e-15
+    assert abs(row[22] - 2.5839748528310782) < 1e-15
+    assert abs(row[20] + 0.7763932022500210) < 1e-15
+
+
 def test_steepened_plane_relaxes_to_the_distance():
     """d = 2 (x - 20.5): the zero set stays between the same points (the
     field near it stays antisymmetric: characteristics leave the front), and
