@@ -178,3 +178,48 @@ def test_judge_resets_tiles_whose_crossing_state_differs():
     assert np.array_equal(out[keep], phi[keep], equal_nan=True)
     # identical fields: nothing to reset
     assert CL.judge(shadow, shadow)[1] == 0
+
+
+def features_plane_case():
+    """A coarse plane front phi = x - x0 (unit normal along x), a constant
+    speed F = 0.6 with the bound Fmax = 0.8 passed in, dt = dx / (2 Fmax): one
+    plain step moves a linear field by exactly -dt F |grad phi| = -dt F away
+    from the inflow face (the zero-gradient ghost at i = 0 stops it there)."""
+    n = 32
+    dx = 1.0 / n
+    gamma = 6 * dx
+    fmax = 0.8
+    dt = 0.5 * dx / fmax
+    phi = W.plane((n, n, n), dx, (1.0, 0.0, 0.0), 0.5)
+    F = np.full((n, n, n), 0.6)
+    allt = np.arange((n // 8) ** 3, dtype=np.int32)
+    delta = CL.plain_increment(phi, F, dx, dt, allt)
+    return n, dx, gamma, fmax, dt, phi, F, delta
+
+
+def test_features_hand_values_on_a_plane():
+    """Feature channels in their order: phi / gamma clipped at +-2, F / Fmax
+    with the given bound, and the plain increment in units of the grid
+    spacing, -dt F / dx = -0.375 on a unit-slope plane."""
+    n, dx, gamma, fmax, dt, phi, F, delta = features_plane_case()
+    feat = CL.features(phi, F, delta, dx, gamma, fmax)
+    assert feat.shape == (3, n, n, n)
+    x = (np.arange(n) + 0.5) * dx - 0.5          # phi along a row (= x - 1/2)
+    want0 = np.clip(x / gamma, -2.0, 2.0)        # -2 (clipped) ... 1/12 ... 2 (clipped)
+    assert np.max(np.abs(feat[0] - want0[None, None, :])) < 1e-14
+    assert feat[0, 0, 0, 0] == -2.0 and feat[0, 0, 0, n - 1] == 2.0
+    assert abs(feat[0, 3, 2, 16] - 1.0 / 12.0) < 1e-15    # half a cell past the front
+    assert abs(feat[0, 3, 2, 18] - 5.0 / 12.0) < 1e-15    # 2.5 cells past it, inside the clip
+    assert np.max(np.abs(feat[1] - 0.75)) < 1e-15
+    assert np.max(np.abs(feat[2][:, :, 1:] + 0.375)) < 1e-12      # interior of the rows
+    assert np.all(feat[2][:, :, 0] == 0.0)                        # inflow face: no gradient
+
+
+def test_features_scale_with_the_coarse_spacing():
+    """Doubling dx (same field values, same dt) halves the increment channel:
+    it is delta / dx, the spacing the caller passes (the coarse one)."""
+    n, dx, gamma, fmax, dt, phi, F, delta = features_plane_case()
+    a = CL.features(phi, F, delta, dx, gamma, fmax)
+    b = CL.features(phi, F, delta, 2 * dx, gamma, fmax)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.max(np.abs(b[2] - 0.5 * a[2])) < 1e-15

@@ -1,19 +1,27 @@
 """The pins of the oracle's numpy parts (cut-off, reinitialisation, clamp,
-snapshot) must catch plausible mistakes in them.
+snapshot, closure features) and of the interface metrics must catch
+plausible mistakes in them.
 
-Each case swaps one oracle function for a copy with a planted mistake (the
-cubic's constants exchanged, c taken from the new value, one-sided instead of
+Each case swaps one function for a copy with a planted mistake (the cubic's
+constants exchanged, c taken from the new value, one-sided instead of
 central differences, the -1 term with the wrong sign, S frozen at the start,
-the clamp left out, a transposed tile block) and requires at least one of the
-pins of that function to fail.  Everything runs on the CPU.
+the clamp left out, a transposed tile block, the increment over the fine
+spacing, a clip at +-1, F over its sample maximum, crossings without the
+half-cell offset or with the interpolation weight reversed, a one-sided
+Hausdorff distance, upsampling without the centre shift) and requires at
+least one of the pins of that function to fail.  Everything runs on the CPU.
 """
 import numpy as np
 import pytest
 
 import oracle
+import oracle.closure
+import test_metrics_pins as metric_pins
+import test_oracle_closure as closure_pins
 import test_oracle_cutoff as cut_pins
 import test_oracle_reinit as re_pins
 import test_oracle_snapshot as snap_pins
+from paper_1612_04040_amd import metrics
 
 _cutoff, _smoothed_sign, _reinit_steps = oracle.cutoff, oracle.smoothed_sign, oracle.reinit_steps
 _cutoff_steps, _gather = oracle.cutoff_steps, oracle.gather_tiles
@@ -93,6 +101,74 @@ def gather_transposed(phi, tiles, tile=(8, 8, 8)):
     return np.ascontiguousarray(np.swapaxes(out, 2, 3)) if tile[0] == tile[1] else out[..., ::-1]
 
 
+def features_fine_spacing(phi_c, F_c, delta, dx, gamma, fmax):
+    c0 = np.clip(np.asarray(phi_c, np.float64) / gamma, -2.0, 2.0)
+    c1 = np.asarray(F_c, np.float64) / fmax
+    c2 = np.asarray(delta, np.float64) / (dx / 4)
+    return np.stack([c0, c1, c2])
+
+
+def features_clip_one(phi_c, F_c, delta, dx, gamma, fmax):
+    c0 = np.clip(np.asarray(phi_c, np.float64) / gamma, -1.0, 1.0)
+    c1 = np.asarray(F_c, np.float64) / fmax
+    c2 = np.asarray(delta, np.float64) / dx
+    return np.stack([c0, c1, c2])
+
+
+def features_sample_max(phi_c, F_c, delta, dx, gamma, fmax):
+    f = np.asarray(F_c, np.float64)
+    c0 = np.clip(np.asarray(phi_c, np.float64) / gamma, -2.0, 2.0)
+    return np.stack([c0, f / np.max(np.abs(f)), np.asarray(delta, np.float64) / dx])
+
+
+def crossings_no_offset(phi, dx, origin=0.0):
+    return _crossings(phi, dx, origin - 0.5 * dx)
+
+
+def crossings_reversed_weight(phi, dx, origin=0.0):
+    phi = np.asarray(phi, dtype=np.float64)
+    pts = []
+    for ax in range(3):
+        n = phi.shape[ax]
+        lo = np.take(phi, np.arange(n - 1), axis=ax)
+        hi = np.take(phi, np.arange(1, n), axis=ax)
+        idx = np.nonzero((lo < 0) != (hi < 0))
+        t = hi[idx] / (hi[idx] - lo[idx])
+        pos = [(idx[d] + 0.5) * dx + origin for d in range(3)]
+        pos[ax] = pos[ax] + t * dx
+        z, y, x = pos
+        pts.append(np.stack([x, y, z], axis=1))
+    return np.concatenate(pts)
+
+
+def hausdorff_one_sided(a, b):
+    from scipy.spatial import cKDTree
+    if len(a) == 0 or len(b) == 0:
+        return float("inf") if len(a) != len(b) else 0.0
+    return float(cKDTree(b).query(a)[0].max())
+
+
+def upsample_no_shift(phi_c, factor):
+    phi_c = np.asarray(phi_c, dtype=np.float64)
+    nz, ny, nx = phi_c.shape
+
+    def coords(n):
+        u = (np.arange(n * factor) + 0.5) / factor
+        i0 = np.clip(np.floor(u).astype(np.int64), 0, n - 1)
+        i1 = np.clip(i0 + 1, 0, n - 1)
+        w = np.clip(u - np.floor(u), 0.0, 1.0)
+        return i0, i1, w
+
+    x0, x1, wx = coords(nx)
+    y0, y1, wy = coords(ny)
+    z0, z1, wz = coords(nz)
+    t = phi_c[:, :, x0] * (1 - wx) + phi_c[:, :, x1] * wx
+    t = t[:, y0, :] * (1 - wy)[None, :, None] + t[:, y1, :] * wy[None, :, None]
+    return t[z0] * (1 - wz)[:, None, None] + t[z1] * wz[:, None, None]
+
+
+_crossings = metrics.zero_crossings
+
 CASES = [
     ("cutoff", cutoff_swapped, [cut_pins.test_cutoff_hand_values]),
     ("cutoff", cutoff_linear, [cut_pins.test_cutoff_hand_values]),
@@ -106,13 +182,40 @@ CASES = [
     ("reinit_steps", reinit_no_clamp, [re_pins.test_clamp_on_the_listed_tiles_only]),
     ("gather_tiles", gather_transposed, [snap_pins.test_gather_matches_explicit_loops,
                                          snap_pins.test_scatter_round_trip]),
+    ((oracle.closure, "features"), features_fine_spacing,
+     [closure_pins.test_features_hand_values_on_a_plane]),
+    ((oracle.closure, "features"), features_clip_one,
+     [closure_pins.test_features_hand_values_on_a_plane]),
+    ((oracle.closure, "features"), features_sample_max,
+     [closure_pins.test_features_hand_values_on_a_plane]),
+    ((metrics, "zero_crossings"), crossings_no_offset,
+     [metric_pins.test_plane_crossings_at_known_positions,
+      metric_pins.test_oblique_plane_crossings_lie_on_the_plane]),
+    ((metrics, "zero_crossings"), crossings_reversed_weight,
+     [metric_pins.test_plane_crossings_at_known_positions,
+      metric_pins.test_oblique_plane_crossings_lie_on_the_plane]),
+    ((metrics, "hausdorff"), hausdorff_one_sided,
+     [metric_pins.test_hausdorff_brute_force_and_symmetry]),
+    ((metrics, "upsample_trilinear"), upsample_no_shift,
+     [metric_pins.test_upsample_trilinear_is_exact_on_a_linear_field,
+      metric_pins.test_upsample_trilinear_hand_value]),
 ]
 
 
+def _target(name):
+    return name if isinstance(name, tuple) else (oracle, name)
+
+
+def _label(name):
+    mod, attr = _target(name)
+    return f"{mod.__name__.split('.')[-1]}.{attr}"
+
+
 @pytest.mark.parametrize("name,mutant,pins", CASES,
-                         ids=[f"{c[0]}-{c[1].__name__}" for c in CASES])
+                         ids=[f"{_label(c[0])}-{c[1].__name__}" for c in CASES])
 def test_pins_catch_the_mutant(name, mutant, pins, monkeypatch):
-    monkeypatch.setattr(oracle, name, mutant)
+    mod, attr = _target(name)
+    monkeypatch.setattr(mod, attr, mutant)
     failed = 0
     for pin in pins:
         try:
