@@ -50,6 +50,13 @@ def _lib():
         lib.lso_band_tiles.argtypes = [vp, i32, i32, i32, i32, i32, i32, dbl, i32, vp, i64]
         lib.lso_upwind_steps.restype = i32
         lib.lso_upwind_steps.argtypes = [vp, vp, i32, i32, i32, dbl, dbl, i32, i32, i32, vp, i64, i32]
+        lib.lso_upwind_steps_stored.restype = i32
+        lib.lso_upwind_steps_stored.argtypes = [vp, vp, i32, i32, i32, dbl, dbl, i32, i32, i32, vp,
+                                                i64, i32, dbl]
+        lib.lso_set_threads.restype = None
+        lib.lso_set_threads.argtypes = [i32]
+        lib.lso_round_binary16.restype = None
+        lib.lso_round_binary16.argtypes = [vp, vp, i64]
         _LIB = lib
     return _LIB
 
@@ -57,6 +64,28 @@ def _lib():
 def max_threads():
     """OpenMP threads the oracle's parallel loops use."""
     return int(_lib().lso_max_threads())
+
+
+def set_threads(n):
+    """Sets the OpenMP threads of the oracle's parallel loops (n >= 1)."""
+    _lib().lso_set_threads(int(n))
+
+
+def round_binary16(x):
+    """x (float64) rounded to the nearest IEEE binary16 value, ties to even,
+    as an FP64 array (the rounding of the scaled-FP16 storage)."""
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty_like(a)
+    _lib().lso_round_binary16(a.ctypes.data, out.ctypes.data, int(a.size))
+    return out
+
+
+def store_f16s(v, scale):
+    """The value scaled-FP16 storage holds for v: fl32(fp16(v / s) * s), s the
+    FP32 scale promoted exactly."""
+    s = np.float64(np.float32(scale))
+    return (round_binary16(np.asarray(v, np.float64) / s) * s).astype(np.float32).astype(
+        np.float64)
 
 
 def _dims(a):
@@ -110,12 +139,17 @@ def all_tiles(dims, tile=(8, 8, 8)):
     return np.arange(tile_count(dims, tile), dtype=np.int32)
 
 
-def upwind_steps(phi, F, dx, dt, tiles, nsteps, tile=(8, 8, 8)):
+def upwind_steps(phi, F, dx, dt, tiles, nsteps, tile=(8, 8, 8), store_scale=None):
     """``nsteps`` Jacobi steps of Eq. 3-5 on the listed tiles, in FP64.
 
     Returns a new float64 array; ``phi`` and ``F`` are promoted exactly.
+    With ``store_scale`` s, every new value (of a point whose F is not zero)
+    is rounded to what scaled-FP16 storage holds, fl32(fp16(v / s) * s)
+    (``store_f16s``), before the next step reads it.
     Pinned by the plane, F = 0, expanding/shrinking sphere, reflection,
-    monotonicity and brute-force tests.
+    monotonicity and brute-force tests; the stored form by the binary16
+    rounding against numpy's conversion and by the elementwise equality of
+    one stored step with the FP64 step rounded afterwards.
     """
     p = np.array(phi, dtype=np.float64, order="C", copy=True)
     f = np.ascontiguousarray(F, dtype=np.float64)
@@ -123,8 +157,17 @@ def upwind_steps(phi, F, dx, dt, tiles, nsteps, tile=(8, 8, 8)):
         raise ValueError("phi and F shapes differ")
     t = np.ascontiguousarray(tiles, dtype=np.int32)
     nx, ny, nz = _dims(p)
-    rc = _lib().lso_upwind_steps(p.ctypes.data, f.ctypes.data, nx, ny, nz, float(dx), float(dt),
-                                 *tile, t.ctypes.data if t.size else None, int(t.size), int(nsteps))
+    if store_scale is None:
+        rc = _lib().lso_upwind_steps(p.ctypes.data, f.ctypes.data, nx, ny, nz, float(dx),
+                                     float(dt), *tile, t.ctypes.data if t.size else None,
+                                     int(t.size), int(nsteps))
+    else:
+        s = float(np.float32(store_scale))
+        if not s > 0:
+            raise ValueError("store_scale must be positive")
+        rc = _lib().lso_upwind_steps_stored(p.ctypes.data, f.ctypes.data, nx, ny, nz, float(dx),
+                                            float(dt), *tile, t.ctypes.data if t.size else None,
+                                            int(t.size), int(nsteps), s)
     if rc != 0:
         raise RuntimeError(f"lso_upwind_steps failed: {rc}")
     return p
@@ -237,42 +280,54 @@ def gather_tiles(phi, tiles, tile=(8, 8, 8)):
     return out
 
 
-def decide_precision(phi64, precision):
+def decide_precision(phi64, precision, scale=None):
     """The field on which the band decision is taken, in the kernel's precision.
 
     Where floating point decides an integer (tile membership), both sides
     decide in the same precision: the FP64 state is rounded to the storage
-    precision of the device path first ('f32' -> FP32, 'f64' -> as is).
+    precision of the device path first ('f32' -> FP32, 'f64' -> as is,
+    'f16s' -> the FP32 value scaled-FP16 storage of it would decode to,
+    fl32(fp16(phi / s) * s)).
     """
     if precision == "f64":
         return phi64
     if precision == "f32":
         return phi64.astype(np.float32)
+    if precision == "f16s":
+        return store_f16s(phi64, scale).astype(np.float32)
     raise ValueError(precision)
 
 
 def run_band(phi0, F, dx, dt, gamma, nsteps, window=10, tile=(8, 8, 8), precision="f32",
-             dilate=True, record_tiles=False, beta=None, reinit=None):
+             dilate=True, record_tiles=False, beta=None, reinit=None, scale=None,
+             store=False):
     """The narrow-band driver (Steps 1-3 of the algorithm in Sec. 1.1), FP64.
 
     Every ``window`` steps the band U is rebuilt from the current state
-    (decision in ``precision``), then the state is advanced on U: by the plain
-    steps of Eq. 3-5, or, with ``beta`` given, by the cut-off steps of Eq. 8
-    with the band's gamma.  With ``reinit = (dtau, niter)`` the window ends
-    with Step 3: ``niter`` reinitialisation steps (Eq. 12-13) on U and the
-    clamp of Eq. 10 to the band's gamma.  Returns the final FP64 field and, if
-    asked, the tile list of every window.
+    (decision in ``precision``; 'f16s' needs ``scale``), then the state is
+    advanced on U: by the plain steps of Eq. 3-5, or, with ``beta`` given, by
+    the cut-off steps of Eq. 8 with the band's gamma.  With ``reinit = (dtau,
+    niter)`` the window ends with Step 3: ``niter`` reinitialisation steps
+    (Eq. 12-13) on U and the clamp of Eq. 10 to the band's gamma.  With
+    ``store`` (plain steps, precision 'f16s') the state is held in scaled FP16
+    storage: every step's new values are rounded to it (``upwind_steps`` with
+    ``store_scale``), so the run is the FP64 scheme with FP16 stores.
+    Returns the final FP64 field and, if asked, the tile list of every window.
     """
+    if store and (precision != "f16s" or beta is not None or reinit is not None):
+        raise ValueError("stored runs are plain steps with precision 'f16s'")
     phi = np.array(phi0, dtype=np.float64, copy=True)
     lists = []
     done = 0
     while done < nsteps:
         n = min(window, nsteps - done)
-        gam = np.float32(gamma) if precision == "f32" else np.float64(gamma)
-        tiles = band_tiles(decide_precision(phi, precision), tile, gam, dilate)
+        gam = np.float32(gamma) if precision in ("f32", "f16s") else np.float64(gamma)
+        tiles = band_tiles(decide_precision(phi, precision, scale), tile, gam, dilate)
         if record_tiles:
             lists.append(tiles)
-        if beta is None:
+        if store:
+            phi = upwind_steps(phi, F, dx, dt, tiles, n, tile, store_scale=scale)
+        elif beta is None:
             phi = upwind_steps(phi, F, dx, dt, tiles, n, tile)
         else:
             phi = cutoff_steps(phi, F, dx, dt, tiles, n, beta, gamma, tile)

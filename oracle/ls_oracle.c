@@ -33,6 +33,10 @@
  *             front can move into it).
  *   step      Jacobi: every updated point reads only values of step n; points
  *             outside the listed tiles keep their value.
+ *   storage   optionally (store_scale s > 0) the state is held in scaled FP16,
+ *             an addition to the method: each new value v is stored as
+ *             h = fp16(v / s), rounded to nearest with ties to even, and read
+ *             back as fl32(h * s); a point whose F is zero keeps its value.
  */
 #include <math.h>
 #include <omp.h>
@@ -47,6 +51,45 @@
 
 /* Threads an OpenMP region of the oracle uses (for reporting only). */
 int lso_max_threads(void) { return omp_get_max_threads(); }
+
+/* Sets the threads of the following OpenMP regions (n >= 1). */
+void lso_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
+/*
+ * x rounded to the nearest IEEE binary16 value, ties to even: 10 fraction
+ * bits, so the spacing is 2^(e - 11) for |x| in [2^(e-1), 2^e), never below
+ * 2^-24 (the subnormal spacing); |x| >= 65520 (halfway between the largest
+ * finite value 65504 and 2^16) rounds to infinity.
+ */
+static double round_binary16(double x)
+{
+    if (x != x)
+        return x;
+    const double a = fabs(x);
+    if (a >= 65520.0)
+        return copysign(INFINITY, x);
+    if (a == 0.0)
+        return x;
+    int e;
+    frexp(a, &e); /* a = m 2^e, m in [1/2, 1) */
+    int q = e - 11;
+    if (q < -24)
+        q = -24;
+    /* a / 2^q is exact; nearbyint rounds to nearest, ties to even */
+    return copysign(ldexp(nearbyint(ldexp(a, -q)), q), x);
+}
+
+/* The stored value of v in scaled FP16: fl32(fp16(v / s) * s) (the product
+ * of an 11-bit and a 24-bit significand is exact in double). */
+static double store_f16s(double v, double s) { return (double)(float)(round_binary16(v / s) * s); }
+
+/* Elementwise round_binary16 (exposed so that tests can check it against an
+ * independent conversion). */
+void lso_round_binary16(const double *in, double *out, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = round_binary16(in[i]);
+}
 
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -182,9 +225,9 @@ static double upwind_point(const double *cur, const double *F, int64_t nx, int64
  * in place on phi.  Points of unlisted tiles keep their value.  The tile list
  * must be ascending and in range; returns a status.
  */
-int lso_upwind_steps(double *phi, const double *F, int nx, int ny, int nz,
-                     double dx, double dt, int tx, int ty, int tz,
-                     const int32_t *tiles, int64_t ntiles, int nsteps)
+int lso_upwind_steps_stored(double *phi, const double *F, int nx, int ny, int nz,
+                            double dx, double dt, int tx, int ty, int tz,
+                            const int32_t *tiles, int64_t ntiles, int nsteps, double store_scale)
 {
     if (!phi || !F || !dims_ok(nx, ny, nz, tx, ty, tz) || nsteps < 0 || ntiles < 0)
         return LSO_ERR_ARG;
@@ -214,8 +257,13 @@ int lso_upwind_steps(double *phi, const double *F, int nx, int ny, int nz,
             const int64_t ti = t % ntx, tj = (t / ntx) % nty, tk = t / (ntx * nty);
             for (int64_t k = tk * tz; k < (tk + 1) * tz && k < nz; ++k)
                 for (int64_t j = tj * ty; j < (tj + 1) * ty && j < ny; ++j)
-                    for (int64_t i = ti * tx; i < (ti + 1) * tx && i < nx; ++i)
-                        nxt[(k * ny + j) * nx + i] = upwind_point(phi, F, nx, ny, nz, i, j, k, dx, dt);
+                    for (int64_t i = ti * tx; i < (ti + 1) * tx && i < nx; ++i) {
+                        const int64_t idx = (k * ny + j) * nx + i;
+                        double v = upwind_point(phi, F, nx, ny, nz, i, j, k, dx, dt);
+                        if (store_scale > 0.0 && F[idx] != 0.0)
+                            v = store_f16s(v, store_scale);
+                        nxt[idx] = v;
+                    }
         }
         /* Commit them: step n+1 becomes the current step. */
 #pragma omp parallel for schedule(dynamic, 16)
@@ -230,4 +278,13 @@ int lso_upwind_steps(double *phi, const double *F, int nx, int ny, int nz,
     }
     free(nxt);
     return LSO_OK;
+}
+
+/* lso_upwind_steps_stored with the state kept in FP64 (no storage rounding). */
+int lso_upwind_steps(double *phi, const double *F, int nx, int ny, int nz,
+                     double dx, double dt, int tx, int ty, int tz,
+                     const int32_t *tiles, int64_t ntiles, int nsteps)
+{
+    return lso_upwind_steps_stored(phi, F, nx, ny, nz, dx, dt, tx, ty, tz, tiles, ntiles, nsteps,
+                                   0.0);
 }

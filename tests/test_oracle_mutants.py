@@ -2,7 +2,9 @@
 
 Each case compiles a copy of the oracle's C source with one planted mistake
 (a dropped term, a wrong sign, a wrong or transposed index, the wrong upwind
-branch, a non-strict band test, a short dilation, a lost F = 0 guard) into a
+branch, a non-strict band test, a short dilation, a lost F = 0 guard, a binary16
+rounding with ties away from zero, an extra fraction bit or no subnormal
+floor, a stored point of zero speed rounded again) into a
 temporary library, swaps it in, and requires at least one pin to fail.
 Everything runs on the CPU.
 """
@@ -14,6 +16,7 @@ import oracle
 from oracle import build as obuild
 
 import test_oracle_band as band_pins
+import test_oracle_f16s as f16_pins
 import test_oracle_pins as pins
 
 SRC = os.path.join(os.path.dirname(obuild.__file__), "ls_oracle.c")
@@ -29,7 +32,11 @@ MUTANTS = {
     "lost_zero_speed_guard": ("if (f == 0.0)\n        return c;", "if (0)\n        return c;"),
     "band_not_strict": ("if (fabs(v) < gamma)", "if (fabs(v) <= gamma)"),
     "dilation_one_sided": ("for (int64_t dk = -1; dk <= 1; ++dk)", "for (int64_t dk = 0; dk <= 1; ++dk)"),
-    "gauss_seidel": ("nxt[(k * ny + j) * nx + i] = upwind_point(phi", "phi[(k * ny + j) * nx + i] = upwind_point(phi"),
+    "gauss_seidel": ("nxt[idx] = v;", "nxt[idx] = v;\n                        phi[idx] = v;"),
+    "binary16_ties_away": ("nearbyint(ldexp(a, -q))", "round(ldexp(a, -q))"),
+    "binary16_extra_bit": ("int q = e - 11;", "int q = e - 12;"),
+    "binary16_no_subnormal_floor": ("if (q < -24)", "if (q < -34)"),
+    "stored_zero_speed_rounded": ("if (store_scale > 0.0 && F[idx] != 0.0)", "if (store_scale > 0.0)"),
 }
 
 
@@ -51,6 +58,8 @@ def _pins():
         out.append((f"band_brute_a{tile}", lambda t=tile: band_pins.test_band_bruteforce((13, 9, 7), t, False)))
     out.append(("band_plane", lambda: band_pins.test_plane_band_closed_form(0.4, (8, 8, 8))))
     out.append(("band_f32", band_pins.test_band_f32_decision_matches_f32_compare))
+    out.append(("binary16", f16_pins.test_round_binary16_equals_numpy_conversion))
+    out.append(("stored_steps", f16_pins.test_stored_steps_compose_and_round_each_step))
     return out
 
 
