@@ -306,6 +306,20 @@ int ls_band_gather_f16s(const uint16_t *phi_h, const ls_grid *g, const int32_t *
                         const int32_t *ntiles_dev, uint16_t *out, int32_t *ids_out,
                         int64_t capacity, void *stream);
 
+/* Counted copy (support of the snapshot's device-to-host transfer): copies
+ * n = min(max(*count_dev, 0), max_units) units of unit_bytes bytes from src to
+ * dst, the count read on the device when the kernel runs, so that a copy of
+ * exactly the tiles a gather produced is enqueued without the host waiting
+ * for the gather.  dst and src are device-accessible (device memory, or host
+ * memory allocated pinned, e.g. hipHostMalloc / torch's pin_memory: the
+ * kernel then writes host memory directly) and must not overlap; with
+ * count_out non-NULL (device-accessible) the copy also stores n there.  blocks
+ * is the number of workgroups (0: a quarter of the compute units), kept small
+ * so that the copy shares the GPU with the compute stream.  Errors: NULL
+ * pointers, unit_bytes <= 0, max_units outside [0, 2^31), blocks < 0. */
+int ls_copy_counted(void *dst, const void *src, const int32_t *count_dev, int64_t unit_bytes,
+                    int64_t max_units, int32_t *count_out, int blocks, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Batches: many grids of uneven size, advanced in lockstep by the same
  * launches (the narrow-band driver above, applied to every grid at once).

@@ -349,3 +349,13 @@ def test_closure_run_errors():
     assert call(window=0) == ls.LS_ERR_ARG
     assert call(capacity=cap - 1) == ls.LS_ERR_CAPACITY
     assert call(g=ls.grid((36, 32, 32))) == ls.LS_ERR_UNSUPPORTED  # dims must be multiples of 8
+
+
+def test_copy_counted_errors():
+    ok = dict(dst=FAKE, src=FAKE, count_dev=FAKE, unit_bytes=16, max_units=4, count_out=None,
+              blocks=1, stream=0)
+    for over in (dict(dst=None), dict(src=None), dict(count_dev=None), dict(unit_bytes=0),
+                 dict(unit_bytes=-4), dict(max_units=-1), dict(max_units=1 << 31),
+                 dict(blocks=-1), dict(unit_bytes=1 << 40, max_units=1 << 30)):
+        a = dict(ok, **over)
+        assert _status(ls.ls_copy_counted, *a.values()) == ls.LS_ERR_ARG, over

@@ -9,6 +9,7 @@ import oracle
 from gpu_util import dev, host, random_tiles, to_dev
 from paper_1612_04040_amd import workloads as W
 from paper_1612_04040_amd.band import BandGrid
+from paper_1612_04040_amd import ls
 from paper_1612_04040_amd.snapshot import Snapshots
 
 pytestmark = pytest.mark.gpu
@@ -85,6 +86,34 @@ def test_async_snapshots_equal_synchronous_ones():
     for k, ((ids, vals), (band, want)) in enumerate(zip(got, ref)):
         assert ids.tolist() == band.tolist(), k
         assert vals.tobytes() == want.tobytes(), k
+    snaps.close()
+    with pytest.raises(RuntimeError):
+        snaps.take(p)
+    snaps.close()  # a second close does nothing
+
+
+@pytest.mark.parametrize("unit_bytes", [80, 12, 6, 3])
+def test_counted_copy_moves_exactly_the_counted_units(unit_bytes):
+    """ls_copy_counted: min(max(count, 0), max_units) units, the count read on
+    the device, into pinned host memory and into device memory, with the count
+    stored; nothing beyond is written (16-, 4-, 2- and 1-byte forms)."""
+    nbytes = 4000
+    src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device=dev())
+    maxu = nbytes // unit_bytes
+    for count, want in ((7, 7), (maxu + 30, maxu), (-3, 0), (0, 0)):
+        cnt = torch.tensor([count], dtype=torch.int32, device=dev())
+        for pinned in (True, False):
+            dst = torch.full((nbytes,), 0xA5, dtype=torch.uint8)
+            dst = dst.pin_memory() if pinned else dst.to(dev())
+            out = torch.full((1,), -9, dtype=torch.int32)
+            out = out.pin_memory() if pinned else out.to(dev())
+            ls.ls_copy_counted(dst, src, cnt, unit_bytes, maxu, count_out=out, blocks=3)
+            torch.cuda.synchronize()
+            d, s_ = dst.cpu().numpy(), src.cpu().numpy()
+            m = want * unit_bytes
+            assert np.array_equal(d[:m], s_[:m]), (unit_bytes, count, pinned)
+            assert np.all(d[m:] == 0xA5), (unit_bytes, count, pinned)
+            assert int(out.cpu()[0]) == want
 
 
 def test_snapshot_buffers_full_is_an_error():
