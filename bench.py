@@ -105,13 +105,23 @@ def measured_traffic(kernel, workload, digest):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, budget_s, beta=None):
-    """The oracle (FP64, OpenMP) on whole windows of the same workload (with
-    the cut-off steps when beta is given)."""
+def cpu_model():
+    """The host CPU's model name (as lscpu reports it), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_windows(wl, budget_s, beta, max_windows):
+    """Whole windows of the oracle (band rebuild + steps) until the budget is
+    spent: (band point-updates, windows, seconds)."""
     import oracle
 
-    if budget_s <= 0:
-        return None
     phi = wl.phi.astype(np.float64)
     g32 = np.float32(wl.gamma)
     updates, windows = 0, 0
@@ -125,17 +135,39 @@ def cpu_baseline(wl, budget_s, beta=None):
                                       float(g32), wl.tile)
         updates += int(tiles.size) * int(np.prod(wl.tile)) * wl.window
         windows += 1
-        if time.perf_counter() - t0 >= budget_s or windows * wl.window >= wl.nsteps:
+        if (time.perf_counter() - t0 >= budget_s or windows * wl.window >= wl.nsteps
+                or windows >= max_windows):
             break
-    elapsed = time.perf_counter() - t0
+    return updates, windows, time.perf_counter() - t0
+
+
+def cpu_baseline(wl, budget_s, beta=None):
+    """The oracle (FP64, OpenMP) on whole windows of the same workload (with
+    the cut-off steps when beta is given), on every host thread, then on one
+    thread over its first window."""
+    import oracle
+
+    if budget_s <= 0:
+        return None
+    threads = oracle.max_threads()
+    updates, windows, elapsed = _oracle_windows(wl, budget_s, beta, 1 << 30)
+    oracle.set_threads(1)
+    try:
+        u1, w1, e1 = _oracle_windows(wl, budget_s, beta, 1)
+    finally:
+        oracle.set_threads(threads)
+    what = (f"band rebuild + FP64 {'cut-off ' if beta is not None else ''}upwind steps) of the "
+            f"{wl.name}{_suffix(beta, None)} workload")
     return {
         "value": updates / elapsed / 1e9,
         "unit": "GLUPS",
-        "cores": oracle.max_threads(),
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"first {windows} window(s) x {wl.window} steps (band rebuild + FP64 "
-                  f"{'cut-off ' if beta is not None else ''}upwind steps) of the "
-                  f"{wl.name}{_suffix(beta, None)} workload, {elapsed:.1f} s",
+        "sample": f"first {windows} window(s) x {wl.window} steps ({what}, {elapsed:.1f} s",
+        "cpu_model": cpu_model(),
+        "single_thread": {"value": u1 / e1 / 1e9, "unit": "GLUPS", "cores": 1,
+                          "sample": f"first {w1} window(s) x {wl.window} steps ({what}, "
+                                    f"{e1:.1f} s"},
     }
 
 
@@ -385,6 +417,7 @@ def _snapshot_run(args, torch, ls, W, BandGrid, dev):
         if i == 1:
             ls.ls_stats_enable(False)
     g_launches, g_timed, g_ms = ls.ls_stats_read(ls.LS_KERNEL_GATHER)
+    snaps.close()  # copies done, pinned buffers and the copy stream released before exit
     t_plain, _, ts = times[False]
     t_snap, taken, _ = times[True]
     updates = ts * int(np.prod(wl.tile))
