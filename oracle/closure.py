@@ -207,18 +207,34 @@ def crossing_tiles(phi, tile=(8, 8, 8)):
     return out
 
 
-def judge(phi, shadow, tile=(8, 8, 8)):
+def judge(phi, shadow, tile=(8, 8, 8), dx=None, tau=0.0):
     """The judge after a window: (phi with every tile whose crossing state
     differs from the shadow's replaced by the shadow's values, the number of
-    such tiles)."""
+    such tiles).  With tau > 0 (and the spacing dx) a tile is replaced as
+    well when the two fronts lie apart by more than tau dx there: some point
+    next to either front (|phi| < dx or |shadow| < dx) has
+    |phi - shadow| > tau dx (both fields are distance-like near the front, so
+    the difference of the values there is the distance between the fronts)."""
     out = np.array(phi, copy=True)
-    bad = np.flatnonzero(crossing_tiles(phi, tile) != crossing_tiles(shadow, tile))
+    bad = crossing_tiles(phi, tile) != crossing_tiles(shadow, tile)
     nz, ny, nx = phi.shape
     tx, ty, tz = tile
     ntx, nty = -(-nx // tx), -(-ny // ty)
-    for t in bad:
+
+    def block(t):
         ti, tj, tk = t % ntx, (t // ntx) % nty, t // (ntx * nty)
-        sl = (slice(tk * tz, (tk + 1) * tz), slice(tj * ty, (tj + 1) * ty),
-              slice(ti * tx, (ti + 1) * tx))
+        return (slice(tk * tz, (tk + 1) * tz), slice(tj * ty, (tj + 1) * ty),
+                slice(ti * tx, (ti + 1) * tx))
+
+    if tau > 0:
+        for t in range(bad.size):
+            sl = block(t)
+            a, b = phi[sl], shadow[sl]
+            near = (np.abs(a) < dx) | (np.abs(b) < dx)
+            if np.any(near & (np.abs(a - b) > tau * dx)):
+                bad[t] = True
+    idx = np.flatnonzero(bad)
+    for t in idx:
+        sl = block(t)
         out[sl] = shadow[sl]
-    return out, int(bad.size)
+    return out, int(idx.size)

@@ -180,6 +180,42 @@ def test_judge_resets_tiles_whose_crossing_state_differs():
     assert CL.judge(shadow, shadow)[1] == 0
 
 
+def test_judge_front_position_bound():
+    """The judge with a front-position bound tau (in dx): on 16^3 fields of
+    plane fronts phi = x - c (distance-like, dx = 1/16), by hand per tile
+    (id = (tk*2 + tj)*2 + ti): tile 0 front moved by 1.5 dx (reset at
+    tau = 1), tile 4 by 0.5 dx (kept), tile 6 differing by 1.5 dx only on
+    points away from both fronts (kept: no point next to a front differs),
+    tile 3 front moved by exactly tau dx (kept: strictly more than tau is
+    needed); tau = 0 is the topology judge alone (no reset: every tile has
+    the same crossing state in both fields)."""
+    n, dx = 16, 1.0 / 16
+    x = (np.arange(n) + 0.5) * dx
+    shadow = np.broadcast_to(x - 4.5 * dx, (n, n, n)).copy()  # front at x = 4.5 dx ... tile ti=0
+    shadow[:, 8:, :] = np.broadcast_to(x - 12.5 * dx, (n, 8, n))  # rows y >= 8: front in ti = 1
+    phi = shadow.copy()
+    # tile 0 (z < 8, y < 8, x < 8): front moved by 1.5 dx
+    phi[:8, :8, :8] = shadow[:8, :8, :8] - 1.5 * dx
+    # tile 1 (x >= 8, y < 8, z < 8): no front in either; tile 3 (x >= 8, y >= 8,
+    # z < 8): front moved by exactly 1 dx (0.0625 is exact in binary)
+    phi[:8, 8:, 8:] = shadow[:8, 8:, 8:] - 1.0 * dx
+    # tile 4 (z >= 8, y < 8, x < 8): front moved by 0.5 dx
+    phi[8:, :8, :8] = shadow[8:, :8, :8] - 0.5 * dx
+    # tile 6 (z >= 8, y >= 8, x < 8): values 4 dx and more from both fronts moved by 1.5 dx
+    blk = shadow[8:, 8:, :8]
+    phi[8:, 8:, :8] = np.where(np.abs(blk) > 3 * dx, blk + 1.5 * np.sign(blk) * dx, blk)
+    topo = CL.judge(phi, shadow, dx=dx, tau=0.0)
+    assert topo[1] == 0
+    out, k = CL.judge(phi, shadow, dx=dx, tau=1.0)
+    assert k == 1
+    assert np.array_equal(out[:8, :8, :8], shadow[:8, :8, :8])
+    keep = np.ones(phi.shape, bool)
+    keep[:8, :8, :8] = False
+    assert np.array_equal(out[keep], phi[keep])
+    # a bound below the 0.5 dx move resets tile 4 as well, and below 1 dx tile 3
+    assert CL.judge(phi, shadow, dx=dx, tau=0.4)[1] == 3
+
+
 def features_plane_case():
     """A coarse plane front phi = x - x0 (unit normal along x), a constant
     speed F = 0.6 with the bound Fmax = 0.8 passed in, dt = dx / (2 Fmax): one

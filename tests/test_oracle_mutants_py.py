@@ -6,7 +6,8 @@ Each case swaps one function for a copy with a planted mistake (the cubic's
 constants exchanged, c taken from the new value, one-sided instead of
 central differences, the -1 term with the wrong sign, S frozen at the start,
 the clamp left out, a transposed tile block, the increment over the fine
-spacing, a clip at +-1, F over its sample maximum, crossings without the
+spacing, a clip at +-1, F over its sample maximum, a judge that resets a
+front moved by exactly its bound, crossings without the
 half-cell offset or with the interpolation weight reversed, a one-sided
 Hausdorff distance, upsampling without the centre shift) and requires at
 least one of the pins of that function to fail.  Everything runs on the CPU.
@@ -169,6 +170,14 @@ def upsample_no_shift(phi_c, factor):
 
 _crossings = metrics.zero_crossings
 
+_judge = oracle.closure.judge
+
+
+def judge_non_strict(phi, shadow, tile=(8, 8, 8), dx=None, tau=0.0):
+    """A move of exactly tau dx already resets."""
+    return _judge(phi, shadow, tile, dx, tau * (1 - 1e-12) if tau > 0 else tau)
+
+
 CASES = [
     ("cutoff", cutoff_swapped, [cut_pins.test_cutoff_hand_values]),
     ("cutoff", cutoff_linear, [cut_pins.test_cutoff_hand_values]),
@@ -188,6 +197,8 @@ CASES = [
      [closure_pins.test_features_hand_values_on_a_plane]),
     ((oracle.closure, "features"), features_sample_max,
      [closure_pins.test_features_hand_values_on_a_plane]),
+    ((oracle.closure, "judge"), judge_non_strict,
+     [closure_pins.test_judge_front_position_bound]),
     ((metrics, "zero_crossings"), crossings_no_offset,
      [metric_pins.test_plane_crossings_at_known_positions,
       metric_pins.test_oblique_plane_crossings_lie_on_the_plane]),
