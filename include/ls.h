@@ -178,6 +178,62 @@ int ls_band_run_f16s(uint16_t *phi_h, float scale, const float *F, const ls_grid
                      uint16_t *scratch, void *workspace, int64_t workspace_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Tile-major ("brick") layout.  The grid's tiles one after another in tile-id
+ * order, each tile's points contiguous with x fastest inside the tile: point
+ * (i, j, k) of tile t = (tk*nty + tj)*ntx + ti at element
+ * t*512 + (k%8)*64 + (j%8)*8 + (i%8).  A run of band tiles along x is then
+ * one contiguous stretch of memory, which the band kernels stream where the
+ * x-fastest layout scatters it over 64 grid rows.  Requires 8x8x8 tiles,
+ * whole tiles on every axis (nx, ny, nz multiples of 8; LS_ERR_UNSUPPORTED
+ * otherwise) and 16-byte aligned buffers (LS_ERR_ARG); a brick field has as
+ * many elements as the grid.
+ *
+ * ls_bricks_from_dense_* / ls_bricks_to_dense_*: the permutation between the
+ * layouts (FP32 values, or scaled-FP16 codes moved as they are); src and dst
+ * must not overlap.
+ *
+ * ls_band_build_bricks_*: ls_band_build_* on a brick field (same list, same
+ * plan in the workspace).
+ *
+ * ls_band_run_bricks_*: the windowed driver of Sec. 1.1 on brick fields phi_b
+ * and F_b (F_b = the speed converted with ls_bricks_from_dense_f32; FP32 for
+ * both storages), with scratch_b the ping-pong partner (a brick field of
+ * phi's type).  Per window of `window` steps: the band build (a full scan of
+ * phi_b for the first window, the exact incremental rescan of the previous
+ * band after), `window` steps of Eq. 3-5 on it (with beta > 0: the cut-off
+ * steps of Eq. 8 with c(phi) of beta and the band's gamma; beta = 0: plain
+ * steps), then reinit_iters reinitialisation steps of Eq. 12-13 (pseudo time
+ * step dtau) on the same band, the last followed by the clamp of Eq. 10 to
+ * [-gamma, gamma] (reinit_iters = 0: no Step 3).  Every value equals, bit for
+ * bit, what the x-fastest calls compute (ls_band_run_*, ls_band_run_cutoff_*,
+ * ls_band_run_reinit_*) on the same fields converted, since the kernels
+ * evaluate the same arithmetic on the same neighbours.  tiles / ntiles_dev /
+ * tile_steps_dev and the errors as for ls_band_run_*; 0 < beta < gamma < inf
+ * when beta != 0, gamma positive and finite when reinit_iters > 0.
+ * ------------------------------------------------------------------------- */
+int ls_bricks_from_dense_f32(const float *src, const ls_grid *g, float *dst, void *stream);
+int ls_bricks_to_dense_f32(const float *src, const ls_grid *g, float *dst, void *stream);
+int ls_bricks_from_dense_f16s(const uint16_t *src, const ls_grid *g, uint16_t *dst,
+                              void *stream);
+int ls_bricks_to_dense_f16s(const uint16_t *src, const ls_grid *g, uint16_t *dst, void *stream);
+int ls_band_build_bricks_f32(const float *phi_b, const ls_grid *g, float gamma, int dilate,
+                             int32_t *tiles, int64_t capacity, int32_t *ntiles_dev,
+                             void *workspace, int64_t workspace_bytes, void *stream);
+int ls_band_build_bricks_f16s(const uint16_t *phi_b, float scale, const ls_grid *g, float gamma,
+                              int dilate, int32_t *tiles, int64_t capacity, int32_t *ntiles_dev,
+                              void *workspace, int64_t workspace_bytes, void *stream);
+int ls_band_run_bricks_f32(float *phi_b, const float *F_b, const ls_grid *g, float dx, float dt,
+                           float gamma, int nsteps, int window, float beta, int reinit_iters,
+                           float dtau, int32_t *tiles, int64_t capacity, int32_t *ntiles_dev,
+                           int64_t *tile_steps_dev, float *scratch_b, void *workspace,
+                           int64_t workspace_bytes, void *stream);
+int ls_band_run_bricks_f16s(uint16_t *phi_b, float scale, const float *F_b, const ls_grid *g,
+                            float dx, float dt, float gamma, int nsteps, int window, float beta,
+                            int reinit_iters, float dtau, int32_t *tiles, int64_t capacity,
+                            int32_t *ntiles_dev, int64_t *tile_steps_dev, uint16_t *scratch_b,
+                            void *workspace, int64_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Cut-off step and driver (Sec. 1.1, Eq. 7-8): the same calls as
  * ls_upwind_step_* and ls_band_run_* for the cut-off equation
  * phi_t + c(phi) F |grad phi| = 0, with
@@ -407,9 +463,12 @@ typedef struct ls_tuning {
                          1 off, 2 on */
     int32_t vector;   /* 0 auto (FP32 and FP16s, 8x8x8 tiles, nx a multiple of
                          4, aligned buffers: the vectorised kernel), 1 off */
-    int32_t temporal; /* 0 off (default), 1 on: two steps per launch where the
-                         vectorised kernel runs on grids of whole tiles in y
-                         and z (bit-identical; measured slower) */
+    int32_t temporal; /* steps per launch (bit-identical either way).  0 auto:
+                         one on the x-fastest layout; on the brick layout two
+                         for FP32, one for FP16s;
+                         1 two (x-fastest: where the vectorised kernel runs on
+                         grids of whole tiles in y and z, measured slower);
+                         2 one */
 } ls_tuning;
 int ls_set_tuning(const ls_tuning *t);
 int ls_get_tuning(ls_tuning *t);
@@ -443,7 +502,8 @@ int ls_upwind_launch_info(const ls_grid *g, int precision, int32_t *blocks, int3
  * While enabled, the launches of the kernel `which` (LS_KERNEL_UPWIND: the
  * band step kernel, LS_KERNEL_BAND_FLAG: the band build's scan of phi,
  * LS_KERNEL_REINIT: the reinitialisation steps, LS_KERNEL_GATHER: the band
- * snapshot's gather) are
+ * snapshot's gather, LS_KERNEL_CLOSURE: the closure's fused network kernel)
+ * are
  * bracketed by pairs of HIP events recorded on the launch stream: one pair
  * around each scan, and one pair around the back-to-back step launches of a
  * call (a window's launches), so the time per launch includes the short gaps
@@ -454,7 +514,13 @@ int ls_upwind_launch_info(const ls_grid *g, int precision, int32_t *blocks, int3
  * per kernel are recorded.  Do not enable it while a stream is being captured
  * into a HIP graph.
  * ------------------------------------------------------------------------- */
-enum { LS_KERNEL_UPWIND = 0, LS_KERNEL_BAND_FLAG = 1, LS_KERNEL_REINIT = 2, LS_KERNEL_GATHER = 3 };
+enum {
+    LS_KERNEL_UPWIND = 0,
+    LS_KERNEL_BAND_FLAG = 1,
+    LS_KERNEL_REINIT = 2,
+    LS_KERNEL_GATHER = 3,
+    LS_KERNEL_CLOSURE = 4
+};
 int ls_stats_enable(int on);
 int ls_stats_read(int which, int64_t *launches, int64_t *timed, double *total_ms);
 
@@ -550,8 +616,13 @@ int ls_adam_step(float *params, const float *grad, float *m, float *v, int64_t n
  * phi >= 0) differs between the corrected field and the shadow takes the
  * shadow's values.  A correction may so move the interface but not create,
  * remove, split or merge a piece of it inside a tile against the plain run.
+ * judge == 2 bounds the interface's position as well: a tile also takes the
+ * shadow's values when the two fronts lie more than one grid spacing apart
+ * there (a point next to either front, |phi| < dx or |shadow| < dx, where
+ * |phi - shadow| > dx); judge == 1 is the topology judge alone.
  * *resets_dev (int32, caller-zeroed; required when judging) accumulates the
- * number of tiles reset.  judge == 0: no shadow run (resets_dev may be NULL).
+ * number of tiles reset.  judge == 0: no shadow run (resets_dev may be NULL);
+ * other values of judge: LS_ERR_ARG.
  *
  * On return phi holds the result; the band list of the corrected run's last
  * window is in tiles / ntiles_dev. */

@@ -169,3 +169,49 @@ class BandGrid:
             ls.ls_band_run_f16s(phi, scale, F, self.g, dx, dt, gamma, nsteps, window, self.tiles,
                                 self.capacity, self.ntiles, tile_steps, self.scratch, self.ws,
                                 self.ws_bytes, stream)
+
+    # -- tile-major ("brick") layout -------------------------------------------
+    def to_bricks(self, src, dst, stream=None):
+        """src (x-fastest) -> dst (tile-major); FP32 values or scaled-FP16 codes."""
+        if self.precision == "f32" or src.dtype == torch.float32:
+            ls.ls_bricks_from_dense_f32(src, self.g, dst, stream)
+        else:
+            ls.ls_bricks_from_dense_f16s(src, self.g, dst, stream)
+
+    def from_bricks(self, src, dst, stream=None):
+        """src (tile-major) -> dst (x-fastest)."""
+        if self.precision == "f32" or src.dtype == torch.float32:
+            ls.ls_bricks_to_dense_f32(src, self.g, dst, stream)
+        else:
+            ls.ls_bricks_to_dense_f16s(src, self.g, dst, stream)
+
+    def build_bricks(self, phi_b, gamma, dilate=True, scale=None, stream=None):
+        d = 1 if dilate else 0
+        if self.precision == "f32":
+            ls.ls_band_build_bricks_f32(phi_b, self.g, gamma, d, self.tiles, self.capacity,
+                                        self.ntiles, self.ws, self.ws_bytes, stream)
+        elif self.precision == "f16s":
+            ls.ls_band_build_bricks_f16s(phi_b, scale, self.g, gamma, d, self.tiles,
+                                         self.capacity, self.ntiles, self.ws, self.ws_bytes,
+                                         stream)
+        else:
+            raise ValueError("the brick layout takes f32 or f16s storage")
+
+    def run_bricks(self, phi_b, F_b, dx, dt, gamma, nsteps, window=10, scale=None,
+                   tile_steps=None, stream=None, beta=None, reinit=None):
+        """The windowed driver on tile-major fields (phi_b in this grid's storage, F_b FP32,
+        both converted with to_bricks); the scratch buffer serves as the brick ping-pong
+        partner.  ``beta``: the cut-off steps of Eq. 8; ``reinit = (dtau, iters)``: Step 3
+        ends each window."""
+        b = 0.0 if beta is None else float(beta)
+        dtau, iters = (0.0, 0) if reinit is None else (float(reinit[0]), int(reinit[1]))
+        if self.precision == "f32":
+            ls.ls_band_run_bricks_f32(phi_b, F_b, self.g, dx, dt, gamma, nsteps, window, b, iters,
+                                      dtau, self.tiles, self.capacity, self.ntiles, tile_steps,
+                                      self.scratch, self.ws, self.ws_bytes, stream)
+        elif self.precision == "f16s":
+            ls.ls_band_run_bricks_f16s(phi_b, scale, F_b, self.g, dx, dt, gamma, nsteps, window,
+                                       b, iters, dtau, self.tiles, self.capacity, self.ntiles,
+                                       tile_steps, self.scratch, self.ws, self.ws_bytes, stream)
+        else:
+            raise ValueError("the brick layout takes f32 or f16s storage")

@@ -87,10 +87,11 @@ class ClosureGrid:
     def run(self, phi, F, dx, dt, gamma, fmax, params, nsteps, window=10, judge=True,
             stream=None):
         """Corrected narrow-band run, judged by a plain shadow run unless
-        judge=False; self.fallbacks and self.resets accumulate (zero them
-        first)."""
+        judge=False (0): True (1) judges the interface's topology per tile, 2
+        its position as well (the fronts within one grid spacing);
+        self.fallbacks and self.resets accumulate (zero them first)."""
         t, cap, n, ws, wsb = self._band()
-        ls.ls_closure_run_f32(phi, F, self.g, dx, dt, gamma, fmax, params, nsteps, window, judge,
+        ls.ls_closure_run_f32(phi, F, self.g, dx, dt, gamma, fmax, params, nsteps, window, int(judge),
                               t, cap, n, self.fallbacks, self.resets, ws, wsb, self.cws,
                               self.cws_bytes, stream)
 

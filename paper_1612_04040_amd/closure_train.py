@@ -208,7 +208,10 @@ def evaluate(seed, n_fine, nsteps, params, device, reps=3):
     phi_l = torch.empty_like(phi_c0)
     zero_i = torch.zeros(1, dtype=torch.int32, device=device)
     fields = {}
-    for name, judge in (("learned", False), ("judged", True)):
+    # the product run is "judged" (the plain shadow judges the topology and the
+    # position of the front per tile, judge mode 2); the topology judge alone
+    # (mode 1) and no judge are reported beside it
+    for name, judge in (("learned", 0), ("judged_topology", 1), ("judged", 2)):
         def learned_run(s):
             ls.ls_copy_f32(phi_l, phi_c0, phi_l.numel(), s)
             ls.ls_copy_f32(cg.fallbacks, zero_i, 1, s)  # int32 zeros, same width
@@ -220,13 +223,14 @@ def evaluate(seed, n_fine, nsteps, params, device, reps=3):
             learned_run, stream, reps)
         out[f"{name}_fallbacks"] = int(cg.fallbacks.item())
         if judge:
-            out["judge_resets"] = int(cg.resets.item())
+            out[f"{name}_resets"] = int(cg.resets.item())
         fields[name] = phi_l.cpu().numpy()
 
     dxf = case.dx_fine
     pf = metrics.zero_crossings(fine, dxf)
     for name, field in (("restricted_fine", best), ("plain_coarse", plain),
                         ("learned_coarse", fields["learned"]),
+                        ("judged_topology_coarse", fields["judged_topology"]),
                         ("judged_coarse", fields["judged"])):
         up = metrics.upsample_trilinear(field, ratio)
         pc = metrics.zero_crossings(up, dxf)
@@ -236,6 +240,7 @@ def evaluate(seed, n_fine, nsteps, params, device, reps=3):
     # coarse lattice (in fine dx)
     pb = metrics.zero_crossings(best, case.dx_coarse)
     for name, field in (("plain_coarse", plain), ("learned_coarse", fields["learned"]),
+                        ("judged_topology_coarse", fields["judged_topology"]),
                         ("judged_coarse", fields["judged"])):
         pc = metrics.zero_crossings(field, case.dx_coarse)
         out[f"hausdorff_{name}_to_restricted_dx_fine"] = metrics.hausdorff(pc, pb) / dxf

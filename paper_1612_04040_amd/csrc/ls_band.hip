@@ -33,7 +33,8 @@ struct EmitHeadTile {
 // Record of item pos (word 7 holds its first tile): [0] first tile, [1] run
 // length, [2..5] bit l = "tile l of the run has its y-, y+, z-, z+ face
 // neighbour in the band (or outside the grid)", [6] bits 0 / 1 = same for the
-// x- / x+ neighbour of the run.
+// x- / x+ neighbour of the run, [7] the same for the diagonal neighbours of
+// runs of at most 4 tiles (below).
 struct ItemRecordFn {
     int32_t *rec;
     const uint8_t *umap;
@@ -56,6 +57,29 @@ struct ItemRecordFn {
         }
         const uint32_t xb = uint32_t(ti0 == 0 || umap[t0 - 1]) |
                             (uint32_t(ti0 + len == ntx || umap[t0 + len]) << 1);
+        // word 7 (runs of at most 4 tiles): the diagonal neighbours the
+        // two-step kernel reads, 1 = in the band (or outside the grid): bits
+        // 4l..4l+3 the (y-,z-), (y-,z+), (y+,z-), (y+,z+) neighbours of tile l;
+        // bits 16..19 / 20..23 the y-, y+, z-, z+ neighbours of the tile
+        // before / after the run
+        uint32_t diag = 0;
+        if (R <= 4) {
+            const int64_t sy = ntx, sz = static_cast<int64_t>(ntx) * nty;
+            auto in = [&](int64_t t, int dj, int dk) {
+                if (tj + dj < 0 || tj + dj >= nty || tk + dk < 0 || tk + dk >= ntz) return 1u;
+                return umap[t + dj * sy + dk * sz] ? 1u : 0u;
+            };
+            for (int l = 0; l < len; ++l) {
+                const int64_t t = t0 + l;
+                diag |= (in(t, -1, -1) | in(t, -1, 1) << 1 | in(t, 1, -1) << 2 | in(t, 1, 1) << 3)
+                        << (4 * l);
+            }
+            auto ends = [&](int64_t t) {
+                return in(t, -1, 0) | in(t, 1, 0) << 1 | in(t, 0, -1) << 2 | in(t, 0, 1) << 3;
+            };
+            diag |= (ti0 > 0 ? ends(t0 - 1) : 15u) << 16;
+            diag |= (ti0 + len < ntx ? ends(t0 + len) : 15u) << 20;
+        }
         o[0] = t0;
         o[1] = len;
         o[2] = static_cast<int32_t>(m0);
@@ -63,6 +87,7 @@ struct ItemRecordFn {
         o[4] = static_cast<int32_t>(m2);
         o[5] = static_cast<int32_t>(m3);
         o[6] = static_cast<int32_t>(xb);
+        o[7] = static_cast<int32_t>(diag);
     }
 };
 
@@ -298,7 +323,7 @@ static int band_args(const S *phi, const ls_grid *grid, typename Codec<S>::C gam
 
 // Dilation (or copy) of the flags into the update map, then the ordered band
 // list and the step plan of that list.
-static int band_finish(const Geom &g, uint8_t *ws, int dilate, int32_t *tiles,
+int band_finish(const Geom &g, uint8_t *ws, int dilate, int32_t *tiles,
                        int32_t *ntiles_dev, hipStream_t stream, TileAccum accum) {
     const Workspace w = workspace_layout(g);
     const dim3 dgrid(static_cast<unsigned>(cdiv64(g.ntx, 64)), static_cast<unsigned>(cdiv64(g.nty, 4)),

@@ -15,6 +15,7 @@
 #include <cmath>
 
 #include "ls_compact.h"
+#include "ls_stats.h"
 #include "ls_stencil.h"
 
 namespace ls {
@@ -743,11 +744,15 @@ __global__ void adam_kernel(float *__restrict__ w, const float *__restrict__ gra
 // The plain scheme as judge of the corrected run's interface: every 8^3 tile
 // whose zero-crossing state (holding points of both signs, phi < 0 and
 // phi >= 0, or not) differs between the corrected field x and the plain
-// shadow field p takes p's values; *resets counts those tiles.  One block of
-// 512 threads per tile (a point per thread), grid-stride over the tiles.
+// shadow field p takes p's values; with tau > 0 so does every tile where the
+// two fronts lie more than tau dx apart (a point next to either front,
+// |x| < dx or |p| < dx, with |x - p| > tau dx; both fields are distance-like
+// there); *resets counts those tiles.  One block of 512 threads per tile (a
+// point per thread), grid-stride over the tiles.
 __global__ __launch_bounds__(512) void closure_judge_kernel(float *__restrict__ x,
                                                             const float *__restrict__ p, int nx,
                                                             int ny, int ntx, int nty, int ntiles,
+                                                            float dx, float tau,
                                                             int32_t *resets) {
     const int lx = threadIdx.x & 7, ly = (threadIdx.x >> 3) & 7, lz = threadIdx.x >> 6;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -758,7 +763,10 @@ __global__ __launch_bounds__(512) void closure_judge_kernel(float *__restrict__ 
         const float xv = x[i], pv = p[i];
         const int xneg = __syncthreads_or(xv < 0.f), xpos = __syncthreads_or(!(xv < 0.f));
         const int pneg = __syncthreads_or(pv < 0.f), ppos = __syncthreads_or(!(pv < 0.f));
-        if ((xneg && xpos) != (pneg && ppos)) {  // uniform over the block
+        const bool near = fabsf(xv) < dx || fabsf(pv) < dx;
+        const int apart =
+            __syncthreads_or(tau > 0.f && near && fabsf(xv - pv) > tau * dx);
+        if ((xneg && xpos) != (pneg && ppos) || apart) {  // uniform over the block
             x[i] = pv;
             if (threadIdx.x == 0) atomicAdd(resets, 1);
         }
@@ -992,12 +1000,15 @@ static int closure_fused(const ClosureCall &c, const float *phi, const float *F,
     In4 feat{phi, F, plain, nullptr, 1.0f / gamma, 1.0f / fmax, 1.0f / dx};
     // with `apply` the corrections go to the workspace's r field first
     float *corr = apply ? at<float>(c, c.w.r) : nullptr;
+    int64_t slot;
+    if ((rc = stats_before(LS_KERNEL_CLOSURE, c.s, &slot)) != LS_OK) return rc;
     hipLaunchKernelGGL(closure_fused_kernel, dim3(blocks), dim3(kFusedBlock), kFusedLds, c.s,
                        conv_geo(c.G), at<const int32_t>(c, c.w.active),
                        at<const int32_t>(c, c.w.counters), static_cast<int>(c.G.ntiles), feat,
                        at<const __bf16>(c, c.w.wp0), at<const __bf16>(c, c.w.wp1),
                        at<const __bf16>(c, c.w.wp2), params, rout, corr, dx, fallbacks);
     LS_LAUNCH_CHECK("closure_fused_kernel");
+    if ((rc = stats_after(LS_KERNEL_CLOSURE, c.s, slot)) != LS_OK) return rc;
     if (apply) {
         hipLaunchKernelGGL(apply_corr_kernel, dim3(blocks * 4), dim3(kBlock), 0, c.s,
                            conv_geo(c.G), at<const int32_t>(c, c.w.active),
@@ -1204,6 +1215,10 @@ int ls_closure_run_f32(float *phi, const float *F, const ls_grid *g, float dx, f
         ls::set_error("closure run: need nsteps >= 0 and window > 0");
         return LS_ERR_ARG;
     }
+    if (judge < 0 || judge > 2) {
+        ls::set_error("closure run: judge must be 0, 1 or 2 (got %d)", judge);
+        return LS_ERR_ARG;
+    }
     if (capacity < G0.ntiles) {
         ls::set_error("closure run: capacity %lld < %lld tiles", (long long)capacity,
                       (long long)G0.ntiles);
@@ -1245,9 +1260,11 @@ int ls_closure_run_f32(float *phi, const float *F, const ls_grid *g, float dx, f
         }
         if (judge) {
             const unsigned jb = static_cast<unsigned>(std::min<int64_t>(c.G.ntiles, 4096));
+            // judge 2: the fronts within one grid spacing of each other as well
+            const float tau = judge == 2 ? 1.0f : 0.0f;
             hipLaunchKernelGGL(ls::closure_judge_kernel, dim3(jb), dim3(512), 0, c.s, buf[cur],
                                static_cast<const float *>(shadow), c.G.nx, c.G.ny, c.G.ntx,
-                               c.G.nty, static_cast<int>(c.G.ntiles), resets_dev);
+                               c.G.nty, static_cast<int>(c.G.ntiles), dx, tau, resets_dev);
             LS_LAUNCH_CHECK("closure_judge_kernel");
         }
     }

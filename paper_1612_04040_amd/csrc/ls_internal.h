@@ -48,6 +48,7 @@ struct Geom {
     int64_t ntiles;
     int64_t npoints;
     int32_t elem_bytes;  // bytes of a stored phi value (sets the default run width); 4 if unset
+    int32_t run_tiles = 0;  // tiles per work item when > 0 (else from the run width)
 };
 
 // Validates g and fills out; returns LS_OK or a status with the message set.

@@ -8,7 +8,7 @@
 namespace ls {
 
 namespace {
-constexpr int kKinds = 4;
+constexpr int kKinds = 5;
 constexpr int64_t kMaxPairs = 65536;
 
 struct Record {

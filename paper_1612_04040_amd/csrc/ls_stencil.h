@@ -67,16 +67,28 @@ __device__ inline C upwind_point(C c, C xm, C xp, C ym, C yp, C zm, C zp, C f, C
             return c - dt * f * g;
         }
     } else {
-        const bool pos = f > C(0);
         const C ax = c - xm, bx = xp - c;
         const C ay = c - ym, by = yp - c;
         const C az = c - zm, bz = zp - c;
-        // upwind pair: F > 0 takes (max(D-,0), min(D+,0)); F < 0 (max(D+,0), min(D-,0))
-        const C px = fmaxf(pos ? ax : bx, 0.f), qx = fminf(pos ? bx : ax, 0.f);
-        const C py = fmaxf(pos ? ay : by, 0.f), qy = fminf(pos ? by : ay, 0.f);
-        const C pz = fmaxf(pos ? az : bz, 0.f), qz = fminf(pos ? bz : az, 0.f);
-        const C s = px * px + qx * qx + py * py + qy * qy + pz * pz + qz * qz;
-        return c - (dtdx * f) * __builtin_amdgcn_sqrtf(s);
+        // upwind pair of each axis: F > 0 takes (max(D-,0), min(D+,0)) (Eq. 4),
+        // F < 0 (min(D-,0), max(D+,0)) (Eq. 5, the same two squares): the
+        // median of (D-, 0, L) and of (D+, 0, -L) with L = +inf for F > 0 and
+        // -inf for F < 0 selects either pair with one instruction each
+        const C L = f > C(0) ? __builtin_inff() : -__builtin_inff();
+        const C px = __builtin_amdgcn_fmed3f(ax, 0.f, L), qx = __builtin_amdgcn_fmed3f(bx, 0.f, -L);
+        const C py = __builtin_amdgcn_fmed3f(ay, 0.f, L), qy = __builtin_amdgcn_fmed3f(by, 0.f, -L);
+        const C pz = __builtin_amdgcn_fmed3f(az, 0.f, L), qz = __builtin_amdgcn_fmed3f(bz, 0.f, -L);
+        // the sum and the update as explicit fused multiply-adds, so that every
+        // kernel compiled from this evaluates the same roundings in the same
+        // order (contraction left to the compiler may pair the terms
+        // differently from one kernel to the next)
+        C s = px * px;
+        s = fmaf(qx, qx, s);
+        s = fmaf(py, py, s);
+        s = fmaf(qy, qy, s);
+        s = fmaf(pz, pz, s);
+        s = fmaf(qz, qz, s);
+        return fmaf(-(dtdx * f), __builtin_amdgcn_sqrtf(s), c);
     }
 }
 
@@ -117,7 +129,10 @@ __device__ inline C smoothed_sign(C c, C xm, C xp, C ym, C yp, C zm, C zp, C dx)
         return c == C(0) ? C(0) : s;
     } else {
         const C ex = xp - xm, ey = yp - ym, ez = zp - zm;
-        const C q = c * c + 0.25f * (ex * ex + ey * ey + ez * ez);
+        C t = ex * ex;  // explicit fused multiply-adds (see upwind_point)
+        t = fmaf(ey, ey, t);
+        t = fmaf(ez, ez, t);
+        const C q = fmaf(c, c, 0.25f * t);
         return c == C(0) ? C(0) : c * __builtin_amdgcn_rsqf(q);
     }
 }
@@ -151,7 +166,7 @@ __device__ inline C mode_finish(C v, C f, C dt, C gamma) {
 #pragma clang fp contract(off)
             w = v + dt * f;
         } else {
-            w = v + dt * f;
+            w = fmaf(dt, f, v);
         }
         if constexpr (MODE == kReinitClamp) w = w < -gamma ? -gamma : (w > gamma ? gamma : w);
         return w;

@@ -258,6 +258,7 @@ constexpr int kDefaultBlocksPerCu = 32;
 constexpr int64_t kPipelineBytes = int64_t(1) << 30;
 
 bool pipeline_forced() { return g_tuning.pipeline == 2; }
+int brick_temporal_mode() { return g_tuning.temporal; }
 
 bool use_pipeline(int64_t phi_bytes, int run_tiles) {
     if (g_tuning.pipeline == 1) return false;
@@ -272,6 +273,7 @@ static int run_width() { return g_tuning.run_width > 0 ? g_tuning.run_width : kD
 // Tiles per work item: the run width in points, by default 128 bytes of
 // stored phi (a full cache line per item row: 32 FP32, 64 FP16, 16 FP64 values).
 int plan_run_tiles(const Geom &g) {
+    if (g.run_tiles > 0) return std::min(kMaxRun, g.run_tiles);
     const int eb = g.elem_bytes > 0 ? g.elem_bytes : 4;
     const int width = g_tuning.run_width > 0 ? g_tuning.run_width : kDefaultRunWidth * 4 / eb;
     return std::max(1, std::min(kMaxRun, width / g.tx));
@@ -845,7 +847,7 @@ int ls_set_tuning(const ls_tuning *t) {
     ls::clear_error();
     if (!t || t->run_width < 0 || t->blocks_per_cu < 0 || t->blocks_per_cu > 64 ||
         t->pipeline < 0 || t->pipeline > 2 || t->vector < 0 || t->vector > 1 ||
-        t->temporal < 0 || t->temporal > 1) {
+        t->temporal < 0 || t->temporal > 2) {
         ls::set_error("tuning: NULL or out-of-range field");
         return LS_ERR_ARG;
     }

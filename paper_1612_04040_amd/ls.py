@@ -78,6 +78,17 @@ _SIGNATURES = {
     "ls_band_build_f32": (_I32, [_VP, _G, _F32, _I32, _VP, _I64, _VP, _VP, _I64, _VP]),
     "ls_band_build_f64": (_I32, [_VP, _G, _F64, _I32, _VP, _I64, _VP, _VP, _I64, _VP]),
     "ls_band_build_f16s": (_I32, [_VP, _F32, _G, _F32, _I32, _VP, _I64, _VP, _VP, _I64, _VP]),
+    "ls_bricks_from_dense_f32": (_I32, [_VP, _G, _VP, _VP]),
+    "ls_bricks_to_dense_f32": (_I32, [_VP, _G, _VP, _VP]),
+    "ls_bricks_from_dense_f16s": (_I32, [_VP, _G, _VP, _VP]),
+    "ls_bricks_to_dense_f16s": (_I32, [_VP, _G, _VP, _VP]),
+    "ls_band_build_bricks_f32": (_I32, [_VP, _G, _F32, _I32, _VP, _I64, _VP, _VP, _I64, _VP]),
+    "ls_band_build_bricks_f16s": (_I32, [_VP, _F32, _G, _F32, _I32, _VP, _I64, _VP, _VP, _I64,
+                                         _VP]),
+    "ls_band_run_bricks_f32": (_I32, [_VP, _VP, _G, _F32, _F32, _F32, _I32, _I32, _F32, _I32,
+                                      _F32, _VP, _I64, _VP, _VP, _VP, _VP, _I64, _VP]),
+    "ls_band_run_bricks_f16s": (_I32, [_VP, _F32, _VP, _G, _F32, _F32, _F32, _I32, _I32, _F32,
+                                       _I32, _F32, _VP, _I64, _VP, _VP, _VP, _VP, _I64, _VP]),
     "ls_upwind_step_f32": (_I32, [_VP, _VP, _G, _F32, _F32, _VP, _VP, _I32, _VP, _VP, _I64, _VP]),
     "ls_upwind_step_f64": (_I32, [_VP, _VP, _G, _F64, _F64, _VP, _VP, _I32, _VP, _VP, _I64, _VP]),
     "ls_upwind_step_f16s": (_I32, [_VP, _F32, _VP, _G, _F32, _F32, _VP, _VP, _I32, _VP, _VP, _I64,
@@ -155,6 +166,7 @@ LS_KERNEL_UPWIND = 0
 LS_KERNEL_BAND_FLAG = 1
 LS_KERNEL_REINIT = 2
 LS_KERNEL_GATHER = 3
+LS_KERNEL_CLOSURE = 4
 
 
 def lib():
@@ -231,6 +243,55 @@ def ls_band_build_f32(phi, g, gamma, dilate, tiles, capacity, ntiles_dev, worksp
     return _check(lib().ls_band_build_f32(_ptr(phi), _g(g), gamma, dilate, _ptr(tiles), capacity,
                                           _ptr(ntiles_dev), _ptr(workspace), workspace_bytes,
                                           _stream(stream)))
+
+
+def ls_bricks_from_dense_f32(src, g, dst, stream=None):
+    return _check(lib().ls_bricks_from_dense_f32(_ptr(src), _g(g), _ptr(dst), _stream(stream)))
+
+
+def ls_bricks_to_dense_f32(src, g, dst, stream=None):
+    return _check(lib().ls_bricks_to_dense_f32(_ptr(src), _g(g), _ptr(dst), _stream(stream)))
+
+
+def ls_bricks_from_dense_f16s(src, g, dst, stream=None):
+    return _check(lib().ls_bricks_from_dense_f16s(_ptr(src), _g(g), _ptr(dst), _stream(stream)))
+
+
+def ls_bricks_to_dense_f16s(src, g, dst, stream=None):
+    return _check(lib().ls_bricks_to_dense_f16s(_ptr(src), _g(g), _ptr(dst), _stream(stream)))
+
+
+def ls_band_build_bricks_f32(phi_b, g, gamma, dilate, tiles, capacity, ntiles_dev, workspace,
+                             workspace_bytes, stream=None):
+    return _check(lib().ls_band_build_bricks_f32(_ptr(phi_b), _g(g), gamma, dilate, _ptr(tiles),
+                                                 capacity, _ptr(ntiles_dev), _ptr(workspace),
+                                                 workspace_bytes, _stream(stream)))
+
+
+def ls_band_build_bricks_f16s(phi_b, scale, g, gamma, dilate, tiles, capacity, ntiles_dev,
+                              workspace, workspace_bytes, stream=None):
+    return _check(lib().ls_band_build_bricks_f16s(_ptr(phi_b), scale, _g(g), gamma, dilate,
+                                                  _ptr(tiles), capacity, _ptr(ntiles_dev),
+                                                  _ptr(workspace), workspace_bytes,
+                                                  _stream(stream)))
+
+
+def ls_band_run_bricks_f32(phi_b, F_b, g, dx, dt, gamma, nsteps, window, beta, reinit_iters,
+                           dtau, tiles, capacity, ntiles_dev, tile_steps_dev, scratch_b,
+                           workspace, workspace_bytes, stream=None):
+    return _check(lib().ls_band_run_bricks_f32(
+        _ptr(phi_b), _ptr(F_b), _g(g), dx, dt, gamma, nsteps, window, beta, reinit_iters, dtau,
+        _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(tile_steps_dev), _ptr(scratch_b),
+        _ptr(workspace), workspace_bytes, _stream(stream)))
+
+
+def ls_band_run_bricks_f16s(phi_b, scale, F_b, g, dx, dt, gamma, nsteps, window, beta,
+                            reinit_iters, dtau, tiles, capacity, ntiles_dev, tile_steps_dev,
+                            scratch_b, workspace, workspace_bytes, stream=None):
+    return _check(lib().ls_band_run_bricks_f16s(
+        _ptr(phi_b), scale, _ptr(F_b), _g(g), dx, dt, gamma, nsteps, window, beta, reinit_iters,
+        dtau, _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(tile_steps_dev), _ptr(scratch_b),
+        _ptr(workspace), workspace_bytes, _stream(stream)))
 
 
 def ls_band_build_f64(phi, g, gamma, dilate, tiles, capacity, ntiles_dev, workspace,
@@ -579,7 +640,7 @@ def ls_closure_run_f32(phi, F, g, dx, dt, gamma, fmax, params, nsteps, window, j
                        cws_bytes, stream=None):
     return _check(lib().ls_closure_run_f32(
         _ptr(phi), _ptr(F), _g(g), dx, dt, gamma, fmax, _ptr(params), int(nsteps), int(window),
-        1 if judge else 0, _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(fallbacks_dev),
+        int(judge), _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(fallbacks_dev),
         _ptr(resets_dev), _ptr(ws), ws_bytes, _ptr(cws), cws_bytes, _stream(stream)))
 
 

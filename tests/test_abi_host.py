@@ -359,3 +359,52 @@ def test_copy_counted_errors():
                  dict(blocks=-1), dict(unit_bytes=1 << 40, max_units=1 << 30)):
         a = dict(ok, **over)
         assert _status(ls.ls_copy_counted, *a.values()) == ls.LS_ERR_ARG, over
+
+
+def test_brick_errors():
+    """The brick calls reject shapes and arguments they do not take, on the host."""
+    g = ls.grid((64, 64, 64))
+    cases = [
+        (lambda: ls.ls_bricks_from_dense_f32(FAKE, ls.grid((60, 64, 64)), FAKE * 2, 0),
+         ls.LS_ERR_UNSUPPORTED),
+        (lambda: ls.ls_bricks_from_dense_f32(FAKE, ls.grid((64, 64, 64), (8, 4, 8)), FAKE * 2, 0),
+         ls.LS_ERR_UNSUPPORTED),
+        (lambda: ls.ls_bricks_to_dense_f32(None, g, FAKE, 0), ls.LS_ERR_ARG),
+        (lambda: ls.ls_bricks_to_dense_f16s(FAKE, g, FAKE, 0), ls.LS_ERR_ARG),  # same buffer
+        (lambda: ls.ls_bricks_from_dense_f16s(FAKE + 2, g, FAKE * 2, 0), ls.LS_ERR_ARG),
+        (lambda: ls.ls_band_build_bricks_f32(FAKE, g, 0.1, 2, FAKE, ls.ls_grid_tiles(g), FAKE,
+                                             FAKE * 256, ls.ls_workspace_bytes(g), 0),
+         ls.LS_ERR_ARG),
+        (lambda: ls.ls_band_build_bricks_f16s(FAKE, 0.0, g, 0.1, 1, FAKE, ls.ls_grid_tiles(g),
+                                              FAKE, FAKE * 256, ls.ls_workspace_bytes(g), 0),
+         ls.LS_ERR_ARG),
+    ]
+    run = dict(phi_b=FAKE, F_b=FAKE * 2, g=g, dx=0.01, dt=0.005, gamma=0.06, nsteps=10,
+               window=10, beta=0.0, reinit_iters=0, dtau=0.0, tiles=FAKE,
+               capacity=ls.ls_grid_tiles(g), ntiles_dev=FAKE, tile_steps_dev=None,
+               scratch_b=FAKE * 3, workspace=FAKE * 256,
+               workspace_bytes=ls.ls_workspace_bytes(g), stream=0)
+    for over, status in [(dict(window=0), ls.LS_ERR_ARG), (dict(beta=0.07), ls.LS_ERR_ARG),
+                         (dict(beta=-0.01), ls.LS_ERR_ARG), (dict(scratch_b=FAKE), ls.LS_ERR_ARG),
+                         (dict(dx=0.0), ls.LS_ERR_ARG), (dict(capacity=5), ls.LS_ERR_CAPACITY),
+                         (dict(workspace_bytes=64), ls.LS_ERR_CAPACITY),
+                         (dict(reinit_iters=-1), ls.LS_ERR_ARG),
+                         (dict(g=ls.grid((64, 64, 60))), ls.LS_ERR_UNSUPPORTED)]:
+        a = dict(run, **over)
+        cases.append((lambda a=a: ls.ls_band_run_bricks_f32(*a.values()), status))
+    for fn, status in cases:
+        with pytest.raises(ls.LsError) as e:
+            fn()
+        assert e.value.status == status, (e.value.message, status)
+        assert e.value.message
+
+
+def test_closure_run_rejects_unknown_judge_modes():
+    g = ls.grid((64, 64, 64))
+    for judge in (-1, 3):
+        with pytest.raises(ls.LsError) as e:
+            ls.ls_closure_run_f32(FAKE, FAKE, g, 0.01, 0.005, 0.06, 1.0, FAKE, 10, 10, judge, FAKE,
+                                  ls.ls_grid_tiles(g), FAKE, FAKE, FAKE, FAKE * 256, 1 << 20,
+                                  FAKE * 256, 1 << 20, 0)
+        assert e.value.status == ls.LS_ERR_ARG
+        assert "judge" in e.value.message

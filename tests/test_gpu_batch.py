@@ -82,6 +82,39 @@ def test_batch_grid_matches_oracle():
         assert np.max(np.abs(got - want)) <= bound
 
 
+@pytest.mark.parametrize("tile", CANDIDATES)
+def test_batch_every_tile_shape_matches_oracle(tile):
+    """Every tile shape the autotuner can pick, batched and alone, against the
+    oracle run with the same tile shape: grids of 45^3 and 38^3 (partial tiles
+    at every high face for every shape, ragged x-runs), 30 steps in windows of
+    10.  Band lists of every window bit-exact, phi within the FP32 bound."""
+    insts = W.ellipsoid_batch(seed=31, base=32, sizes=[45, 38])
+    specs = [((it.n,) * 3, tile, it.dx, it.dt, it.gamma) for it in insts]
+    assert all(it.n % t for it in insts for t in tile)  # partial tiles on every axis
+    b = Batch(specs)
+    b.load([it.phi for it in insts], [it.F for it in insts])
+    b.run(30, 10)
+    lists = b.band_lists()
+    for i, it in enumerate(insts):
+        print(f"batch tile {tile} grid {it.n}^3", flush=True)
+        want, wl = oracle.run_band(it.phi, it.F, it.dx, it.dt, np.float32(it.gamma), 30,
+                                   window=10, tile=tile, record_tiles=True)
+        bound = fp32_step_bound(it.phi, it.F, it.dx, it.dt, 30)
+        got = host(b.view(b.phi, i)).astype(np.float64)
+        assert lists[i].tolist() == wl[-1].tolist(), f"batched grid {i}: band list"
+        assert np.max(np.abs(got - want)) <= bound, f"batched grid {i}"
+        # the same grid through the single-grid driver with this tile shape
+        bg = BandGrid((it.n,) * 3, tile, "f32")
+        pd = to_dev(it.phi)
+        got_lists = []
+        for w in range(3):
+            bg.run(pd, to_dev(it.F), it.dx, it.dt, it.gamma, 10, 10)
+            got_lists.append(bg.band_list().numpy().tolist())
+        assert got_lists == [x.tolist() for x in wl], f"single grid {i}: band lists"
+        single = host(pd).astype(np.float64)
+        assert np.max(np.abs(single - want)) <= bound, f"single grid {i}"
+
+
 def test_batch_graph_replay_matches_eager():
     specs, phis, Fs, _ = _specs(seed=8, count=6)
     b = Batch(specs)

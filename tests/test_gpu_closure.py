@@ -320,6 +320,61 @@ def test_judge_resets_a_bubble_the_plain_run_removes():
     assert err <= 1e-3 * dx, err / dx
 
 
+def test_judge_bounds_the_front_position():
+    """A plane front phi = x - 8.5 dx (32^3) advancing at F = 0.8 with dt =
+    dx / 2 (0.4 dx per step) and a constant correction r = -1/2 (accepted;
+    the limiter makes the corrected increment 3/2 of the plain one, 0.6 dx
+    per step): after a window of 8 steps the corrected front (13.3 dx) leads
+    the plain shadow's (11.7 dx) by 1.6 dx, both in the same tiles (the same
+    crossing topology).  The topology judge
+    (judge = 1) keeps the corrected run; the position judge (judge = 2,
+    fronts within 1 dx) resets the tiles along the front to the shadow, and
+    the judged run matches the FP64 reference (oracle corrected steps, plain
+    shadow and position judge)."""
+    n = 32
+    dx = 1.0 / n
+    dt = float(np.float32(0.5 * dx))
+    phi0 = W.plane((n, n, n), dx, (1.0, 0.0, 0.0), 8.5 * dx, dtype=np.float32)
+    F = np.full((n, n, n), 0.8, np.float32)
+    gamma = float(np.float32(6 * dx))
+    p = C.unflatten(C.init_params(np.random.default_rng(2)))
+    p["b2"][:] = -0.5
+    params = to_dev(C.flatten(p))
+    Fd = to_dev(F)
+    cg = C.ClosureGrid((n, n, n))
+    runs, resets = {}, {}
+    for judge in (1, 2):
+        pd = to_dev(phi0)
+        cg.fallbacks.zero_()
+        cg.resets.zero_()
+        cg.run(pd, Fd, dx, dt, gamma, 1.0, params, 8, 8, judge=judge)
+        runs[judge] = host(pd)
+        resets[judge] = int(host(cg.resets)[0])
+        assert int(host(cg.fallbacks)[0]) == 0
+    assert resets[1] == 0
+    assert resets[2] > 0
+    # the FP64 reference of the position-judged run
+    pr = {k: bf16(v.astype(np.float32)) for k, v in C.unflatten(C.flatten(p)).items()}
+    for k in ("b0", "b1", "b2"):
+        pr[k] = C.unflatten(C.flatten(p))[k].astype(np.float32).astype(np.float64)
+    g32 = np.float32(gamma)
+    shadow = oracle.run_band(phi0, F, dx, dt, g32, 8, window=8)
+    x = phi0.astype(np.float64)
+    for s in range(8):
+        if s == 0:
+            band = oracle.band_tiles(x.astype(np.float32), TILE, g32, True)
+            active = oracle.band_tiles(x.astype(np.float32), TILE, g32, False)
+        x, fb = CL.closure_step(pr, x, F, dx, dt, g32, np.float32(1.0), band, active)
+        assert fb == 0
+    unjudged = x.copy()
+    assert np.max(np.abs(unjudged - runs[1])) <= 1e-3 * dx
+    x, k = CL.judge(x, shadow, dx=dx, tau=1.0)
+    assert k == resets[2]
+    err = np.max(np.abs(runs[2].astype(np.float64) - x))
+    report("closure_judge_position", max_err_dx=float(err / dx), resets=resets[2])
+    assert err <= 1e-3 * dx, err / dx
+
+
 @pytest.mark.timeout(600)
 def test_forward_full_size_sampled_tiles():
     """The network at the evaluation size (128^3 coarse grid of the closure

@@ -16,6 +16,8 @@
 * The 256-grid batch at full size: sampled grids equal their single-grid runs,
   bit for bit.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -163,67 +165,144 @@ def test_torus_f16s_reduced():
     assert err.max() <= bound
 
 
-@pytest.mark.timeout(900)
-@pytest.mark.parametrize("n", [256])
-def test_torus_f16s_error_report(n):
-    """The scaled-FP16 torus recipe, 500 steps, against the FP64 oracle run on
-    the unquantised inputs with its own band decisions: the errors near the
-    front and in the tube, and the Hausdorff distance of the fronts, are
-    reported; asserted: the tube error stays within the FP16 storage bound
-    (steps + 1) x half an FP16 ulp of the largest |phi|/s in the band, times s
-    (the update is non-expansive in the max norm and each step adds at most
-    one store rounding; the band lists of the two runs can differ at the band
-    margin, outside the tube), and the fronts lie within 1 dx."""
-    from paper_1612_04040_amd import metrics as M
+def _f16s_runs(n, steps, progress):
+    """The scaled-FP16 torus recipe at n^3 for `steps` steps, three ways:
+    the GPU (window by window, band lists recorded); the oracle with the same
+    storage (FP64 arithmetic, every new value rounded to what scaled FP16
+    holds, band decisions on its own stored state); the oracle in FP64 on the
+    unquantised inputs (band decisions in FP32).  Returns the GPU field, both
+    oracle fields and the three runs' band lists."""
+    import time
 
-    steps = 500
     wl = W.torus_grf(n, steps, base=128)
     s = np.float32(wl.scale)
+    g32 = np.float32(wl.gamma)
     h = W.quantize_f16s(wl.phi, s)
     bg = BandGrid((n, n, n), wl.tile, "f16s")
     hd, Fd = torch.from_numpy(h).to(dev()), to_dev(wl.F)
-    lists = []
+    gpu_lists = []
     for _ in range(steps // wl.window):
         bg.build(hd, wl.gamma, dilate=True, scale=float(s))
-        lists.append(bg.band_list().numpy())
+        gpu_lists.append(bg.band_list().numpy())
         bg.step(hd, Fd, wl.dx, wl.dt, wl.window, scale=float(s))
     got = oracle.dequant_f16s(host(hd), s).astype(np.float64)
-    want, own_lists = oracle.run_band(wl.phi.astype(np.float64), wl.F, wl.dx, wl.dt,
-                                      np.float32(wl.gamma), steps, window=wl.window,
-                                      record_tiles=True)
-    err = np.abs(got - want)
-    front = np.abs(want) < wl.dx
-    tube = np.abs(want) < wl.gamma
-    rec = dict(n=n, steps=steps,
-               windows_with_other_lists=int(sum(a.tolist() != b.tolist()
-                                                for a, b in zip(lists, own_lists))),
-               max_err_front_dx=float(err[front].max() / wl.dx),
-               max_err_tube_dx=float(err[tube].max() / wl.dx),
-               rms_err_front_dx=float(np.sqrt(np.mean(err[front] ** 2)) / wl.dx),
-               hausdorff_dx=M.hausdorff(M.zero_crossings(got, wl.dx),
-                                        M.zero_crossings(want, wl.dx)) / wl.dx,
-               by_abs_phi_dx=error_by_band_distance(err, want, wl.dx))
-    band = np.zeros((n // 8,) * 3, bool)
-    for tl in own_lists:
-        band.reshape(-1)[tl] = True
-    mask = np.repeat(np.repeat(np.repeat(band, 8, 0), 8, 1), 8, 2)
-    hmax = float(max(np.abs(want[mask]).max(), np.abs(wl.phi[mask]).max())) / float(s)
-    half_ulp = 2.0 ** (np.floor(np.log2(hmax)) - 11)
-    rec["bound_dx"] = (steps + 1) * half_ulp * float(s) / wl.dx
-    report("torus_f16s_error", **rec)
-    print(f"[f16s torus {n}^3] {rec}", flush=True)
-    assert rec["max_err_tube_dx"] <= rec["bound_dx"]
-    assert rec["hausdorff_dx"] <= 1.0
+    del hd, Fd, bg
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    stored = oracle.dequant_f16s(h, s).astype(np.float64)
+    stored_lists = []
+    plain = wl.phi.astype(np.float64)
+    wl.phi = None
+    plain_lists = []
+    for w in range(steps // wl.window):
+        tl = oracle.band_tiles(oracle.decide_precision(stored, "f16s", s), wl.tile, g32, True)
+        stored_lists.append(tl)
+        stored = oracle.upwind_steps(stored, wl.F, wl.dx, wl.dt, tl, wl.window, wl.tile,
+                                     store_scale=s)
+        tl = oracle.band_tiles(oracle.decide_precision(plain, "f32"), wl.tile, g32, True)
+        plain_lists.append(tl)
+        plain = oracle.upwind_steps(plain, wl.F, wl.dx, wl.dt, tl, wl.window, wl.tile)
+        if progress:
+            print(f"  oracle window {w + 1}/{steps // wl.window} "
+                  f"({time.perf_counter() - t0:.0f} s)", flush=True)
+    return wl, s, got, stored, plain, gpu_lists, stored_lists, plain_lists
+
+
+def _f16s_error_report(n, steps=500, progress=False):
+    """The scaled-FP16 torus recipe (R = 0.3, r = 0.1, F = 1 + 0.3 GRF,
+    s = gamma = 6 dx, 8^3 tiles, 10-step windows) against the oracle.
+
+    Storage rounding and band divergence are separated: the GPU run is
+    compared with the oracle run that stores in the same format and takes its
+    band decisions on its own stored values, so the two differ only where
+    the GPU's FP32 arithmetic and the oracle's FP64 arithmetic round a new
+    value to neighbouring FP16 codes (a value within a few FP32 ulps of a
+    rounding midpoint; the step code test below pins that this is the only
+    difference).  Such a flip moves a value by one FP16 ulp, and the
+    non-expansive update carries it on without growth, so the difference near
+    the front (|phi| < dx, |h| < 1/6, one ulp <= 2^-13 s) stays far below its
+    worst case of one flip per step; asserted: 0.05 dx (about 68 ulps; a
+    storage that truncated instead of rounding to nearest would drift by half
+    an ulp per step, ~0.18 dx after 500 steps), and the fronts within 0.5 dx.
+    The error of the FP16-stored scheme against the FP64 oracle on the
+    unquantised inputs is reported (the storage error itself: the oracle's own
+    stored run against its FP64 run, and the device against the FP64 run); the
+    device's front lies within 0.5 dx of the distance the storage format puts
+    between the two oracle runs."""
+    from paper_1612_04040_amd import metrics as M
+
+    wl, s, got, stored, plain, gl, sl, pl = _f16s_runs(n, steps, progress)
+    dx, gamma = wl.dx, wl.gamma
+    ulp_front = 2.0 ** -13 * float(s)
+    rec = {"n": n, "steps": steps}
+    rec["windows_with_other_lists_vs_stored"] = int(sum(a.tolist() != b.tolist()
+                                                        for a, b in zip(gl, sl)))
+    rec["windows_with_other_lists_vs_fp64"] = int(sum(a.tolist() != b.tolist()
+                                                      for a, b in zip(gl, pl)))
+    nt = n // 8
+    masks = {}
+    for name, lists in (("A", None), ("U", sl[-1])):
+        if lists is None:
+            lists = oracle.band_tiles(oracle.decide_precision(stored, "f16s", s), wl.tile,
+                                      np.float32(gamma), False)
+        band = np.zeros(nt ** 3, bool)
+        band[lists] = True
+        masks[name] = np.repeat(np.repeat(np.repeat(band.reshape(nt, nt, nt), 8, 0), 8, 1),
+                                8, 2)
+    for tag, ref in (("stored", stored), ("fp64", plain)):
+        err = np.abs(got - ref)
+        front = np.abs(ref) < dx
+        tube = np.abs(ref) < gamma
+        rec[f"vs_{tag}"] = {
+            "max_err_front_dx": float(err[front].max() / dx),
+            "rms_err_front_dx": float(np.sqrt(np.mean(err[front] ** 2)) / dx),
+            "max_err_tube_dx": float(err[tube].max() / dx),
+            "max_err_A_dx": float(err[masks["A"]].max() / dx),
+            "max_err_U_dx": float(err[masks["U"]].max() / dx),
+            "hausdorff_dx": M.hausdorff(M.zero_crossings(got, dx), M.zero_crossings(ref, dx)) / dx,
+        }
+        del err
+    rec["vs_stored"]["front_err_in_ulps"] = rec["vs_stored"]["max_err_front_dx"] * dx / ulp_front
+    rec["storage_vs_fp64"] = {
+        "max_err_front_dx": float(np.abs(stored - plain)[np.abs(plain) < dx].max() / dx),
+        "hausdorff_dx": M.hausdorff(M.zero_crossings(stored, dx),
+                                    M.zero_crossings(plain, dx)) / dx}
+    rec["worst_case_front_bound_dx"] = steps * ulp_front / dx
+    report(f"torus_f16s_error_{n}", **rec)
+    print(f"[f16s torus {n}^3, {steps} steps] {rec}", flush=True)
+    # the device's FP16-stored run against the oracle's FP16-stored run
+    assert rec["vs_stored"]["max_err_front_dx"] <= 0.05
+    assert rec["vs_stored"]["hausdorff_dx"] <= 0.5
+    # against the FP64 scheme the device is as far as the storage format
+    # itself takes the oracle (stored vs FP64), within the same margin
+    assert rec["vs_fp64"]["hausdorff_dx"] <= rec["storage_vs_fp64"]["hausdorff_dx"] + 0.5
+
+
+@pytest.mark.timeout(900)
+def test_torus_f16s_error_512():
+    """The FP16s recipe at 512^3, 500 steps (the oracle runs twice on the
+    host: with the FP16 storage and in plain FP64)."""
+    _f16s_error_report(512)
+
+
+@pytest.mark.timeout(1500)
+@pytest.mark.skipif(not os.environ.get("LS_F16S_FULL"),
+                    reason="1024^3 x 500 steps: two oracle runs of ~5 min each on the host; "
+                           "set LS_F16S_FULL=1 to run it (its figures are in the design notes)")
+def test_torus_f16s_error_1024():
+    _f16s_error_report(1024, progress=True)
 
 
 @pytest.mark.timeout(1200)
 def test_torus1024_f16s_full_size_first_step():
     """The 1024^3 scaled-FP16 torus at full size, in the launch configuration
     the bench times (8^3 tiles, 64-point item rows, the vectorised FP16 step):
-    the band list of phi^0 equals the oracle's bit for bit, and one step
-    matches the FP64 oracle's step of the dequantised phi^0 on every band
-    point within one FP16 storage rounding (half an ulp of |phi|/s, times s)
-    plus the FP32 arithmetic bound."""
+    the band list of phi^0 equals the oracle's bit for bit; after one step
+    every stored code is the FP16 rounding (to nearest, ties to even) of the
+    FP64 oracle's new value / s, except within the FP32 arithmetic error of a
+    rounding midpoint, where it is one of the two neighbouring codes; and the
+    values are within one FP16 storage rounding (half an ulp of |phi|/s,
+    times s) plus the FP32 arithmetic bound."""
     from gpu_util import fp32_step_bound
 
     n = 1024
@@ -239,13 +318,48 @@ def test_torus1024_f16s_full_size_first_step():
     want_list = oracle.band_tiles(phi0, wl.tile, np.float32(wl.gamma), True)
     assert got_list.tolist() == want_list.tolist()
     bg.step(hd, Fd, wl.dx, wl.dt, 1, scale=float(s))
-    got = oracle.dequant_f16s(host(hd), s)
+    codes = host(hd)
+    got = oracle.dequant_f16s(codes, s)
     want = oracle.upwind_steps(phi0, wl.F, wl.dx, wl.dt, want_list, 1, wl.tile)
     mask = np.zeros((n // 8,) * 3, bool)
     mask.reshape(-1)[want_list] = True
-    g = got.reshape(n // 8, 8, n // 8, 8, n // 8, 8).transpose(0, 2, 4, 1, 3, 5)[mask]
-    w = want.reshape(n // 8, 8, n // 8, 8, n // 8, 8).transpose(0, 2, 4, 1, 3, 5)[mask]
-    del got, want
+
+    def band(a):
+        return a.reshape(n // 8, 8, n // 8, 8, n // 8, 8).transpose(0, 2, 4, 1, 3, 5)[mask]
+
+    g, w, c16, c0 = band(got), band(want), band(codes), band(phi0)
+    del got, want, codes
+    # The stored codes are the round-to-nearest-even FP16 codes of the exact
+    # new value / s wherever that decision does not depend on arithmetic
+    # precision: the device's FP32 value of v / s differs from the FP64 one by
+    # at most 2 u |v| (the final fma and the division) plus 16 u of the
+    # increment |v - phi| (differences, six squares, sqrt, dt/dx * F), u =
+    # 2^-24; a code may differ from the FP64 one by one ulp only where the
+    # FP64 value lies within that distance of a rounding midpoint.  (A
+    # truncating or mis-scaled store fails this on most points.)
+    u = 2.0 ** -24
+    sc = float(s)
+    vh = w / sc
+    delta = (2 * u * np.abs(w) + 16 * u * np.abs(w - c0.astype(np.float64))) / sc + \
+        2 * u * np.abs(vh)
+    lo, hi = oracle.round_binary16(vh - delta), oracle.round_binary16(vh + delta)
+    gh = c16.astype(np.float64)
+    decided = lo == hi
+    assert np.array_equal(gh[decided], lo[decided]), \
+        f"{int(np.sum(gh[decided] != lo[decided]))} decided codes differ"
+    # elsewhere a code the interval of possible FP32 results rounds to (the
+    # two codes around the midpoint; more in the subnormal range, where the
+    # interval can span several codes)
+    und = ~decided
+    inside = (gh[und] >= lo[und]) & (gh[und] <= hi[und])
+    if not inside.all():
+        i = np.flatnonzero(~inside)[:5]
+        print("outside:", vh[und][i], gh[und][i], lo[und][i], hi[und][i], delta[und][i])
+    assert inside.all()
+    report("torus1024_f16s_first_step_codes", band_points=int(gh.size),
+           undecided=int(np.sum(~decided)),
+           flips=int(np.sum(gh[~decided] != oracle.round_binary16(vh[~decided]))))
+    del vh, delta, lo, hi, gh, decided, c16, c0
     # per point: half an FP16 ulp of |want|/s (2^-25 s in the subnormal range),
     # the FP32 roundings of v / s and of the decode h * s, and the FP32
     # arithmetic of the step (global bound)
