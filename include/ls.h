@@ -126,6 +126,29 @@ int ls_upwind_step_f16s(uint16_t *phi_h, float scale, const float *F, const ls_g
                         void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Band build without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): ls_band_build_f32 with the workspace taken from a fixed
+ * device array of the library instead of an argument.  Same arguments,
+ * results (bit for bit), checks and errors as ls_band_build_f32 otherwise.
+ *
+ * The array holds ls_band_build_noalloc_max_bytes() bytes (16 MiB) on every
+ * device the library runs on, until the process ends; a grid whose workspace
+ * (ls_workspace_bytes) is larger returns LS_ERR_CAPACITY before anything is
+ * launched (8^3 tiles: grids of up to about 440 000 tiles, e.g. 512^3).  The
+ * call allocates nothing (no hipMalloc, no library allocation; keep kernel
+ * timing, ls_stats_enable, off, since it creates HIP events).  Every call on
+ * one device uses that device's one array and leaves its contents behind:
+ * calls that overlap on one device (concurrent streams, or host threads)
+ * race and must be serialised by the caller.  The array's address is looked
+ * up on the first call on each device (LS_ERR_HIP if that fails).
+ * ------------------------------------------------------------------------- */
+int64_t ls_band_build_noalloc_max_bytes(void);
+int ls_band_build_f32_noalloc(const float *phi, const ls_grid *g, float gamma, int dilate,
+                              int32_t *tiles, int64_t capacity, int32_t *ntiles_dev,
+                              void *stream);
+
+/* ---------------------------------------------------------------------------
  * Incremental band rebuild: the list ls_band_build_* (dilate = 1) would
  * return, computed by rescanning only the tiles of a previous band list
  * prev_tiles[0 .. *prev_ntiles_dev) instead of the whole grid.

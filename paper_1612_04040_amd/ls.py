@@ -89,6 +89,8 @@ _SIGNATURES = {
                                       _F32, _VP, _I64, _VP, _VP, _VP, _VP, _I64, _VP]),
     "ls_band_run_bricks_f16s": (_I32, [_VP, _F32, _VP, _G, _F32, _F32, _F32, _I32, _I32, _F32,
                                        _I32, _F32, _VP, _I64, _VP, _VP, _VP, _VP, _I64, _VP]),
+    "ls_band_build_noalloc_max_bytes": (_I64, []),
+    "ls_band_build_f32_noalloc": (_I32, [_VP, _G, _F32, _I32, _VP, _I64, _VP, _VP]),
     "ls_upwind_step_f32": (_I32, [_VP, _VP, _G, _F32, _F32, _VP, _VP, _I32, _VP, _VP, _I64, _VP]),
     "ls_upwind_step_f64": (_I32, [_VP, _VP, _G, _F64, _F64, _VP, _VP, _I32, _VP, _VP, _I64, _VP]),
     "ls_upwind_step_f16s": (_I32, [_VP, _F32, _VP, _G, _F32, _F32, _VP, _VP, _I32, _VP, _VP, _I64,
@@ -292,6 +294,15 @@ def ls_band_run_bricks_f16s(phi_b, scale, F_b, g, dx, dt, gamma, nsteps, window,
         _ptr(phi_b), scale, _ptr(F_b), _g(g), dx, dt, gamma, nsteps, window, beta, reinit_iters,
         dtau, _ptr(tiles), capacity, _ptr(ntiles_dev), _ptr(tile_steps_dev), _ptr(scratch_b),
         _ptr(workspace), workspace_bytes, _stream(stream)))
+
+
+def ls_band_build_noalloc_max_bytes():
+    return _check(lib().ls_band_build_noalloc_max_bytes())
+
+
+def ls_band_build_f32_noalloc(phi, g, gamma, dilate, tiles, capacity, ntiles_dev, stream=None):
+    return _check(lib().ls_band_build_f32_noalloc(_ptr(phi), _g(g), gamma, dilate, _ptr(tiles),
+                                                  capacity, _ptr(ntiles_dev), _stream(stream)))
 
 
 def ls_band_build_f64(phi, g, gamma, dilate, tiles, capacity, ntiles_dev, workspace,

@@ -361,6 +361,35 @@ def test_copy_counted_errors():
         assert _status(ls.ls_copy_counted, *a.values()) == ls.LS_ERR_ARG, over
 
 
+def test_band_build_noalloc_errors():
+    """The allocation-free build rejects bad arguments and grids whose
+    workspace exceeds its fixed array, before touching a device."""
+    cap_bytes = ls.ls_band_build_noalloc_max_bytes()
+    assert cap_bytes == 16 << 20
+    g = ls.grid((64, 64, 64))
+    ok = dict(phi=FAKE, g=g, gamma=0.1, dilate=1, tiles=FAKE, capacity=ls.ls_grid_tiles(g),
+              ntiles_dev=FAKE, stream=0)
+    cases = [
+        (dict(phi=None), ls.LS_ERR_ARG),
+        (dict(tiles=None), ls.LS_ERR_ARG),
+        (dict(ntiles_dev=None), ls.LS_ERR_ARG),
+        (dict(dilate=-1), ls.LS_ERR_ARG),
+        (dict(gamma=float("nan")), ls.LS_ERR_ARG),
+        (dict(capacity=10), ls.LS_ERR_CAPACITY),
+        (dict(g=ls.grid((64, 0, 64))), ls.LS_ERR_ARG),
+    ]
+    for over, status in cases:
+        a = dict(ok, **over)
+        assert _status(ls.ls_band_build_f32_noalloc, *a.values()) == status, over
+    # 512^3 in 8^3 tiles fits the array; 1024^3 does not
+    assert ls.ls_workspace_bytes(ls.grid((512, 512, 512))) <= cap_bytes
+    big = ls.grid((1024, 1024, 1024))
+    assert ls.ls_workspace_bytes(big) > cap_bytes
+    a = dict(ok, g=big, capacity=ls.ls_grid_tiles(big))
+    assert _status(ls.ls_band_build_f32_noalloc, *a.values()) == ls.LS_ERR_CAPACITY
+    assert "fixed" in ls.ls_last_error()
+
+
 def test_brick_errors():
     """The brick calls reject shapes and arguments they do not take, on the host."""
     g = ls.grid((64, 64, 64))
