@@ -33,7 +33,9 @@ static_assert(kNParams == 8673, "parameter count");
 
 __device__ inline __bf16 to_bf16(float v) { return static_cast<__bf16>(v); }
 __device__ inline float from_bf16(__bf16 v) { return static_cast<float>(v); }
-__device__ inline float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU with the hardware reciprocal (about 1 ulp; the result is rounded to
+// BF16 or feeds a BF16-rounded product)
+__device__ inline float silu_f(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 // Cut-off function of Eq. 8 with beta = gamma / 2, in u = |phi| / gamma:
 // 1 for u <= 1/2, 8 (u - 1)^2 (2u - 1/2) for 1/2 < u <= 1, 0 beyond.
 __device__ inline float cutoff_f(float phi, float inv_gamma) {
@@ -43,7 +45,7 @@ __device__ inline float cutoff_f(float phi, float inv_gamma) {
     return 0.0f;
 }
 __device__ inline float silu_grad_f(float z) {
-    const float s = 1.0f / (1.0f + __expf(-z));
+    const float s = __builtin_amdgcn_rcpf(1.0f + __expf(-z));
     return s * (1.0f + z * (1.0f - s));
 }
 
@@ -282,19 +284,68 @@ __global__ __launch_bounds__(kBlock) void closure_conv_kernel(
 // (from features of the 14^3 points within 3), layer 2 on the 10^3 points
 // within 1, layer 3 on the tile.  An active tile lies one tile inside the
 // band, so every point read is in the band or outside the grid (zero).
+//
+// The three layers advance together plane by plane in z, each wave keeping
+// one layer's weights in registers: wave 0 computes layer-1 plane s in step
+// s, waves 1-2 layer-2 plane s-3 (from layer-1 planes s-3..s-1), wave 3
+// output plane s-6 (from layer-2 planes s-6..s-4, with phi and the plain step
+// of its points loaded one step ahead), one barrier per step.
+// Layer-1 and layer-2 activations live in rings of four z-planes, so a block
+// holds 52 KB of LDS and three blocks share a CU.  The arithmetic of every
+// point (operands, chunk order, rounding) is that of the layer-by-layer
+// kernels.
 
 constexpr int kF0 = kT + 6, kF1 = kT + 4, kF2 = kT + 2;  // 14, 12, 10
+constexpr int kPl1 = kF1 * kF1, kPl2 = kF2 * kF2;        // points of a plane
 constexpr size_t kFusedIn = size_t(kF0) * kF0 * kF0 * 4;  // bf16 elements
-constexpr size_t kFusedA0 = size_t(kF1) * kF1 * kF1 * 16;
-constexpr size_t kFusedA1 = size_t(kF2) * kF2 * kF2 * 16;
-constexpr size_t kFusedW = size_t(4 + 14 + 14) * 64 * 8;  // packed weights of the 3 layers
-constexpr size_t kFusedLds = 2 * (kFusedIn + kFusedA0 + kFusedA1 + kFusedW);
-// activations are stored as two planes of 8 channels (channels 0-7, then
+// a ring slot: one plane as two halves of 8 channels (channels 0-7, then
 // 8-15), 16 bytes per point: the 16 points of an MFMA column block read 256
 // contiguous bytes, free of LDS bank conflicts
-constexpr int kHalf0 = kF1 * kF1 * kF1 * 8, kHalf1 = kF2 * kF2 * kF2 * 8;
-constexpr float kCorrLimit = 0.5f;  // |correction| <= kCorrLimit * |plain increment|
-constexpr int kFusedBlock = 512, kFusedWaves = kFusedBlock / 64;
+constexpr size_t kSlot1 = size_t(2) * kPl1 * 8, kSlot2 = size_t(2) * kPl2 * 8;
+constexpr int kRing = 4;
+constexpr size_t kFusedLds = 2 * (kFusedIn + kRing * kSlot1 + kRing * kSlot2);
+constexpr int kFusedSteps = kF1 + 2;  // 14: layer 1 in steps 0-11, output in 6-13
+constexpr float kCorrLimit = 0.5f;    // |correction| <= kCorrLimit * |plain increment|
+constexpr int kFusedBlock = 256, kL1Waves = 1, kL2Waves = 2;
+constexpr int kFusedBlocksPerCu = 3;
+static_assert(kFusedBlocksPerCu * (kFusedLds + 64) <= 160 * 1024, "fused LDS per CU");
+
+// One output group of a 16-channel layer from a ring of planes: the 14
+// reduction chunks (tap 2c + (lane/16)/2, 8 channels each), chunk c's B
+// operand at byte base + off[c] + the ring slot of its tap's z offset (sb0,
+// sb1, sb2 for dz = 0, 1, 2; tap 2c + hi has dz 0 for c < 4, hi for c = 4, 1
+// for c = 5..8, 2 beyond).  Seven operand loads are kept in flight: the
+// loads of chunks 0-6 first, then each product issues the load of the chunk
+// seven later into the registers it has just read.
+__device__ inline f32x4 ring_conv16(const bf16x8 (&wa)[14], const unsigned char *base,
+                                    const int (&off)[14], int hi, int sb0, int sb1, int sb2) {
+    auto at = [&](int c) {
+        const int sb = c < 4 ? sb0 : (c == 4 ? (hi ? sb1 : sb0) : (c < 9 ? sb1 : sb2));
+        return *reinterpret_cast<const bf16x8 *>(base + off[c] + sb);
+    };
+    bf16x8 b[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) b[c] = at(c);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[c], b[c], acc, 0, 0, 0);
+        b[c] = at(c + 7);
+    }
+#pragma unroll
+    for (int c = 0; c < 7; ++c)
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[c + 7], b[c], acc, 0, 0, 0);
+    // the order above for the scheduler: seven LDS reads, then seven pairs
+    // (product, read), then seven products (masks: 0x100 LDS read, 0x8 MFMA)
+    __builtin_amdgcn_sched_group_barrier(0x100, 7, 0);
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+        __builtin_amdgcn_sched_group_barrier(0x8, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x8, 7, 0);
+    return acc;
+}
 
 __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
     ConvGeo g, const int32_t *__restrict__ tiles, const int32_t *__restrict__ ntiles_dev,
@@ -303,227 +354,261 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
     float *__restrict__ corr, float dx, int32_t *__restrict__ fallbacks) {
     extern __shared__ __align__(16) unsigned char fsm[];
     __bf16 *in = reinterpret_cast<__bf16 *>(fsm);
-    __bf16 *a0 = in + kFusedIn;
-    __bf16 *a1 = a0 + kFusedA0;
-    __bf16 *wts = a1 + kFusedA1;  // chunks 0-3 layer 1, 4-17 layer 2, 18-31 layer 3
+    __bf16 *a0 = in + kFusedIn;             // layer-1 ring
+    __bf16 *a1 = a0 + kRing * kSlot1;       // layer-2 ring
     __shared__ int bad_s;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int j = lane & 15, kq = lane >> 4;
+    const int lane = threadIdx.x & 63;
+    // wave-uniform role: 0 layer 1, 1-2 layer 2, 3 layer 3
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int j = lane & 15, kq = lane >> 4, hi = kq >> 1;
     const int n = min(*ntiles_dev, ntiles_cap);
-
-    // the packed weights of all layers, once per block
-    for (int i = threadIdx.x; i < static_cast<int>(kFusedW / 8); i += kFusedBlock) {
-        const int c = i / 64, l = i % 64;
-        const __bf16 *src = c < 4 ? wp0 + (c * 64 + l) * 8
-                                  : (c < 18 ? wp1 + ((c - 4) * 64 + l) * 8
-                                            : wp2 + ((c - 18) * 64 + l) * 8);
-        *reinterpret_cast<uint4 *>(wts + i * 8) = *reinterpret_cast<const uint4 *>(src);
-    }
 
     for (int p = blockIdx.x; p < n; p += gridDim.x) {
         const int t = tiles[p];
         if (t < 0 || t >= g.ntx * g.nty * g.ntz) continue;  // uniform
         const int ti = t % g.ntx, rr = t / g.ntx;
         const int x0 = ti * kT, y0 = (rr % g.nty) * kT, z0 = (rr / g.nty) * kT;
-        // features of the 14^3 points (zero outside the grid): every load of
-        // the thread issued first, then the conversions and LDS stores
+        // features of the 14^3 points (zero outside the grid), in NPARTS parts
+        // of the points: every load of a part issued first, then the
+        // conversions and LDS stores
         constexpr int NP0 = kF0 * kF0 * kF0;
-        constexpr int NQ = (NP0 + kFusedBlock - 1) / kFusedBlock;
-        float vph[NQ], vf[NQ], vpl[NQ];
-        bool vok[NQ];
+        constexpr int NPARTS = 2;
+        constexpr int NQ = (NP0 + NPARTS * kFusedBlock - 1) / (NPARTS * kFusedBlock);
+#pragma unroll 1
+        for (int part = 0; part < NPARTS; ++part) {
+            float vph[NQ], vf[NQ], vpl[NQ];
+            bool vok[NQ];
 #pragma unroll
-        for (int k = 0; k < NQ; ++k) {
-            const int q = threadIdx.x + k * kFusedBlock;
-            const int px = q % kF0, py = (q / kF0) % kF0, pz = q / (kF0 * kF0);
-            const int gx = x0 + px - 3, gy = y0 + py - 3, gz = z0 + pz - 3;
-            vok[k] = q < NP0 && gx >= 0 && gy >= 0 && gz >= 0 && gx < g.nx && gy < g.ny &&
-                     gz < g.nz;
-            vph[k] = vf[k] = vpl[k] = 0.f;
-            if (vok[k]) {
-                const int64_t gi = (static_cast<int64_t>(gz) * g.ny + gy) * g.nx + gx;
-                vph[k] = feat.phi[gi];
-                vf[k] = feat.F[gi];
-                vpl[k] = feat.plain[gi];
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < NQ; ++k) {
-            const int q = threadIdx.x + k * kFusedBlock;
-            if (q < NP0) {
-                float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+            for (int k = 0; k < NQ; ++k) {
+                const int q = threadIdx.x + (part * NQ + k) * kFusedBlock;
+                const int px = q % kF0, py = (q / kF0) % kF0, pz = q / (kF0 * kF0);
+                const int gx = x0 + px - 3, gy = y0 + py - 3, gz = z0 + pz - 3;
+                vok[k] = q < NP0 && gx >= 0 && gy >= 0 && gz >= 0 && gx < g.nx && gy < g.ny &&
+                         gz < g.nz;
+                vph[k] = vf[k] = vpl[k] = 0.f;
                 if (vok[k]) {
-                    v0 = fminf(fmaxf(vph[k] * feat.inv_gamma, -2.f), 2.f);
-                    v1 = vf[k] * feat.inv_fmax;
-                    v2 = (vpl[k] - vph[k]) * feat.inv_dx;
+                    const int64_t gi = (static_cast<int64_t>(gz) * g.ny + gy) * g.nx + gx;
+                    vph[k] = feat.phi[gi];
+                    vf[k] = feat.F[gi];
+                    vpl[k] = feat.plain[gi];
                 }
-                __bf16 d[4] = {to_bf16(v0), to_bf16(v1), to_bf16(v2), to_bf16(0.f)};
-                *reinterpret_cast<uint2 *>(in + q * 4) = *reinterpret_cast<const uint2 *>(d);
+            }
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) {
+                const int q = threadIdx.x + (part * NQ + k) * kFusedBlock;
+                if (q < NP0) {
+                    float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+                    if (vok[k]) {
+                        v0 = fminf(fmaxf(vph[k] * feat.inv_gamma, -2.f), 2.f);
+                        v1 = vf[k] * feat.inv_fmax;
+                        v2 = (vpl[k] - vph[k]) * feat.inv_dx;
+                    }
+                    __bf16 d[4] = {to_bf16(v0), to_bf16(v1), to_bf16(v2), to_bf16(0.f)};
+                    *reinterpret_cast<uint2 *>(in + q * 4) = *reinterpret_cast<const uint2 *>(d);
+                }
             }
         }
         if (threadIdx.x == 0) bad_s = 0;
         __syncthreads();
-
-        // layer 1: 12^3 outputs, 108 groups of 16.  Per lane, the LDS offset of
-        // each tap it feeds is fixed (tap = 8c + 2(lane/16) + h): precomputed.
-        {
-            bf16x8 wa[4];
-            int off[4][2];
+        // the role's weights (A operands, from L2 after the first tile) and
+        // per-chunk LDS offsets; loaded after the features' barrier, so that
+        // they take no registers during the feature loads.  The lane index is
+        // made opaque here so that the compiler keeps these address
+        // computations in the loop instead of holding them in registers
+        // across the whole kernel.
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        const int lkq = ln >> 4, lhi = lkq >> 1;
+        bf16x8 wa[14];
+        int off[14];
+        float bb[4];
+        float b2 = 0.f;
+        if (wave < kL1Waves) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                wa[c] = *reinterpret_cast<const bf16x8 *>(wts + (c * 64 + lane) * 8);
+            for (int c = 0; c < 14; ++c) {
+                wa[c] = c < 4 ? *reinterpret_cast<const bf16x8 *>(wp0 + (c * 64 + ln) * 8)
+                              : bf16x8{};
+                off[c] = 0;
+            }
+            // layer 1: the lane's two taps 8c + 2(lane/16) + h of chunk c, 4 input
+            // channels each; taps past the 27th have zero weights: any point reads
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const int tap = 8 * c + 2 * kq + h;
-                    // taps past the 27th have zero weights: any point reads as well
-                    off[c][h] = tap < kTaps
-                                    ? ((tap / 9) * kF0 + (tap / 3) % 3) * kF0 + tap % 3
-                                    : 0;
+                    const int tap = 8 * c + 2 * lkq + h;
+                    off[2 * c + h] = tap < kTaps
+                                         ? (((tap / 9) * kF0 + (tap / 3) % 3) * kF0 + tap % 3) * 8
+                                         : 0;  // bytes
                 }
-            }
-            float bb[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) bb[i] = params[kB0 + 4 * kq + i];
-            for (int grp = wave; grp < (kF1 * kF1 * kF1) / 16; grp += kFusedWaves) {
-                const int pt = grp * 16 + j;
-                const int lx = pt % kF1, ly = (pt / kF1) % kF1, lz = pt / (kF1 * kF1);
-                const int q0 = (lz * kF0 + ly) * kF0 + lx;
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    uint2 v[2];
-#pragma unroll
-                    for (int h = 0; h < 2; ++h)
-                        v[h] = *reinterpret_cast<const uint2 *>(in + (q0 + off[c][h]) * 4);
-                    const bf16x8 b =
-                        __builtin_bit_cast(bf16x8, make_uint4(v[0].x, v[0].y, v[1].x, v[1].y));
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[c], b, acc, 0, 0, 0);
-                }
-                const int gx = x0 + lx - 2, gy = y0 + ly - 2, gz = z0 + lz - 2;
-                const bool inside = gx >= 0 && gy >= 0 && gz >= 0 && gx < g.nx && gy < g.ny &&
-                                    gz < g.nz;
-                __bf16 ab[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) ab[i] = to_bf16(inside ? silu_f(acc[i] + bb[i]) : 0.f);
-                *reinterpret_cast<uint2 *>(a0 + (kq >> 1) * kHalf0 + pt * 8 + 4 * (kq & 1)) =
-                    *reinterpret_cast<uint2 *>(ab);
-            }
-        }
-        __syncthreads();
-
-        // layer 2: 10^3 outputs, 63 groups of 16 (the last one partial);
-        // tap = 2c + (lane/16)/2, channels 8 ((lane/16) & 1) .. +7
-        {
-            bf16x8 wa[14];
-            int off[14];
+            for (int i = 0; i < 4; ++i) bb[i] = params[kB0 + 4 * lkq + i];
+        } else {
+            const bool l2 = wave < kL1Waves + kL2Waves;
+            const __bf16 *wp = l2 ? wp1 : wp2;
+            const int pw = l2 ? kF1 : kF2;                       // input plane width
+            const int half = (lkq & 1) * (l2 ? kPl1 : kPl2) * 8;  // channel half
 #pragma unroll
             for (int c = 0; c < 14; ++c) {
-                wa[c] = *reinterpret_cast<const bf16x8 *>(wts + ((4 + c) * 64 + lane) * 8);
-                const int tap = 2 * c + (kq >> 1);
-                off[c] = (tap < kTaps ? (((tap / 9) * kF1 + (tap / 3) % 3) * kF1 + tap % 3) * 8
-                                      : 0) +
-                         (kq & 1) * kHalf0;  // taps past the 27th: zero weights
+                wa[c] = *reinterpret_cast<const bf16x8 *>(wp + (c * 64 + ln) * 8);
+                // tap 2c + (lane/16)/2, in-plane part; the z part picks the slot
+                const int tap = min(2 * c + lhi, kTaps - 1);  // tap 27: zero weights
+                off[c] = ((((tap / 3) % 3) * pw + tap % 3) * 8 + half) * 2;  // bytes
             }
-            float bb[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) bb[i] = params[kB1 + 4 * kq + i];
-            constexpr int NP = kF2 * kF2 * kF2;
-            for (int grp = wave; grp < (NP + 15) / 16; grp += kFusedWaves) {
-                const int pt = grp * 16 + j;
-                const int ptc = min(pt, NP - 1);  // lanes past the end compute a copy
-                const int lx = ptc % kF2, ly = (ptc / kF2) % kF2, lz = ptc / (kF2 * kF2);
-                const int q0 = ((lz * kF1 + ly) * kF1 + lx) * 8;
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int c = 0; c < 14; ++c) {
-                    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(a0 + q0 + off[c]);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[c], b, acc, 0, 0, 0);
-                }
-                const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z0 + lz - 1;
-                const bool inside = gx >= 0 && gy >= 0 && gz >= 0 && gx < g.nx && gy < g.ny &&
-                                    gz < g.nz;
-                __bf16 ab[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) ab[i] = to_bf16(inside ? silu_f(acc[i] + bb[i]) : 0.f);
-                if (pt < NP)
-                    *reinterpret_cast<uint2 *>(a1 + (kq >> 1) * kHalf1 + pt * 8 + 4 * (kq & 1)) =
-                        *reinterpret_cast<uint2 *>(ab);
-            }
+            for (int i = 0; i < 4; ++i) bb[i] = l2 ? params[kB1 + 4 * lkq + i] : 0.f;
+            b2 = params[kB2];
         }
-        __syncthreads();
 
-        // layer 3 on the tile: r, the gated correction and the fallback test
-        constexpr int NG3 = 512 / 16 / kFusedWaves;  // layer-3 groups per wave
-        float rv[NG3];
-        {
-            bf16x8 wa[14];
-            int off[14];
+        float cph[4] = {0.f, 0.f, 0.f, 0.f}, cpl[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int s = 0; s < kFusedSteps; ++s) {
+            if (wave < kL1Waves) {
+                if (s < kF1) {
+                    // layer-1 plane s (z offset s - 2): 144 points, 9 groups
+                    const int lz = s;
+                    __bf16 *dst = a0 + (s % kRing) * kSlot1 + hi * kPl1 * 8 + 4 * (kq & 1);
+#pragma unroll 1
+                    for (int grp = wave; grp < kPl1 / 16; grp += kL1Waves) {
+                        const int pt = grp * 16 + j;
+                        const int lx = pt % kF1, ly = pt / kF1;
+                        const unsigned char *src = reinterpret_cast<const unsigned char *>(in) +
+                                                   ((lz * kF0 + ly) * kF0 + lx) * 8;
+                        // all eight operand loads first, then the four products
+                        uint2 v[8];
 #pragma unroll
-            for (int c = 0; c < 14; ++c) {
-                wa[c] = *reinterpret_cast<const bf16x8 *>(wts + ((18 + c) * 64 + lane) * 8);
-                const int tap = 2 * c + (kq >> 1);
-                off[c] = (tap < kTaps ? (((tap / 9) * kF2 + (tap / 3) % 3) * kF2 + tap % 3) * 8
-                                      : 0) +
-                         (kq & 1) * kHalf1;  // taps past the 27th: zero weights
-            }
-            const float b2 = params[kB2];
-            // phi and the plain step on the lane's points, for the gate and the limiter
-            float gph[NG3], gpl[NG3];
+                        for (int k = 0; k < 8; ++k)
+                            v[k] = *reinterpret_cast<const uint2 *>(src + off[k]);
+                        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int gi8 = 0; gi8 < NG3; ++gi8) {
-                const int pt = (wave + kFusedWaves * gi8) * 16 + j;
-                const int64_t gpt = (static_cast<int64_t>(z0 + (pt >> 6)) * g.ny +
-                                     (y0 + ((pt >> 3) & 7))) * g.nx + (x0 + (pt & 7));
-                gph[gi8] = gpl[gi8] = 0.f;
-                if (kq == 0) {
-                    gph[gi8] = feat.phi[gpt];
-                    gpl[gi8] = feat.plain[gpt];
+                        for (int c = 0; c < 4; ++c) {
+                            const bf16x8 b = __builtin_bit_cast(
+                                bf16x8, make_uint4(v[2 * c].x, v[2 * c].y, v[2 * c + 1].x,
+                                                   v[2 * c + 1].y));
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[c], b, acc, 0, 0, 0);
+                        }
+                        __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);  // LDS reads
+                        __builtin_amdgcn_sched_group_barrier(0x8, 4, 0);    // products
+                        const int gx = x0 + lx - 2, gy = y0 + ly - 2, gz = z0 + lz - 2;
+                        const bool inside = gx >= 0 && gy >= 0 && gz >= 0 && gx < g.nx &&
+                                            gy < g.ny && gz < g.nz;
+                        __bf16 ab[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const float a = silu_f(acc[i] + bb[i]);  // finite: no branch
+                            ab[i] = to_bf16(inside ? a : 0.f);
+                        }
+                        *reinterpret_cast<uint2 *>(dst + pt * 8) = *reinterpret_cast<uint2 *>(ab);
+                    }
+                }
+            } else if (wave < kL1Waves + kL2Waves) {
+                const int b = s - 3;
+                if (b >= 0 && b < kF2) {
+                    // layer-2 plane b (z offset b - 1) from layer-1 planes b..b+2:
+                    // 100 points, 7 groups (the last one partial), alternating
+                    // between the layer's waves
+                    // ring slots in bytes
+                    const int sb0 = (b % kRing) * kSlot1 * 2, sb1 = ((b + 1) % kRing) * kSlot1 * 2,
+                              sb2 = ((b + 2) % kRing) * kSlot1 * 2;
+__bf16 *dst = a1 + (b % kRing) * kSlot2 + hi * kPl2 * 8 + 4 * (kq & 1);
+#pragma unroll 1
+                    for (int grp = wave - kL1Waves; grp < (kPl2 + 15) / 16; grp += kL2Waves) {
+                        const int pt = grp * 16 + j;
+                        const int ptc = min(pt, kPl2 - 1);  // lanes past the end compute a copy
+                        const int lx = ptc % kF2, ly = ptc / kF2;
+                        const f32x4 acc = ring_conv16(
+                            wa, reinterpret_cast<const unsigned char *>(a0) + (ly * kF1 + lx) * 16,
+                            off, hi, sb0, sb1, sb2);
+                        const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z0 + b - 1;
+                        const bool inside = gx >= 0 && gy >= 0 && gz >= 0 && gx < g.nx &&
+                                            gy < g.ny && gz < g.nz;
+                        __bf16 ab[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const float a = silu_f(acc[i] + bb[i]);  // finite: no branch
+                            ab[i] = to_bf16(inside ? a : 0.f);
+                        }
+                        if (pt < kPl2)
+                            *reinterpret_cast<uint2 *>(dst + pt * 8) =
+                                *reinterpret_cast<uint2 *>(ab);
+                    }
+                }
+            } else {
+                const int lz = s - 6;
+                // phi and the plain step of plane lz + 1 (gate and limiter),
+                // issued now and used in the next step
+                float nph[4] = {0.f, 0.f, 0.f, 0.f}, npl[4] = {0.f, 0.f, 0.f, 0.f};
+                if (kq == 0 && lz + 1 >= 0 && lz + 1 < kT) {
+#pragma unroll
+                    for (int grp = 0; grp < 4; ++grp) {
+                        const int pt = grp * 16 + j;
+                        const int64_t gpt = (static_cast<int64_t>(z0 + lz + 1) * g.ny +
+                                             (y0 + (pt >> 3))) * g.nx + (x0 + (pt & 7));
+                        nph[grp] = feat.phi[gpt];
+                        npl[grp] = feat.plain[gpt];
+                    }
+                }
+                if (lz >= 0 && lz < kT) {
+                    // output plane lz from layer-2 planes lz..lz+2: r, the gated
+                    // correction and the fallback test on 64 points, 4 groups
+                    // ring slots in bytes
+                    const int sb0 = (lz % kRing) * kSlot2 * 2,
+                              sb1 = ((lz + 1) % kRing) * kSlot2 * 2,
+                              sb2 = ((lz + 2) % kRing) * kSlot2 * 2;
+#pragma unroll 1
+                    for (int grp = 0; grp < 4; ++grp) {
+                        const int pt = grp * 16 + j;
+                        const int lx = pt & 7, ly = pt >> 3;
+                        int q0 = (ly * kF2 + lx) * 16;
+                        // opaque: keeps the chunk addresses from being hoisted out
+                        // of the loops into registers
+                        asm volatile("" : "+v"(q0));
+                        const f32x4 acc = ring_conv16(
+                            wa, reinterpret_cast<const unsigned char *>(a1) + q0, off, hi, sb0,
+                            sb1, sb2);
+                        if (kq == 0) {
+                            const int64_t gpt = (static_cast<int64_t>(z0 + lz) * g.ny +
+                                                 (y0 + ly)) * g.nx + (x0 + lx);
+                            const float ph = cph[0];
+                            float r = acc[0] + b2;
+                            if (rout) rout[gpt] = r;
+                            r *= cutoff_f(ph, feat.inv_gamma);
+                            if (!(fabsf(r) <= 0.5f)) atomicOr(&bad_s, 1);  // NaN fails too
+                            // limiter: the correction changes the plain increment
+                            // by at most half of it, so it never reverses or
+                            // stalls the plain step
+                            const float lim = kCorrLimit * fabsf(cpl[0] - ph);
+                            if (corr) corr[gpt] = fminf(fmaxf(dx * r, -lim), lim);
+                        }
+                        // the next group's values to the front (static indices)
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) {
+                            cph[i] = cph[i + 1];
+                            cpl[i] = cpl[i + 1];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    cph[i] = nph[i];
+                    cpl[i] = npl[i];
                 }
             }
-#pragma unroll
-            for (int gi8 = 0; gi8 < NG3; ++gi8) {
-                const int pt = (wave + kFusedWaves * gi8) * 16 + j;
-                const int lx = pt & 7, ly = (pt >> 3) & 7, lz = pt >> 6;
-                const int q0 = ((lz * kF2 + ly) * kF2 + lx) * 8;
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int c = 0; c < 14; ++c) {
-                    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(a1 + q0 + off[c]);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[c], b, acc, 0, 0, 0);
+            __syncthreads();
+        }
+        // a tile that fails the test falls back to the plain step: its
+        // corrections (added to the plain step by a later kernel, since
+        // other blocks still read the plain step around their tiles) are zero
+        if (bad_s != 0) {
+            if (corr) {
+                for (int pt = threadIdx.x; pt < kT * kT * kT; pt += kFusedBlock) {
+                    const int64_t gpt = (static_cast<int64_t>(z0 + (pt >> 6)) * g.ny +
+                                         (y0 + ((pt >> 3) & 7))) * g.nx + (x0 + (pt & 7));
+                    corr[gpt] = 0.f;
                 }
-                rv[gi8] = acc[0] + b2;
-                if (kq == 0) {
-                    const int64_t gpt =
-                        (static_cast<int64_t>(z0 + lz) * g.ny + (y0 + ly)) * g.nx + (x0 + lx);
-                    if (rout) rout[gpt] = rv[gi8];
-                    const float ph = gph[gi8];
-                    rv[gi8] *= cutoff_f(ph, feat.inv_gamma);
-                    if (!(fabsf(rv[gi8]) <= 0.5f)) atomicOr(&bad_s, 1);  // NaN fails too
-                    // limiter: the correction changes the plain increment by at
-                    // most half of it, so it never reverses or stalls the plain step
-                    const float lim = kCorrLimit * fabsf(gpl[gi8] - ph);
-                    rv[gi8] = fminf(fmaxf(dx * rv[gi8], -lim), lim);
-                }
+                if (threadIdx.x == 0 && fallbacks) atomicAdd(fallbacks, 1);
             }
         }
-        __syncthreads();
-        if (corr) {
-            // the correction of the tile (zero when it falls back), added to
-            // the plain step by a later kernel: other blocks still read the
-            // plain step around their tiles
-            const bool ok = bad_s == 0;
-            if (kq == 0) {
-#pragma unroll
-                for (int gi8 = 0; gi8 < NG3; ++gi8) {
-                    const int pt = (wave + kFusedWaves * gi8) * 16 + j;
-                    const int lx = pt & 7, ly = (pt >> 3) & 7, lz = pt >> 6;
-                    const int64_t gpt =
-                        (static_cast<int64_t>(z0 + lz) * g.ny + (y0 + ly)) * g.nx + (x0 + lx);
-                    corr[gpt] = ok ? rv[gi8] : 0.f;
-                }
-            }
-            if (!ok && threadIdx.x == 0 && fallbacks) atomicAdd(fallbacks, 1);
-        }
-        __syncthreads();  // LDS free for the next tile
+        __syncthreads();  // LDS and bad_s free for the next tile
     }
 }
 
@@ -995,8 +1080,8 @@ static int closure_fused(const ClosureCall &c, const float *phi, const float *F,
     DeviceInfo di;
     int rc = device_info(&di);
     if (rc != LS_OK) return rc;
-    const unsigned blocks =
-        static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(c.G.ntiles, di.cus)));
+    const unsigned blocks = static_cast<unsigned>(std::max<int64_t>(
+        1, std::min<int64_t>(c.G.ntiles, int64_t(di.cus) * kFusedBlocksPerCu)));
     In4 feat{phi, F, plain, nullptr, 1.0f / gamma, 1.0f / fmax, 1.0f / dx};
     // with `apply` the corrections go to the workspace's r field first
     float *corr = apply ? at<float>(c, c.w.r) : nullptr;
