@@ -13,6 +13,7 @@ import argparse
 import collections
 import json
 import os
+import re
 import sqlite3
 import sys
 
@@ -53,10 +54,12 @@ def kernel_counters(db):
 
 
 def _mean_over(counters, prefix, name):
-    """Dispatch-weighted mean of counter `name` over the kernels starting with prefix."""
+    """Dispatch-weighted mean of counter `name` over the kernels whose names
+    match the regular expression `prefix` at their start (a plain name
+    prefix is such an expression)."""
     n = tot = 0.0
     for (k, c), (d, v) in counters.items():
-        if c == name and k.startswith(prefix):
+        if c == name and re.match(prefix, k):
             n += d
             tot += d * v
     if n == 0:
@@ -78,8 +81,8 @@ def _calibration(db, counter):
 
 
 def traffic(fetch_db, write_db, prefix):
-    """HBM bytes per dispatch of the kernels starting with `prefix` (all their
-    variants together), calibrated by the copy kernel."""
+    """HBM bytes per dispatch of the kernels matching `prefix` at the start of
+    their names (all their variants together), calibrated by the copy kernel."""
     f = kernel_counters(fetch_db)
     w = kernel_counters(write_db)
     f_cal = _calibration(fetch_db, "FETCH_SIZE") * 1024.0
@@ -102,7 +105,8 @@ def main(argv=None):
     tr = sub.add_parser("traffic")
     tr.add_argument("fetch_db")
     tr.add_argument("write_db")
-    tr.add_argument("--kernel", required=True, help="kernel name prefix")
+    tr.add_argument("--kernel", required=True,
+                    help="kernel name prefix (a regular expression matched at the start)")
     tr.add_argument("--key", required=True, help="kernel/workload key in traffic.json")
     tr.add_argument("--digest", required=True, help="kernel source digest of the run")
     tr.add_argument("--out", default=os.path.join(os.path.dirname(os.path.dirname(
@@ -118,7 +122,7 @@ def main(argv=None):
                 print(f"{k[:100]:100s} {cn:20s} dispatches={n:6d} mean={v:16.1f}")
     else:
         names = {k for k, _ in kernel_counters(a.fetch_db)}
-        match = sorted(n for n in names if n.startswith(a.kernel))
+        match = sorted(n for n in names if re.match(a.kernel, n))
         if not match:
             print(f"no kernel starting with {a.kernel}", file=sys.stderr)
             return 1
