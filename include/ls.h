@@ -398,6 +398,13 @@ int ls_band_gather_f16s(const uint16_t *phi_h, const ls_grid *g, const int32_t *
  * pointers, unit_bytes <= 0, max_units outside [0, 2^31), blocks < 0. */
 int ls_copy_counted(void *dst, const void *src, const int32_t *count_dev, int64_t unit_bytes,
                     int64_t max_units, int32_t *count_out, int blocks, void *stream);
+/* The same for units [first_unit, n) only (dst and src still point at unit 0;
+ * nothing is copied when n <= first_unit; count_out still receives n): the
+ * tail beyond what a copy of a host-known size already moved.  Errors as
+ * above, and first_unit outside [0, max_units]. */
+int ls_copy_counted_from(void *dst, const void *src, const int32_t *count_dev,
+                         int64_t unit_bytes, int64_t first_unit, int64_t max_units,
+                         int32_t *count_out, int blocks, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Batches: many grids of uneven size, advanced in lockstep by the same

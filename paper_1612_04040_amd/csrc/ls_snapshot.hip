@@ -187,9 +187,9 @@ static int band_gather(const S *phi, const ls_grid *grid, const int32_t *tiles,
     return stats_after(LS_KERNEL_GATHER, stream, slot);
 }
 
-// Counted copy: n = min(max(*count, 0), max_units) units of `unit` bytes,
-// moved as elements of type T (the widest width that divides the unit and
-// both addresses), grid-stride; block 0's first thread stores n to
+// Counted copy: units [first, n) of `unit` bytes, n = min(max(*count, 0),
+// max_units), moved as elements of type T (the widest width that divides the
+// unit and both addresses), grid-stride; block 0's first thread stores n to
 // *count_out when it is non-NULL.  The count is read on the device, so a copy
 // of exactly the units a preceding kernel produced is enqueued without the
 // host waiting for that kernel.
@@ -197,23 +197,33 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void copy_counted_kernel(T *__restrict__ dst,
                                                               const T *__restrict__ src,
                                                               const int32_t *__restrict__ count,
-                                                              int64_t per_unit, int64_t max_units,
+                                                              int64_t per_unit, int64_t first,
+                                                              int64_t max_units,
                                                               int32_t *__restrict__ count_out) {
     const int64_t n = min(static_cast<int64_t>(max(*count, 0)), max_units);
     if (count_out && blockIdx.x == 0 && threadIdx.x == 0) *count_out = static_cast<int32_t>(n);
     const int64_t total = n * per_unit;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < total;
-         i += static_cast<int64_t>(gridDim.x) * kBlock)
-        dst[i] = src[i];
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    int64_t i = first * per_unit + static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    // four elements per thread and pass, all loads before the stores, so that
+    // more writes to the destination (host memory over the link) are in flight
+    for (; i + 3 * stride < total; i += 4 * stride) {
+        T v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = src[i + k * stride];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dst[i + k * stride] = v[k];
+    }
+    for (; i < total; i += stride) dst[i] = src[i];
 }
 
 template <class T>
 static int copy_counted(void *dst, const void *src, const int32_t *count, int64_t unit_bytes,
-                        int64_t max_units, int32_t *count_out, unsigned blocks,
+                        int64_t first, int64_t max_units, int32_t *count_out, unsigned blocks,
                         hipStream_t stream) {
     const int64_t per_unit = unit_bytes / static_cast<int64_t>(sizeof(T));
     hipLaunchKernelGGL((copy_counted_kernel<T>), dim3(blocks), dim3(kBlock), 0, stream,
-                       static_cast<T *>(dst), static_cast<const T *>(src), count, per_unit,
+                       static_cast<T *>(dst), static_cast<const T *>(src), count, per_unit, first,
                        max_units, count_out);
     LS_LAUNCH_CHECK("copy_counted_kernel");
     return LS_OK;
@@ -223,16 +233,19 @@ static int copy_counted(void *dst, const void *src, const int32_t *count, int64_
 
 extern "C" {
 
-int ls_copy_counted(void *dst, const void *src, const int32_t *count_dev, int64_t unit_bytes,
-                    int64_t max_units, int32_t *count_out, int blocks, void *stream) {
+int ls_copy_counted_from(void *dst, const void *src, const int32_t *count_dev,
+                         int64_t unit_bytes, int64_t first_unit, int64_t max_units,
+                         int32_t *count_out, int blocks, void *stream) {
     ls::clear_error();
     if (!dst || !src || !count_dev) {
         ls::set_error("copy_counted: dst, src and count_dev must be non-NULL");
         return LS_ERR_ARG;
     }
-    if (unit_bytes <= 0 || max_units < 0 || max_units > INT32_MAX || blocks < 0) {
-        ls::set_error("copy_counted: unit_bytes must be > 0, max_units in [0, 2^31), blocks >= 0 "
-                      "(got %lld, %lld, %d)", (long long)unit_bytes, (long long)max_units, blocks);
+    if (unit_bytes <= 0 || max_units < 0 || max_units > INT32_MAX || blocks < 0 ||
+        first_unit < 0 || first_unit > max_units) {
+        ls::set_error("copy_counted: unit_bytes must be > 0, max_units in [0, 2^31), first_unit "
+                      "in [0, max_units], blocks >= 0 (got %lld, %lld, %lld, %d)",
+                      (long long)unit_bytes, (long long)max_units, (long long)first_unit, blocks);
         return LS_ERR_ARG;
     }
     if (max_units > INT64_MAX / unit_bytes) {
@@ -247,21 +260,33 @@ int ls_copy_counted(void *dst, const void *src, const int32_t *count_dev, int64_
         if (rc != LS_OK) return rc;
         nb = static_cast<unsigned>(di.cus) / 4;
     }
-    const int64_t bytes = unit_bytes * max_units;
+    const int64_t bytes = unit_bytes * (max_units - first_unit);
     nb = static_cast<unsigned>(
         std::max<int64_t>(1, std::min<int64_t>(nb, ls::cdiv64(bytes, 16 * ls::kBlock))));
     const uintptr_t align = reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src) |
                             static_cast<uintptr_t>(unit_bytes);
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    if (align % 16 == 0) return ls::copy_counted<uint4>(dst, src, count_dev, unit_bytes, max_units,
-                                                        count_out, nb, s);
-    if (align % 8 == 0) return ls::copy_counted<uint2>(dst, src, count_dev, unit_bytes, max_units,
-                                                       count_out, nb, s);
-    if (align % 4 == 0) return ls::copy_counted<uint32_t>(dst, src, count_dev, unit_bytes,
-                                                          max_units, count_out, nb, s);
-    if (align % 2 == 0) return ls::copy_counted<uint16_t>(dst, src, count_dev, unit_bytes,
-                                                          max_units, count_out, nb, s);
-    return ls::copy_counted<uint8_t>(dst, src, count_dev, unit_bytes, max_units, count_out, nb, s);
+    const int64_t f = first_unit;
+    if (align % 16 == 0)
+        return ls::copy_counted<uint4>(dst, src, count_dev, unit_bytes, f, max_units, count_out,
+                                       nb, s);
+    if (align % 8 == 0)
+        return ls::copy_counted<uint2>(dst, src, count_dev, unit_bytes, f, max_units, count_out,
+                                       nb, s);
+    if (align % 4 == 0)
+        return ls::copy_counted<uint32_t>(dst, src, count_dev, unit_bytes, f, max_units,
+                                          count_out, nb, s);
+    if (align % 2 == 0)
+        return ls::copy_counted<uint16_t>(dst, src, count_dev, unit_bytes, f, max_units,
+                                          count_out, nb, s);
+    return ls::copy_counted<uint8_t>(dst, src, count_dev, unit_bytes, f, max_units, count_out, nb,
+                                     s);
+}
+
+int ls_copy_counted(void *dst, const void *src, const int32_t *count_dev, int64_t unit_bytes,
+                    int64_t max_units, int32_t *count_out, int blocks, void *stream) {
+    return ls_copy_counted_from(dst, src, count_dev, unit_bytes, 0, max_units, count_out, blocks,
+                                stream);
 }
 
 int ls_band_gather_f32(const float *phi, const ls_grid *g, const int32_t *tiles,

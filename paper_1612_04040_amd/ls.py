@@ -149,6 +149,7 @@ _SIGNATURES = {
     "ls_stats_enable": (_I32, [_I32]),
     "ls_copy_f32": (_I32, [_VP, _VP, _I64, _VP]),
     "ls_copy_counted": (_I32, [_VP, _VP, _VP, _I64, _I64, _VP, _I32, _VP]),
+    "ls_copy_counted_from": (_I32, [_VP, _VP, _VP, _I64, _I64, _I64, _VP, _I32, _VP]),
     "ls_stats_read": (_I32, [_I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                              ctypes.POINTER(_F64)]),
     "ls_autotune": (_I32, [_VP, _I32, _I32, ctypes.c_char_p, _VP, _I32]),
@@ -519,6 +520,13 @@ def ls_copy_counted(dst, src, count_dev, unit_bytes, max_units, count_out=None, 
     return _check(lib().ls_copy_counted(_ptr(dst), _ptr(src), _ptr(count_dev), int(unit_bytes),
                                         int(max_units), _ptr(count_out), int(blocks),
                                         _stream(stream)))
+
+
+def ls_copy_counted_from(dst, src, count_dev, unit_bytes, first_unit, max_units, count_out=None,
+                         blocks=0, stream=None):
+    return _check(lib().ls_copy_counted_from(_ptr(dst), _ptr(src), _ptr(count_dev),
+                                             int(unit_bytes), int(first_unit), int(max_units),
+                                             _ptr(count_out), int(blocks), _stream(stream)))
 
 
 def ls_stats_enable(on):

@@ -4,10 +4,14 @@ The output of the narrow-band algorithm (Sec. 1.1, Step 4) taken off the GPU
 while it keeps computing: ``take`` enqueues, on the compute stream, the band
 gather (``ls_band_gather_*``: the band tiles' values, tile-major, and their
 ids) into one of two device staging buffers plus a device copy of the band
-count, then, on a separate copy stream that waits for the gather, the
-library's counted copy (``ls_copy_counted``) of exactly that many tiles and
-ids into pinned host memory, the count read on the device.  The host never
-waits: ``take`` returns as soon as the work is enqueued, and the caller
+count, then, on a separate copy stream that waits for the gather, the copy of
+the tiles and ids into pinned host memory: a DMA copy of a size the host knows
+(the band count of the last snapshot the host has read, with a margin of
+1/8 + 64 tiles), then the library's counted copy (``ls_copy_counted_from``)
+of the tiles beyond it, if any, the count read on the device (the first
+snapshot, with no count known yet, goes by the counted copy alone unless the
+caller gave an estimate).  The host
+never waits: ``take`` returns as soon as the work is enqueued, and the caller
 enqueues the next windows while the copy runs.  Gather k + 2 reuses the
 staging buffer of snapshot k and waits, on the GPU, for that buffer's copy to
 finish; the host buffer of snapshot k is reused by snapshot k + 2, so a
@@ -49,9 +53,11 @@ class Snapshots:
     its first capacity tiles); two device staging buffers and two pinned host
     buffers of that size are allocated up front.  copy_blocks: workgroups of
     each counted copy (0: the library's default, a quarter of the compute
-    units)."""
+    units).  expected: an estimate of the band count (tiles), taken as the
+    host-known count until a snapshot has been read (None: the first
+    snapshots go by the counted copy alone)."""
 
-    def __init__(self, bg, capacity=None, copy_blocks=0):
+    def __init__(self, bg, capacity=None, copy_blocks=0, expected=None):
         self.bg = bg
         dev = bg.tiles.device
         self.tile = bg.tile
@@ -71,6 +77,8 @@ class Snapshots:
         self.consumed = [True, True]
         self.taken = 0
         self.copy_blocks = int(copy_blocks)
+        # band count of the last snapshot read on the host
+        self.known = None if expected is None else int(expected)
         self.closed = False
 
     def take(self, phi, stream=None):
@@ -91,11 +99,18 @@ class Snapshots:
         self.gathered[i].record(s)
         self.copy_stream.wait_event(self.gathered[i])
         esize = self.stage[i].element_size()
-        ls.ls_copy_counted(self.host[i], self.stage[i], self.stage_count[i], self.tp * esize,
-                           self.cap, count_out=self.count[i:i + 1], blocks=self.copy_blocks,
-                           stream=self.copy_stream)
-        ls.ls_copy_counted(self.host_ids[i], self.stage_ids[i], self.stage_count[i], 4, self.cap,
-                           blocks=self.copy_blocks, stream=self.copy_stream)
+        # tiles moved by DMA: a host-known bound on the count; the counted
+        # copy takes whatever lies beyond it
+        b = 0 if self.known is None else min(self.cap, self.known + self.known // 8 + 64)
+        if b > 0:
+            with torch.cuda.stream(self.copy_stream):
+                self.host[i][: b * self.tp].copy_(self.stage[i][: b * self.tp], non_blocking=True)
+                self.host_ids[i][:b].copy_(self.stage_ids[i][:b], non_blocking=True)
+        ls.ls_copy_counted_from(self.host[i], self.stage[i], self.stage_count[i],
+                                self.tp * esize, b, self.cap, count_out=self.count[i:i + 1],
+                                blocks=self.copy_blocks, stream=self.copy_stream)
+        ls.ls_copy_counted_from(self.host_ids[i], self.stage_ids[i], self.stage_count[i], 4, b,
+                                self.cap, blocks=self.copy_blocks, stream=self.copy_stream)
         self.copied[i].record(self.copy_stream)
         self.serial[i] = self.taken
         self.consumed[i] = False
@@ -108,6 +123,7 @@ class Snapshots:
             raise RuntimeError("snapshot overwritten before it was read")
         self.copied[i].synchronize()
         n = min(int(self.count[i]), self.cap)
+        self.known = n
         ids = self.host_ids[i][:n].numpy()
         vals = self.host[i][: n * self.tp].numpy()
         tx, ty, tz = self.tile

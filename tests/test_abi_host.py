@@ -361,6 +361,16 @@ def test_copy_counted_errors():
         assert _status(ls.ls_copy_counted, *a.values()) == ls.LS_ERR_ARG, over
 
 
+def test_copy_counted_from_errors():
+    ok = dict(dst=FAKE, src=FAKE, count_dev=FAKE, unit_bytes=16, first_unit=0, max_units=4,
+              count_out=None, blocks=1, stream=0)
+    for over in (dict(dst=None), dict(src=None), dict(count_dev=None), dict(unit_bytes=0),
+                 dict(max_units=-1), dict(max_units=1 << 31), dict(blocks=-1),
+                 dict(first_unit=-1), dict(first_unit=5), dict(unit_bytes=1 << 40, max_units=1 << 30)):
+        a = dict(ok, **over)
+        assert _status(ls.ls_copy_counted_from, *a.values()) == ls.LS_ERR_ARG, over
+
+
 def test_band_build_noalloc_errors():
     """The allocation-free build rejects bad arguments and grids whose
     workspace exceeds its fixed array, before touching a device."""

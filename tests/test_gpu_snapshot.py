@@ -116,6 +116,50 @@ def test_counted_copy_moves_exactly_the_counted_units(unit_bytes):
             assert int(out.cpu()[0]) == want
 
 
+@pytest.mark.parametrize("unit_bytes,first", [(80, 0), (80, 5), (12, 3), (3, 1000), (80, 13107)])
+def test_counted_copy_from_moves_the_tail(unit_bytes, first):
+    """ls_copy_counted_from: units [first, n) only, n = min(max(count, 0),
+    max_units) stored to count_out; units below first and beyond n are not
+    written.  1 MiB with one workgroup runs the four-per-thread loop."""
+    nbytes = 1 << 20
+    src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device=dev())
+    maxu = nbytes // unit_bytes
+    first = min(first, maxu)
+    for count in (maxu - 7, first + 1, first, first - 1, maxu + 9):
+        want = max(0, min(count, maxu))
+        cnt = torch.tensor([count], dtype=torch.int32, device=dev())
+        dst = torch.full((nbytes,), 0xA5, dtype=torch.uint8).pin_memory()
+        out = torch.full((1,), -9, dtype=torch.int32).pin_memory()
+        ls.ls_copy_counted_from(dst, src, cnt, unit_bytes, first, maxu, count_out=out, blocks=1)
+        torch.cuda.synchronize()
+        d, s_ = dst.numpy(), src.cpu().numpy()
+        lo, hi = first * unit_bytes, max(first, want) * unit_bytes
+        assert np.all(d[:lo] == 0xA5), (unit_bytes, first, count)
+        assert np.array_equal(d[lo:hi], s_[lo:hi]), (unit_bytes, first, count)
+        assert np.all(d[hi:] == 0xA5), (unit_bytes, first, count)
+        assert int(out[0]) == want
+
+
+def test_snapshot_beyond_the_known_count():
+    """A snapshot whose band outgrows the host-known bound (4 tiles read back,
+    then 300 listed: a DMA copy of 4 + 0 + 64 tiles and the counted copy of
+    the other 232) and one that shrinks (8 tiles) equal the oracle's gather."""
+    dims, tile = (64, 64, 64), (8, 8, 8)
+    rng = np.random.default_rng(11)
+    phi = rng.standard_normal(dims[::-1]).astype(np.float32)
+    p = torch.from_numpy(phi).to(dev())
+    bg = BandGrid(dims, tile, "f32")
+    snaps = Snapshots(bg)
+    for n in (4, 300, 8):
+        tiles = np.sort(rng.choice(512, size=n, replace=False)).astype(np.int32)
+        bg.tiles[:n] = torch.from_numpy(tiles).to(dev())
+        bg.ntiles.fill_(n)
+        ids, vals = snaps.take(p).wait(copy=True)
+        assert ids.tolist() == tiles.tolist(), n
+        assert vals.tobytes() == oracle.gather_tiles(phi, tiles, tile).tobytes(), n
+    snaps.close()
+
+
 def test_snapshot_buffers_full_is_an_error():
     bg = BandGrid((32, 32, 32), (8, 8, 8), "f32")
     bg.tiles[:4] = torch.arange(4, dtype=torch.int32, device=dev())
