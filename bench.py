@@ -73,6 +73,8 @@ def parse():
                          "timed region; dense runs the driver on the x-fastest fields")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="CPU work budget of the oracle baseline (0 disables it)")
+    ap.add_argument("--snapshot-copy-blocks", type=int, default=0,
+                    help="workgroups of each snapshot's counted copy (0: the library's default)")
     ap.add_argument("--snapshot-every", type=int, default=0,
                     help="spheres512 only: time the windows as separate driver calls with an "
                          "asynchronous band snapshot (gather + copy to pinned host memory on a "
@@ -506,12 +508,16 @@ def _snapshot_run(args, torch, ls, W, BandGrid, dev):
     F = torch.from_numpy(wl.F).to(dev)
     phi = phi0.clone()
     gamma = float(np.float32(wl.gamma))
-    snaps = Snapshots(bg)
+    # the band count of phi0 (read once, untimed) as the first host-known count
+    bg.build(phi0, gamma)
+    snaps = Snapshots(bg, copy_blocks=args.snapshot_copy_blocks,
+                      expected=int(bg.ntiles[:1].item()))
     tile_steps = torch.zeros(1, dtype=torch.int64, device=dev)
     k = args.snapshot_every
 
-    def windows(with_snaps, count):
+    def windows(with_snaps, count, ev):
         got, pending = 0, []
+        ev[0].record()
         for w in range(count):
             bg.run(phi, F, wl.dx, wl.dt, gamma, wl.window, wl.window, tile_steps=tile_steps)
             if with_snaps and (w + 1) % k == 0:
@@ -519,6 +525,7 @@ def _snapshot_run(args, torch, ls, W, BandGrid, dev):
                 if len(pending) == 2:
                     pending.pop(0).wait()
                     got += 1
+        ev[1].record()  # the compute stream's work done (the last copy may still run)
         for p_ in pending:
             p_.wait()
             got += 1
@@ -533,16 +540,18 @@ def _snapshot_run(args, torch, ls, W, BandGrid, dev):
         torch.cuda.synchronize()
         if i == 1:
             ls.ls_stats_enable(True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         t0 = time.perf_counter()
-        taken = windows(with_snaps, args.steps)
+        taken = windows(with_snaps, args.steps, ev)
         torch.cuda.synchronize()
-        times[with_snaps] = (time.perf_counter() - t0, taken, int(tile_steps.item()))
+        times[with_snaps] = (time.perf_counter() - t0, taken, int(tile_steps.item()),
+                             ev[0].elapsed_time(ev[1]) / 1e3)
         if i == 1:
             ls.ls_stats_enable(False)
     g_launches, g_timed, g_ms = ls.ls_stats_read(ls.LS_KERNEL_GATHER)
     snaps.close()  # copies done, pinned buffers and the copy stream released before exit
-    t_plain, _, ts = times[False]
-    t_snap, taken, _ = times[True]
+    t_plain, _, ts, c_plain = times[False]
+    t_snap, taken, _, c_snap = times[True]
     updates = ts * int(np.prod(wl.tile))
     band_pts = updates / (args.steps * wl.window)
     return {
@@ -551,13 +560,17 @@ def _snapshot_run(args, torch, ls, W, BandGrid, dev):
         "ms_per_step": t_snap / args.steps * 1e3,
         "snapshots": taken,
         "overhead_frac": (t_snap - t_plain) / t_plain,
+        # the compute stream alone (events around the windows): the overhead
+        # without the drain of the last snapshot's copy
+        "compute_overhead_frac": (c_snap - c_plain) / c_plain,
         "gather_avg_us": g_ms * 1e3 / max(g_timed, 1),
         "gather_bytes_per_launch": 8 * band_pts,  # phi read + snapshot write, FP32
         "snapshot_mb": 4 * band_pts / 1e6,
         "config": {"workload": wl.name + f"_snapshot_every_{k}", "grid": [n, n, n],
                    "tile": list(wl.tile), "band_halfwidth_dx": 6,
                    "steps_per_window": wl.window, "upwind_steps": args.steps * wl.window,
-                   "storage": "f32", "parallelism": "single GPU"},
+                   "storage": "f32", "snapshot_copy_blocks": args.snapshot_copy_blocks,
+                   "parallelism": "single GPU"},
     }
 
 
@@ -633,6 +646,7 @@ def main():
                 "without_snapshots_value": round(r["plain_value"], 3),
                 "snapshots": r["snapshots"],
                 "snapshot_overhead_frac": round(r["overhead_frac"], 4),
+                "snapshot_compute_overhead_frac": round(r["compute_overhead_frac"], 4),
                 "snapshot_mb": round(r["snapshot_mb"], 2),
                 "roofline": {"bound": "hbm", "kernel": "ls::band_gather_kernel (f32 quads)",
                              "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -288,8 +288,8 @@ __global__ __launch_bounds__(kBlock) void closure_conv_kernel(
 // The three layers advance together plane by plane in z, each wave keeping
 // one layer's weights in registers: wave 0 computes layer-1 plane s in step
 // s, waves 1-2 layer-2 plane s-3 (from layer-1 planes s-3..s-1), wave 3
-// output plane s-6 (from layer-2 planes s-6..s-4, with phi and the plain step
-// of its points loaded one step ahead), one barrier per step.
+// output plane s-6 (from layer-2 planes s-6..s-4), one barrier per step; the
+// gate, the limiter and the fallback test then run on the whole tile at once.
 // Layer-1 and layer-2 activations live in rings of four z-planes, so a block
 // holds 52 KB of LDS and three blocks share a CU.  The arithmetic of every
 // point (operands, chunk order, rounding) is that of the layer-by-layer
@@ -347,7 +347,7 @@ __device__ inline f32x4 ring_conv16(const bf16x8 (&wa)[14], const unsigned char 
     return acc;
 }
 
-__global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
+__global__ __launch_bounds__(kFusedBlock) __attribute__((amdgpu_waves_per_eu(3))) void closure_fused_kernel(
     ConvGeo g, const int32_t *__restrict__ tiles, const int32_t *__restrict__ ntiles_dev,
     int ntiles_cap, In4 feat, const __bf16 *__restrict__ wp0, const __bf16 *__restrict__ wp1,
     const __bf16 *__restrict__ wp2, const float *__restrict__ params, float *__restrict__ rout,
@@ -356,7 +356,6 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
     __bf16 *in = reinterpret_cast<__bf16 *>(fsm);
     __bf16 *a0 = in + kFusedIn;             // layer-1 ring
     __bf16 *a1 = a0 + kRing * kSlot1;       // layer-2 ring
-    __shared__ int bad_s;
     const int lane = threadIdx.x & 63;
     // wave-uniform role: 0 layer 1, 1-2 layer 2, 3 layer 3
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -408,7 +407,6 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
                 }
             }
         }
-        if (threadIdx.x == 0) bad_s = 0;
         __syncthreads();
         // the role's weights (A operands, from L2 after the first tile) and
         // per-chunk LDS offsets; loaded after the features' barrier, so that
@@ -460,44 +458,61 @@ __global__ __launch_bounds__(kFusedBlock) void closure_fused_kernel(
             b2 = params[kB2];
         }
 
-        float cph[4] = {0.f, 0.f, 0.f, 0.f}, cpl[4] = {0.f, 0.f, 0.f, 0.f};
         for (int s = 0; s < kFusedSteps; ++s) {
             if (wave < kL1Waves) {
                 if (s < kF1) {
                     // layer-1 plane s (z offset s - 2): 144 points, 9 groups
                     const int lz = s;
                     __bf16 *dst = a0 + (s % kRing) * kSlot1 + hi * kPl1 * 8 + 4 * (kq & 1);
+                    // three groups at a time, as independent chains: their 24
+                    // operand reads, then their 12 products, then the three
+                    // epilogues (one group's chain alone is latency-bound)
+                    constexpr int NG = 3;
+                    static_assert((kPl1 / 16) % NG == 0, "layer-1 groups per pass");
 #pragma unroll 1
-                    for (int grp = wave; grp < kPl1 / 16; grp += kL1Waves) {
-                        const int pt = grp * 16 + j;
-                        const int lx = pt % kF1, ly = pt / kF1;
-                        const unsigned char *src = reinterpret_cast<const unsigned char *>(in) +
-                                                   ((lz * kF0 + ly) * kF0 + lx) * 8;
-                        // all eight operand loads first, then the four products
-                        uint2 v[8];
+                    for (int g0 = 0; g0 < kPl1 / 16; g0 += NG) {
+                        uint2 v[NG][8];
 #pragma unroll
-                        for (int k = 0; k < 8; ++k)
-                            v[k] = *reinterpret_cast<const uint2 *>(src + off[k]);
-                        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                        for (int u = 0; u < NG; ++u) {
+                            const int pt = (g0 + u) * 16 + j;
+                            const int lx = pt % kF1, ly = pt / kF1;
+                            const unsigned char *src = reinterpret_cast<const unsigned char *>(in) +
+                                                       ((lz * kF0 + ly) * kF0 + lx) * 8;
 #pragma unroll
-                        for (int c = 0; c < 4; ++c) {
-                            const bf16x8 b = __builtin_bit_cast(
-                                bf16x8, make_uint4(v[2 * c].x, v[2 * c].y, v[2 * c + 1].x,
-                                                   v[2 * c + 1].y));
-                            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[c], b, acc, 0, 0, 0);
+                            for (int k = 0; k < 8; ++k)
+                                v[u][k] = *reinterpret_cast<const uint2 *>(src + off[k]);
                         }
-                        __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);  // LDS reads
-                        __builtin_amdgcn_sched_group_barrier(0x8, 4, 0);    // products
-                        const int gx = x0 + lx - 2, gy = y0 + ly - 2, gz = z0 + lz - 2;
-                        const bool inside = gx >= 0 && gy >= 0 && gz >= 0 && gx < g.nx &&
-                                            gy < g.ny && gz < g.nz;
-                        __bf16 ab[4];
+                        f32x4 acc[NG];
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const float a = silu_f(acc[i] + bb[i]);  // finite: no branch
-                            ab[i] = to_bf16(inside ? a : 0.f);
+                        for (int u = 0; u < NG; ++u) {
+                            acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) {
+                                const bf16x8 b = __builtin_bit_cast(
+                                    bf16x8, make_uint4(v[u][2 * c].x, v[u][2 * c].y,
+                                                       v[u][2 * c + 1].x, v[u][2 * c + 1].y));
+                                acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[c], b, acc[u],
+                                                                                 0, 0, 0);
+                            }
                         }
-                        *reinterpret_cast<uint2 *>(dst + pt * 8) = *reinterpret_cast<uint2 *>(ab);
+                        __builtin_amdgcn_sched_group_barrier(0x100, 8 * NG, 0);  // LDS reads
+                        __builtin_amdgcn_sched_group_barrier(0x8, 4 * NG, 0);    // products
+#pragma unroll
+                        for (int u = 0; u < NG; ++u) {
+                            const int pt = (g0 + u) * 16 + j;
+                            const int lx = pt % kF1, ly = pt / kF1;
+                            const int gx = x0 + lx - 2, gy = y0 + ly - 2, gz = z0 + lz - 2;
+                            const bool inside = gx >= 0 && gy >= 0 && gz >= 0 && gx < g.nx &&
+                                                gy < g.ny && gz < g.nz;
+                            __bf16 ab[4];
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                const float av = silu_f(acc[u][i] + bb[i]);  // finite: no branch
+                                ab[i] = to_bf16(inside ? av : 0.f);
+                            }
+                            *reinterpret_cast<uint2 *>(dst + pt * 8) =
+                                *reinterpret_cast<uint2 *>(ab);
+                        }
                     }
                 }
             } else if (wave < kL1Waves + kL2Waves) {
@@ -534,22 +549,12 @@ __bf16 *dst = a1 + (b % kRing) * kSlot2 + hi * kPl2 * 8 + 4 * (kq & 1);
                 }
             } else {
                 const int lz = s - 6;
-                // phi and the plain step of plane lz + 1 (gate and limiter),
-                // issued now and used in the next step
-                float nph[4] = {0.f, 0.f, 0.f, 0.f}, npl[4] = {0.f, 0.f, 0.f, 0.f};
-                if (kq == 0 && lz + 1 >= 0 && lz + 1 < kT) {
-#pragma unroll
-                    for (int grp = 0; grp < 4; ++grp) {
-                        const int pt = grp * 16 + j;
-                        const int64_t gpt = (static_cast<int64_t>(z0 + lz + 1) * g.ny +
-                                             (y0 + (pt >> 3))) * g.nx + (x0 + (pt & 7));
-                        nph[grp] = feat.phi[gpt];
-                        npl[grp] = feat.plain[gpt];
-                    }
-                }
                 if (lz >= 0 && lz < kT) {
-                    // output plane lz from layer-2 planes lz..lz+2: r, the gated
-                    // correction and the fallback test on 64 points, 4 groups
+                    // output plane lz from layer-2 planes lz..lz+2: r on 64
+                    // points, 4 groups, into rout and into LDS for the pass
+                    // below, at the start of the feature array: feature planes
+                    // below s are no longer read (layer 1 reads planes s..s+2),
+                    // and plane lz's 256 bytes end below (s - 5) * 256 <= s * 1568
                     // ring slots in bytes
                     const int sb0 = (lz % kRing) * kSlot2 * 2,
                               sb1 = ((lz + 1) % kRing) * kSlot2 * 2,
@@ -568,47 +573,45 @@ __bf16 *dst = a1 + (b % kRing) * kSlot2 + hi * kPl2 * 8 + 4 * (kq & 1);
                         if (kq == 0) {
                             const int64_t gpt = (static_cast<int64_t>(z0 + lz) * g.ny +
                                                  (y0 + ly)) * g.nx + (x0 + lx);
-                            const float ph = cph[0];
-                            float r = acc[0] + b2;
+                            const float r = acc[0] + b2;
                             if (rout) rout[gpt] = r;
-                            r *= cutoff_f(ph, feat.inv_gamma);
-                            if (!(fabsf(r) <= 0.5f)) atomicOr(&bad_s, 1);  // NaN fails too
-                            // limiter: the correction changes the plain increment
-                            // by at most half of it, so it never reverses or
-                            // stalls the plain step
-                            const float lim = kCorrLimit * fabsf(cpl[0] - ph);
-                            if (corr) corr[gpt] = fminf(fmaxf(dx * r, -lim), lim);
-                        }
-                        // the next group's values to the front (static indices)
-#pragma unroll
-                        for (int i = 0; i < 3; ++i) {
-                            cph[i] = cph[i + 1];
-                            cpl[i] = cpl[i + 1];
+                            reinterpret_cast<float *>(fsm)[lz * 64 + pt] = r;
                         }
                     }
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    cph[i] = nph[i];
-                    cpl[i] = npl[i];
                 }
             }
             __syncthreads();
         }
-        // a tile that fails the test falls back to the plain step: its
-        // corrections (added to the plain step by a later kernel, since
-        // other blocks still read the plain step around their tiles) are zero
-        if (bad_s != 0) {
-            if (corr) {
-                for (int pt = threadIdx.x; pt < kT * kT * kT; pt += kFusedBlock) {
-                    const int64_t gpt = (static_cast<int64_t>(z0 + (pt >> 6)) * g.ny +
-                                         (y0 + ((pt >> 3) & 7))) * g.nx + (x0 + (pt & 7));
-                    corr[gpt] = 0.f;
-                }
-                if (threadIdx.x == 0 && fallbacks) atomicAdd(fallbacks, 1);
+        if (corr) {
+            // the gated, limited correction of the tile and its fallback test,
+            // two points per thread: a tile that fails the test falls back to
+            // the plain step, its corrections zero.  (They are added to the
+            // plain step by a later kernel, since other blocks still read the
+            // plain step around their tiles.)
+            constexpr int NPT = kT * kT * kT / kFusedBlock;
+            float cv[NPT];
+            int64_t gp[NPT];
+            bool bad = false;
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                const int pt = threadIdx.x + k * kFusedBlock;
+                gp[k] = (static_cast<int64_t>(z0 + (pt >> 6)) * g.ny + (y0 + ((pt >> 3) & 7))) *
+                            g.nx + (x0 + (pt & 7));
+                const float ph = feat.phi[gp[k]];
+                const float r = reinterpret_cast<const float *>(fsm)[pt] *
+                                cutoff_f(ph, feat.inv_gamma);
+                if (!(fabsf(r) <= 0.5f)) bad = true;  // NaN fails too
+                // limiter: the correction changes the plain increment by at
+                // most half of it, so it never reverses or stalls the plain step
+                const float lim = kCorrLimit * fabsf(feat.plain[gp[k]] - ph);
+                cv[k] = fminf(fmaxf(dx * r, -lim), lim);
             }
+            const bool fail = __syncthreads_or(bad);
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) corr[gp[k]] = fail ? 0.f : cv[k];
+            if (fail && threadIdx.x == 0 && fallbacks) atomicAdd(fallbacks, 1);
         }
-        __syncthreads();  // LDS and bad_s free for the next tile
+        __syncthreads();  // LDS free for the next tile
     }
 }
 
