@@ -94,13 +94,18 @@ def parse():
     return args
 
 
-STEP_KERNEL_SOURCES = ("ls_internal.h", "ls_stencil.h", "ls_step.hip", "ls_batch.hip",
-                       "ls_brick.hip")
+# the sources each kind of step kernel is compiled from (its counter
+# summary in profiles/traffic.json is stamped with their digest)
+BRICK_KERNEL_SOURCES = ("ls_internal.h", "ls_stencil.h", "ls_brick.hip")
+DENSE_KERNEL_SOURCES = ("ls_internal.h", "ls_stencil.h", "ls_step.hip")
+BATCH_KERNEL_SOURCES = ("ls_internal.h", "ls_stencil.h", "ls_step.hip", "ls_batch.hip")
+STEP_KERNEL_SOURCES = BRICK_KERNEL_SOURCES
 GATHER_KERNEL_SOURCES = ("ls_internal.h", "ls_snapshot.hip")
 
 
 def kernel_source_digest(sources=None):
-    """Digest of the sources a kernel is compiled from (default: the band step)."""
+    """Digest of the sources a kernel is compiled from (default: the tile-major
+    band step)."""
     here = os.path.dirname(os.path.abspath(__file__))
     csrc = os.path.join(here, "paper_1612_04040_amd", "csrc")
     h = hashlib.sha256()
@@ -322,6 +327,7 @@ def _single_grid(args, torch, ls, W, BandGrid, dev):
     fields = {
         "elapsed": t1 - t0,
         "traffic_kind": traffic_kind,
+        "digest_sources": BRICK_KERNEL_SOURCES if bricks else DENSE_KERNEL_SOURCES,
         "updates": updates,
         "upd_ms": upd_ms,
         "launches": launches,
@@ -414,6 +420,7 @@ def _batch(args, torch, ls, W, dev):
     fields = {
         "elapsed": t1 - t0,
         "traffic_kind": "upwind",
+        "digest_sources": BATCH_KERNEL_SOURCES,
         "updates": updates,
         "upd_ms": upd_ms,
         "launches": launches,
@@ -713,7 +720,7 @@ def main():
     pts_per_launch = f.get("pts_per_launch", f["updates"] / max(f["launches"], 1))
     bytes_per_launch = f.get("bytes_per_point", BYTES_PER_POINT[prec]) * pts_per_launch
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    digest = kernel_source_digest()
+    digest = kernel_source_digest(f["digest_sources"])
     traffic = measured_traffic(f.get("traffic_kind", "upwind"), f["config"]["workload"], digest)
 
     ceiling = copy_ceiling(torch, ls, dev)

@@ -125,8 +125,15 @@ __global__ __launch_bounds__(kBlock) void brick_flag_kernel(
 // from orig (its values frozen for the call), a face on the domain boundary
 // is the tile's own boundary row (zero-gradient boundary).
 
+// Box row pitch: the 8 lanes that share a z (y = 0..7) read 16-byte pieces of
+// their rows SX floats apart; with SX = 4 mod 8 those pieces fall in 8
+// distinct groups of 4 of the 32 LDS banks (SX = 40, a multiple of 8, put two
+// lanes in each group: 2-way conflicts on every row read)
+constexpr int kBrickPitch = kBrickRun * 8 + 12;  // 44 floats
+static_assert(kBrickPitch % 8 == 4, "row pitch 4 mod 8");
+
 struct BrickBox {
-    static constexpr int PAD = 4, SX = kBrickRun * 8 + 2 * PAD, SXY = SX * 10;
+    static constexpr int PAD = 4, SX = kBrickPitch, SXY = SX * 10;
     static constexpr size_t lds = sizeof(float) * SXY * 10;
 };
 
@@ -288,12 +295,14 @@ __global__ __launch_bounds__(kBlock) void brick_step_kernel(StepGeom g, StepArgs
 // on the same values, so the result is the same, bit for bit; the run's own
 // data is read and written once per two steps.
 struct Brick2Box {
-    static constexpr int PAD = 4, SX = kBrickRun * 8 + 2 * PAD, SXY = SX * 12;
+    static constexpr int PAD = 4, SX = kBrickPitch, SXY = SX * 12;
     static constexpr size_t lds = sizeof(float) * SXY * 12;
 };
+static_assert(Brick2Box::PAD + kBrickRun * 8 + 2 <= Brick2Box::SX, "box row holds x in [-2, 8R+1]");
 
 template <class S, int MODE>
-__global__ __launch_bounds__(kBlock) void brick_step2_kernel(StepGeom g, StepArgs<S, float> a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void brick_step2_kernel(
+    StepGeom g, StepArgs<S, float> a) {
     constexpr int PAD = Brick2Box::PAD, SX = Brick2Box::SX, SXY = Brick2Box::SXY;
     extern __shared__ __align__(16) unsigned char smem[];
     float *box = reinterpret_cast<float *>(smem);
@@ -335,6 +344,41 @@ __global__ __launch_bounds__(kBlock) void brick_step2_kernel(StepGeom g, StepArg
             upwind_point<float, false>(c, xm, xp, ym, yp, zm, zp, s, a.dx, a.dt, a.dtdx), s,
             a.dt, a.cut_gamma);
         return s == 0.f ? c : v;  // zero speed: the stored value unchanged
+    };
+    // point()'s arithmetic on the 8 points of a box row from o (16-byte
+    // aligned), every operand read as an aligned 16-byte piece (single floats
+    // at the row's ends met 4-way bank conflicts); emit(e, speed, update,
+    // centre) receives each point
+    auto row8 = [&](int o, const float (&f8)[8], auto &&emit) {
+        float c[10];
+        {
+            const brick_f4 c0 = *reinterpret_cast<const brick_f4 *>(box + o);
+            const brick_f4 c1 = *reinterpret_cast<const brick_f4 *>(box + o + 4);
+            c[0] = (*reinterpret_cast<const brick_f4 *>(box + o - 4))[3];
+            c[9] = (*reinterpret_cast<const brick_f4 *>(box + o + 8))[0];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) c[1 + e] = c0[e], c[5 + e] = c1[e];
+        }
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            const int oh = o + 4 * hh;
+            const brick_f4 ym = *reinterpret_cast<const brick_f4 *>(box + oh - SX);
+            const brick_f4 yp = *reinterpret_cast<const brick_f4 *>(box + oh + SX);
+            const brick_f4 zm = *reinterpret_cast<const brick_f4 *>(box + oh - SXY);
+            const brick_f4 zp = *reinterpret_cast<const brick_f4 *>(box + oh + SXY);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = 4 * hh + q;
+                const float cc = c[e + 1];
+                const float sv = mode_speed<MODE, float, false>(f8[e], cc, c[e], c[e + 2], ym[q],
+                                                                yp[q], zm[q], zp[q], a);
+                const float uv = mode_finish<MODE, float, false>(
+                    upwind_point<float, false>(cc, c[e], c[e + 2], ym[q], yp[q], zm[q], zp[q], sv,
+                                               a.dx, a.dt, a.dtdx),
+                    sv, a.dt, a.cut_gamma);
+                emit(e, sv, uv, cc);
+            }
+        }
     };
 
     for (int w = w0; w < w1; ++w) {
@@ -485,8 +529,9 @@ __global__ __launch_bounds__(kBlock) void brick_step2_kernel(StepGeom g, StepArg
         float s_own[8], s_ring[4], s_x = 0.f;
         if (own_ok) {
             const float f8[8] = {fa[0], fa[1], fa[2], fa[3], fb[0], fb[1], fb[2], fb[3]};
-#pragma unroll
-            for (int e = 0; e < 8; ++e) s_own[e] = kept(point(o_own + e, f8[e]));
+            row8(o_own, f8, [&](int e, float sv, float uv, float cc) {
+                s_own[e] = kept(sv == 0.f ? cc : uv);
+            });
         }
         const int o_ring = bx(r_x, r_y, r_z);
         if (r_upd) {
@@ -522,22 +567,15 @@ __global__ __launch_bounds__(kBlock) void brick_step2_kernel(StepGeom g, StepArg
         if (own_ok) {
             const float f8[8] = {fa[0], fa[1], fa[2], fa[3], fb[0], fb[1], fb[2], fb[3]};
             BrickRow<S> out;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int o = o_own + e;
-                const float c = box[o], xm = box[o - 1], xp = box[o + 1], ym = box[o - SX],
-                            yp = box[o + SX], zm = box[o - SXY], zp = box[o + SXY];
-                const float sp = mode_speed<MODE, float, false>(f8[e], c, xm, xp, ym, yp, zm, zp, a);
-                const float v = mode_finish<MODE, float, false>(
-                    upwind_point<float, false>(c, xm, xp, ym, yp, zm, zp, sp, a.dx, a.dt, a.dtdx),
-                    sp, a.dt, a.cut_gamma);
+            row8(o_own, f8, [&](int e, float sv, float uv, float cc) {
                 if constexpr (std::is_same<S, float>::value)
-                    out.set(e, sp == 0.f ? c : v);
+                    out.set(e, sv == 0.f ? cc : uv);
                 else
-                    out.set(e, sp == 0.f ? (f8[e] == 0.f && MODE < kReinit ? own.raw(e)
-                                                                          : Codec<S>::store(c, sc))
-                                         : Codec<S>::store(v, sc));
-            }
+                    out.set(e, sv == 0.f ? (f8[e] == 0.f && MODE < kReinit
+                                                ? own.raw(e)
+                                                : Codec<S>::store(cc, sc))
+                                         : Codec<S>::store(uv, sc));
+            });
             out.store(a.nxt + obase);
         }
         __syncthreads();  // box free for the next item

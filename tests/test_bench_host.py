@@ -31,11 +31,14 @@ def test_default_steps_cover_the_whole_run(workload, steps, monkeypatch):
 def test_traffic_lookup_is_keyed_by_the_source_digest():
     step = bench.kernel_source_digest()
     gather = bench.kernel_source_digest(bench.GATHER_KERNEL_SOURCES)
-    assert step != gather and len(step) == 16
+    batch = bench.kernel_source_digest(bench.BATCH_KERNEL_SOURCES)
+    dense = bench.kernel_source_digest(bench.DENSE_KERNEL_SOURCES)
+    assert len({step, gather, batch, dense}) == 4 and len(step) == 16
     with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
         rec = json.load(fh)
     for key, v in rec.items():
-        want = gather if key.startswith("gather/") else step
+        want = (gather if key.startswith("gather/") else batch if "batch" in key else
+                step if key.startswith("brick") else dense)
         kernel, workload = key.split("/", 1)
         got = bench.measured_traffic(kernel, workload, want)
         # an entry taken on other sources reads as unmeasured, never as stale bytes
