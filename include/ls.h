@@ -504,8 +504,9 @@ int ls_set_tuning(const ls_tuning *t);
 int ls_get_tuning(ls_tuning *t);
 
 /* Tile-shape autotuner (native): for each size in sizes[0..n) (cubic grids
- * of that many points per axis), the tile shape with the shortest time per
- * window of the FP32 batched band driver, measured once per size bucket of 32
+ * of that many points per axis), among the tile shapes whose time per window
+ * of the FP32 batched band driver is within 3 % of the shortest, the one with
+ * the fewest halo points per tile point, measured once per size bucket of 32
  * points on a batch of copies of a synthetic n^3 ellipsoid (n = bucket*32 +
  * 16; about 2^25 points in all, at most 512 copies) over the shapes the
  * batched step is compiled for: 8x8x8, 16x4x4, 32x4x4, 16x8x8, 4x4x4.  out[i]

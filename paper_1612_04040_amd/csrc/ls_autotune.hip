@@ -25,6 +25,7 @@ namespace ls {
 constexpr int kTuneBucket = 32;
 constexpr int kTuneShapes[][3] = {{8, 8, 8}, {16, 4, 4}, {32, 4, 4}, {16, 8, 8}, {4, 4, 4}};
 constexpr int64_t kTunePoints = int64_t(1) << 25;
+constexpr float kTuneNoise = 1.03f;  // times within 3 % of the fastest count as ties
 constexpr int kTuneMaxCopies = 512;
 constexpr int64_t kTuneAlign = 64;     // copy offsets in elements (256 bytes)
 constexpr int kTuneRowAlign = 32;      // row pitch granule in elements (128 bytes)
@@ -207,12 +208,28 @@ int ls_autotune(const int32_t *sizes, int n, int precision, const char *cache_pa
         auto it = cache.find(key);
         if (it == cache.end()) {
             const int rep = bucket * ls::kTuneBucket + ls::kTuneBucket / 2;
-            ls::TuneEntry best{{8, 8, 8}, INFINITY};
-            for (const auto &t : ls::kTuneShapes) {
-                float ms = 0.f;
-                const int rc = ls::time_shape(rep, t, &ms);
+            constexpr int kShapes = sizeof(ls::kTuneShapes) / sizeof(ls::kTuneShapes[0]);
+            float ms[kShapes];
+            float fastest = INFINITY;
+            for (int k = 0; k < kShapes; ++k) {
+                const int rc = ls::time_shape(rep, ls::kTuneShapes[k], &ms[k]);
                 if (rc != LS_OK) return rc;
-                if (ms < best.ms) best = ls::TuneEntry{{t[0], t[1], t[2]}, ms};
+                fastest = std::min(fastest, ms[k]);
+            }
+            // among the shapes within the timing noise of the fastest, the one
+            // that reads the fewest halo points per updated point (the bytes
+            // beyond the algorithmic ones)
+            ls::TuneEntry best{{8, 8, 8}, INFINITY};
+            double best_halo = INFINITY;
+            for (int k = 0; k < kShapes; ++k) {
+                const int *t = ls::kTuneShapes[k];
+                if (!(ms[k] <= ls::kTuneNoise * fastest)) continue;
+                const double v = double(t[0]) * t[1] * t[2];
+                const double halo = (double(t[0] + 2) * (t[1] + 2) * (t[2] + 2) - v) / v;
+                if (halo < best_halo) {
+                    best_halo = halo;
+                    best = ls::TuneEntry{{t[0], t[1], t[2]}, ms[k]};
+                }
             }
             it = cache.emplace(key, best).first;
             changed = true;
