@@ -9,8 +9,9 @@
   scaled FP16, on grids whose tile rows are not a multiple of the 4-tile work
   item and with an odd step count per window (the copy-back); and it matches
   the oracle directly within the FP32 bound.
-* At full size (the 512^3 three-sphere workload, 200 steps) the brick driver
-  equals the x-fastest driver bit for bit.
+* At full size (the 512^3 three-sphere workload, 200 steps; the 1024^3 torus
+  in FP32, 200 steps, and in scaled FP16, 500 steps) the brick driver equals
+  the x-fastest driver bit for bit.
 """
 import numpy as np
 import pytest
@@ -168,6 +169,44 @@ def test_brick_driver_512_equals_driver():
     bg.to_bricks(Fd, Fb)
     acc_b = torch.zeros(1, dtype=torch.int64, device=dev())
     bg.run_bricks(pb, Fb, wl.dx, wl.dt, g32, 200, 10, tile_steps=acc_b)
+    bg.from_bricks(pb, p0)
+    assert host(p0).tobytes() == want.tobytes()
+    assert bg.band_list().numpy().tolist() == want_list
+    assert int(acc_b.item()) == int(acc_d.item())
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision,steps", [("f32", 200), ("f16s", 500)])
+def test_brick_driver_1024_torus_equals_driver(precision, steps):
+    """The 1024^3 torus workloads at full size, as the bench runs them (FP32:
+    200 steps, two steps per launch; scaled FP16: 500 steps, one step per
+    launch): the brick driver equals the x-fastest driver bit for bit, band
+    list and tile-step count included."""
+    n = 1024
+    wl = W.torus_grf(n, steps)
+    g32 = float(np.float32(wl.gamma))
+    scale = None
+    if precision == "f32":
+        p0 = to_dev(wl.phi)
+    else:
+        scale = float(np.float32(wl.scale))
+        p0 = torch.from_numpy(W.quantize_f16s(wl.phi, np.float32(scale))).to(dev())
+    wl.phi = None
+    Fd = to_dev(wl.F)
+    wl.F = None
+    bg = BandGrid((n,) * 3, wl.tile, precision)
+    pd = p0.clone()
+    acc_d = torch.zeros(1, dtype=torch.int64, device=dev())
+    bg.run(pd, Fd, wl.dx, wl.dt, g32, steps, wl.window, scale=scale, tile_steps=acc_d)
+    want = host(pd)
+    want_list = bg.band_list().numpy().tolist()
+    del pd
+    pb, Fb = torch.empty_like(p0), torch.empty_like(Fd)
+    bg.to_bricks(p0, pb)
+    bg.to_bricks(Fd, Fb)
+    del Fd
+    acc_b = torch.zeros(1, dtype=torch.int64, device=dev())
+    bg.run_bricks(pb, Fb, wl.dx, wl.dt, g32, steps, wl.window, scale=scale, tile_steps=acc_b)
     bg.from_bricks(pb, p0)
     assert host(p0).tobytes() == want.tobytes()
     assert bg.band_list().numpy().tolist() == want_list
