@@ -125,15 +125,20 @@ __global__ __launch_bounds__(kBlock) void brick_flag_kernel(
 // from orig (its values frozen for the call), a face on the domain boundary
 // is the tile's own boundary row (zero-gradient boundary).
 
-// Box row pitch: the 8 lanes that share a z (y = 0..7) read 16-byte pieces of
-// their rows SX floats apart; with SX = 4 mod 8 those pieces fall in 8
-// distinct groups of 4 of the 32 LDS banks (SX = 40, a multiple of 8, put two
-// lanes in each group: 2-way conflicts on every row read)
+// Box pitches against LDS bank conflicts (64 banks of 4 bytes; a 16-byte read
+// by 16 lanes at a time): lane (y, z) of a wave reads 16-byte pieces of its
+// row at y*SX + z*SXY.  With SX = 44 the pieces of y = 0..7 fall in 8 of the
+// 16 four-bank groups and, with SXY = 32 mod 64, those of z + 1 in the other
+// 8, so each 16-lane read is conflict-free (SX = 40 and SXY = 12 SX or 10 SX
+// put up to four pieces in one group).
 constexpr int kBrickPitch = kBrickRun * 8 + 12;  // 44 floats
 static_assert(kBrickPitch % 8 == 4, "row pitch 4 mod 8");
+constexpr int brick_plane_pitch(int rows) {  // smallest >= rows * SX that is 32 mod 64
+    return rows * kBrickPitch + ((32 - rows * kBrickPitch % 64) % 64 + 64) % 64;
+}
 
 struct BrickBox {
-    static constexpr int PAD = 4, SX = kBrickPitch, SXY = SX * 10;
+    static constexpr int PAD = 4, SX = kBrickPitch, SXY = brick_plane_pitch(10);
     static constexpr size_t lds = sizeof(float) * SXY * 10;
 };
 
@@ -295,10 +300,11 @@ __global__ __launch_bounds__(kBlock) void brick_step_kernel(StepGeom g, StepArgs
 // on the same values, so the result is the same, bit for bit; the run's own
 // data is read and written once per two steps.
 struct Brick2Box {
-    static constexpr int PAD = 4, SX = kBrickPitch, SXY = SX * 12;
+    static constexpr int PAD = 4, SX = kBrickPitch, SXY = brick_plane_pitch(12);
     static constexpr size_t lds = sizeof(float) * SXY * 12;
 };
 static_assert(Brick2Box::PAD + kBrickRun * 8 + 2 <= Brick2Box::SX, "box row holds x in [-2, 8R+1]");
+static_assert(BrickBox::SXY == 480 && Brick2Box::SXY == 544, "plane pitches 32 mod 64");
 
 template <class S, int MODE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void brick_step2_kernel(
