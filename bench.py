@@ -695,8 +695,10 @@ def main():
                 "judged_coarse_ms": round(ev["judged_coarse_ms"], 2),
                 "hausdorff_dx_fine": {k: round(ev[f"hausdorff_{k}_dx_fine"], 3) for k in (
                     "restricted_fine", "plain_coarse", "learned_coarse",
-                    "judged_topology_coarse", "judged_coarse")},
+                    "judged_topology_coarse", "judged_coarse", "judged_half_coarse")},
                 "judge_resets": ev.get("judged_resets"),
+                "judged_half_coarse_ms": round(ev["judged_half_coarse_ms"], 2),
+                "judge_half_resets": ev.get("judged_half_resets"),
                 "train_s": round(r["train_s"], 1),
                 "roofline": {"bound": "mfma", "kernel": "ls::closure_fused_kernel (bf16 MFMA "
                              "16x16x32, fp32 accumulation)",

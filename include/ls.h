@@ -650,7 +650,8 @@ int ls_adam_step(float *params, const float *grad, float *m, float *v, int64_t n
  * judge == 2 bounds the interface's position as well: a tile also takes the
  * shadow's values when the two fronts lie more than one grid spacing apart
  * there (a point next to either front, |phi| < dx or |shadow| < dx, where
- * |phi - shadow| > dx); judge == 1 is the topology judge alone.
+ * |phi - shadow| > dx); judge == 3 the same with half a grid spacing
+ * (|phi - shadow| > dx / 2 there); judge == 1 is the topology judge alone.
  * *resets_dev (int32, caller-zeroed; required when judging) accumulates the
  * number of tiles reset.  judge == 0: no shadow run (resets_dev may be NULL);
  * other values of judge: LS_ERR_ARG.

@@ -88,7 +88,8 @@ class ClosureGrid:
             stream=None):
         """Corrected narrow-band run, judged by a plain shadow run unless
         judge=False (0): True (1) judges the interface's topology per tile, 2
-        its position as well (the fronts within one grid spacing);
+        its position as well (the fronts within one grid spacing), 3 the same
+        within half a grid spacing;
         self.fallbacks and self.resets accumulate (zero them first)."""
         t, cap, n, ws, wsb = self._band()
         ls.ls_closure_run_f32(phi, F, self.g, dx, dt, gamma, fmax, params, nsteps, window, int(judge),

@@ -210,8 +210,10 @@ def evaluate(seed, n_fine, nsteps, params, device, reps=3):
     fields = {}
     # the product run is "judged" (the plain shadow judges the topology and the
     # position of the front per tile, judge mode 2); the topology judge alone
-    # (mode 1) and no judge are reported beside it
-    for name, judge in (("learned", 0), ("judged_topology", 1), ("judged", 2)):
+    # (mode 1), the position bound at half a grid spacing (mode 3) and no judge
+    # are reported beside it
+    for name, judge in (("learned", 0), ("judged_topology", 1), ("judged", 2),
+                        ("judged_half", 3)):
         def learned_run(s):
             ls.ls_copy_f32(phi_l, phi_c0, phi_l.numel(), s)
             ls.ls_copy_f32(cg.fallbacks, zero_i, 1, s)  # int32 zeros, same width
@@ -231,7 +233,8 @@ def evaluate(seed, n_fine, nsteps, params, device, reps=3):
     for name, field in (("restricted_fine", best), ("plain_coarse", plain),
                         ("learned_coarse", fields["learned"]),
                         ("judged_topology_coarse", fields["judged_topology"]),
-                        ("judged_coarse", fields["judged"])):
+                        ("judged_coarse", fields["judged"]),
+                        ("judged_half_coarse", fields["judged_half"])):
         up = metrics.upsample_trilinear(field, ratio)
         pc = metrics.zero_crossings(up, dxf)
         out[f"hausdorff_{name}_dx_fine"] = metrics.hausdorff(pc, pf) / dxf
@@ -241,7 +244,8 @@ def evaluate(seed, n_fine, nsteps, params, device, reps=3):
     pb = metrics.zero_crossings(best, case.dx_coarse)
     for name, field in (("plain_coarse", plain), ("learned_coarse", fields["learned"]),
                         ("judged_topology_coarse", fields["judged_topology"]),
-                        ("judged_coarse", fields["judged"])):
+                        ("judged_coarse", fields["judged"]),
+                        ("judged_half_coarse", fields["judged_half"])):
         pc = metrics.zero_crossings(field, case.dx_coarse)
         out[f"hausdorff_{name}_to_restricted_dx_fine"] = metrics.hausdorff(pc, pb) / dxf
     out["speedup_judged_vs_fine"] = out["fine_ms"] / out["judged_coarse_ms"]

@@ -1303,8 +1303,8 @@ int ls_closure_run_f32(float *phi, const float *F, const ls_grid *g, float dx, f
         ls::set_error("closure run: need nsteps >= 0 and window > 0");
         return LS_ERR_ARG;
     }
-    if (judge < 0 || judge > 2) {
-        ls::set_error("closure run: judge must be 0, 1 or 2 (got %d)", judge);
+    if (judge < 0 || judge > 3) {
+        ls::set_error("closure run: judge must be 0, 1, 2 or 3 (got %d)", judge);
         return LS_ERR_ARG;
     }
     if (capacity < G0.ntiles) {
@@ -1348,8 +1348,9 @@ int ls_closure_run_f32(float *phi, const float *F, const ls_grid *g, float dx, f
         }
         if (judge) {
             const unsigned jb = static_cast<unsigned>(std::min<int64_t>(c.G.ntiles, 4096));
-            // judge 2: the fronts within one grid spacing of each other as well
-            const float tau = judge == 2 ? 1.0f : 0.0f;
+            // judge 2 (3): the fronts within one (half a) grid spacing of each
+            // other as well
+            const float tau = judge == 2 ? 1.0f : (judge == 3 ? 0.5f : 0.0f);
             hipLaunchKernelGGL(ls::closure_judge_kernel, dim3(jb), dim3(512), 0, c.s, buf[cur],
                                static_cast<const float *>(shadow), c.G.nx, c.G.ny, c.G.ntx,
                                c.G.nty, static_cast<int>(c.G.ntiles), dx, tau, resets_dev);

@@ -440,7 +440,7 @@ def test_brick_errors():
 
 def test_closure_run_rejects_unknown_judge_modes():
     g = ls.grid((64, 64, 64))
-    for judge in (-1, 3):
+    for judge in (-1, 4):
         with pytest.raises(ls.LsError) as e:
             ls.ls_closure_run_f32(FAKE, FAKE, g, 0.01, 0.005, 0.06, 1.0, FAKE, 10, 10, judge, FAKE,
                                   ls.ls_grid_tiles(g), FAKE, FAKE, FAKE, FAKE * 256, 1 << 20,

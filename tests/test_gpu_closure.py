@@ -375,6 +375,52 @@ def test_judge_bounds_the_front_position():
     assert err <= 1e-3 * dx, err / dx
 
 
+def test_judge_half_spacing_bound():
+    """The plane front of the test above over a window of 4 steps: the
+    corrected front leads the shadow's by 0.8 dx (4 x 0.2 dx), within one
+    grid spacing and beyond half of one. Judge mode 2 keeps the corrected
+    run; mode 3 (fronts within dx / 2) resets the tiles along the front, and
+    matches the FP64 reference with the oracle's judge at tau = 1/2."""
+    n = 32
+    dx = 1.0 / n
+    dt = float(np.float32(0.5 * dx))
+    phi0 = W.plane((n, n, n), dx, (1.0, 0.0, 0.0), 8.5 * dx, dtype=np.float32)
+    F = np.full((n, n, n), 0.8, np.float32)
+    gamma = float(np.float32(6 * dx))
+    p = C.unflatten(C.init_params(np.random.default_rng(2)))
+    p["b2"][:] = -0.5
+    params = to_dev(C.flatten(p))
+    Fd = to_dev(F)
+    cg = C.ClosureGrid((n, n, n))
+    runs, resets = {}, {}
+    for judge in (2, 3):
+        pd = to_dev(phi0)
+        cg.fallbacks.zero_()
+        cg.resets.zero_()
+        cg.run(pd, Fd, dx, dt, gamma, 1.0, params, 4, 4, judge=judge)
+        runs[judge] = host(pd)
+        resets[judge] = int(host(cg.resets)[0])
+        assert int(host(cg.fallbacks)[0]) == 0
+    assert resets[2] == 0
+    assert resets[3] > 0
+    pr = {k: bf16(v.astype(np.float32)) for k, v in C.unflatten(C.flatten(p)).items()}
+    for k in ("b0", "b1", "b2"):
+        pr[k] = C.unflatten(C.flatten(p))[k].astype(np.float32).astype(np.float64)
+    g32 = np.float32(gamma)
+    shadow = oracle.run_band(phi0, F, dx, dt, g32, 4, window=4)
+    x = phi0.astype(np.float64)
+    band = oracle.band_tiles(x.astype(np.float32), TILE, g32, True)
+    active = oracle.band_tiles(x.astype(np.float32), TILE, g32, False)
+    for _ in range(4):
+        x, fb = CL.closure_step(pr, x, F, dx, dt, g32, np.float32(1.0), band, active)
+        assert fb == 0
+    assert np.max(np.abs(x - runs[2])) <= 1e-3 * dx
+    x, k = CL.judge(x, shadow, dx=dx, tau=0.5)
+    assert k == resets[3]
+    err = np.max(np.abs(runs[3].astype(np.float64) - x))
+    assert err <= 1e-3 * dx, err / dx
+
+
 @pytest.mark.timeout(600)
 def test_forward_full_size_sampled_tiles():
     """The network at the evaluation size (128^3 coarse grid of the closure
