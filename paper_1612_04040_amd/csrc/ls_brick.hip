@@ -702,7 +702,12 @@ static StepGeom brick_step_geom(const Geom &G) {
     return s;
 }
 
-constexpr int kBrickBlocksPerCu = 32;
+// workgroups per compute unit of the step launches: 32, and 64 on grids of
+// 2^21 tiles or more (1024^3), whose bands stream from HBM: there more blocks
+// in flight hide more of the memory latency (1024^3 FP32: 255 against 261 us
+// per launch; at 512^3, cache-resident, 64 was 2 % slower and 16 the same)
+constexpr int kBrickBlocksPerCu = 32, kBrickBlocksPerCuLarge = 64;
+constexpr int64_t kBrickLargeTiles = int64_t(1) << 21;
 
 // Two steps per launch in the brick driver (ls_tuning.temporal: 1 on, 2 off;
 // 0 auto: on for FP32, off for FP16s, whose two-step launch is VALU-heavier
@@ -718,7 +723,8 @@ static bool brick_two_step() {
 static int brick_grid(int64_t ntiles) {
     DeviceInfo di;
     if (device_info(&di) != LS_OK) return -1;
-    const int64_t g64 = std::min<int64_t>(int64_t(di.cus) * kBrickBlocksPerCu, ntiles + 7);
+    const int per_cu = ntiles >= kBrickLargeTiles ? kBrickBlocksPerCuLarge : kBrickBlocksPerCu;
+    const int64_t g64 = std::min<int64_t>(int64_t(di.cus) * per_cu, ntiles + 7);
     return static_cast<int>(std::max<int64_t>(8, g64 - g64 % 8));
 }
 
