@@ -25,6 +25,10 @@ int plan_run_tiles(const Geom &g);                               // ls_step.hip
 int fill_zero(uint8_t *p, int64_t bytes, hipStream_t stream);   // ls_band.hip
 
 constexpr int kMaxGroups = 16;
+// workgroups per CU of a group's step launch: more blocks in flight put more
+// of the halo rows neighbouring blocks read in L2 (on the 256-grid batch: 32
+// per CU 199.2 GLUPS, 64 206.8, 128 207.8)
+constexpr int kBatchBlocksPerCu = 64;
 
 // ---------------------------------------------------------------------------
 // host layout (deterministic: the same instance array gives the same layout)
@@ -574,7 +578,7 @@ static int batch_steps(const BatchLayout &L, float *phi, const float *F, float *
     args.orig = phi;
     args.dx = args.dt = args.dtdx = 0.f;
     args.scale = 1.f;
-    const int64_t G = std::max<int64_t>(8, (int64_t(di.cus) * 32) & ~int64_t(7));
+    const int64_t G = std::max<int64_t>(8, (int64_t(di.cus) * kBatchBlocksPerCu) & ~int64_t(7));
     // software pipelining is on only when asked for: measured slower on the
     // 256-grid batch (its predicated kernels need the registers)
     const bool pipe = pipeline_forced();
